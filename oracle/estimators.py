@@ -1,0 +1,149 @@
+"""FP64 estimators of the oracle (test infrastructure only).
+
+Each function is the plain formula from the paper, in double precision:
+  - sample-mean BPMF, Eq. 2, pooled over every (configuration, translation)
+    sample including the infinite (clash) ones;
+  - binding-site volume V_site of the standard-binding-free-energy section
+    (average box-valid region, counted in grid points times h^3);
+  - standard binding free energy, Eqs. 12-13, with the sign reading
+    -kT ln(V_site C0) (Omega / 8 pi^2 = V_site);
+  - importance-sampled and uniformly subsampled forms of Eq. 2 over
+    configurations, and the bootstrap over configurations used for the
+    convergence figure of the results section.
+Partials are rows (m, s, n_valid, n_finite, psi_min, argmin) with
+x = -beta Psi, m = max x and s = sum exp(x - m) over one configuration.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+R_KCAL = 1.987204259e-3
+C_STANDARD = 6.02214076e-4  # 1 mol/L in A^-3
+
+
+def kT(T: float) -> float:
+    return R_KCAL * T
+
+
+def log_z(partials: np.ndarray) -> np.ndarray:
+    """ln Z_c = m_c + ln s_c per configuration (-inf if nothing finite)."""
+    p = np.asarray(partials, dtype=np.float64)
+    out = np.full(p.shape[0], -np.inf)
+    ok = p[:, 3] > 0
+    out[ok] = p[ok, 0] + np.log(p[ok, 1])
+    return out
+
+
+def lse(x: np.ndarray) -> float:
+    """max-shifted log-sum-exp in FP64; -inf for an empty or all -inf set."""
+    x = np.asarray(x, dtype=np.float64)
+    if x.size == 0:
+        return -math.inf
+    m = np.max(x)
+    if m == -math.inf:
+        return -math.inf
+    return float(m + math.log(np.sum(np.exp(x - m))))
+
+
+def bpmf(partials: np.ndarray, T: float) -> float:
+    """Eq. 2 pooled over all configurations of one ligand and one snapshot:
+    B = -kT [ ln sum_c Z_c - ln sum_c n_c ];  +inf if nothing is finite."""
+    p = np.asarray(partials, dtype=np.float64)
+    n = float(np.sum(p[:, 2]))
+    lz = lse(log_z(p))
+    if lz == -math.inf or n <= 0:
+        return math.inf
+    return -kT(T) * (lz - math.log(n))
+
+
+def bpmf_naive(psi_all: np.ndarray, T: float) -> float:
+    """Eq. 2 literally: -kT ln (1/N) sum exp(-beta Psi) (no shift)."""
+    beta = 1.0 / kT(T)
+    psi_all = np.asarray(psi_all, dtype=np.float64)
+    return -kT(T) * math.log(np.mean(np.exp(-beta * psi_all)))
+
+
+def v_site(boxes: np.ndarray, n_rec: int, h: float) -> float:
+    """V_site = h^3 * mean over configurations of the number of box-valid
+    translations, prod_d (n_rec - box_d)."""
+    b = np.asarray(boxes, dtype=np.int64)
+    v = np.clip(n_rec - b, 0, None)
+    return float(h ** 3 * np.mean(np.prod(v, axis=1)))
+
+
+def dg_standard(B: np.ndarray, W: np.ndarray, vsite: float, T: float) -> float:
+    """Eq. 13 with the reading -kT ln(V_site C0):
+    dG = -kT ln sum_s W_s exp(-beta B_s) - kT ln(V_site C0)."""
+    B = np.asarray(B, dtype=np.float64)
+    W = np.asarray(W, dtype=np.float64)
+    W = W / np.sum(W)
+    beta = 1.0 / kT(T)
+    fin = np.isfinite(B) & (W > 0)
+    if not np.any(fin):
+        return math.inf
+    x = np.log(W[fin]) - beta * B[fin]
+    return -kT(T) * lse(x) - kT(T) * math.log(vsite * C_STANDARD)
+
+
+def bpmf_is(logz_cfg: np.ndarray, n_total: float, idx: np.ndarray, q: np.ndarray,
+            T: float) -> float:
+    """Importance-sampled Eq. 2 over configurations:
+    Z_hat = (1/K) sum_k Z_{c_k} / q_{c_k};  B_hat = -kT ln(Z_hat / n_total)."""
+    lz = np.asarray(logz_cfg, dtype=np.float64)[idx]
+    lq = np.log(np.asarray(q, dtype=np.float64)[idx])
+    K = len(idx)
+    val = lse(lz - lq) - math.log(K)
+    if val == -math.inf:
+        return math.inf
+    return -kT(T) * (val - math.log(n_total))
+
+
+def bpmf_uniform_subsample(logz_cfg, n_total, idx, T):
+    P = len(logz_cfg)
+    return bpmf_is(logz_cfg, n_total, idx, np.full(P, 1.0 / P), T)
+
+
+def bootstrap_sigma(partials: np.ndarray, T: float, n_draw: int, reps: int,
+                    rng: np.random.Generator) -> float:
+    """Standard deviation of Eq. 2 over `reps` bootstrap sets of n_draw
+    configurations drawn with replacement (all translations of a drawn
+    configuration move together)."""
+    p = np.asarray(partials, dtype=np.float64)
+    vals = []
+    for _ in range(reps):
+        sel = rng.integers(0, p.shape[0], n_draw)
+        vals.append(bpmf(p[sel], T))
+    v = np.asarray(vals)
+    v = v[np.isfinite(v)]
+    return float(np.std(v)) if v.size > 1 else math.inf
+
+
+def rmse(x, y) -> float:
+    """Eq. 14."""
+    x, y = np.asarray(x, float), np.asarray(y, float)
+    return float(np.sqrt(np.mean((x - y) ** 2)))
+
+
+def armse(x, y) -> float:
+    """Eq. 15."""
+    x, y = np.asarray(x, float), np.asarray(y, float)
+    return float(np.sqrt(np.mean((x - y - (x.mean() - y.mean())) ** 2)))
+
+
+def proposal(yhat: np.ndarray, alpha: float, tau: float) -> np.ndarray:
+    """Defensive mixture q = (1 - alpha) softmax(yhat / tau) + alpha / P."""
+    y = np.asarray(yhat, dtype=np.float64) / tau
+    y = y - np.max(y)
+    e = np.exp(y)
+    P = y.shape[0]
+    return (1.0 - alpha) * e / np.sum(e) + alpha / P
+
+
+def inverse_cdf_sample(q: np.ndarray, uniforms: np.ndarray) -> np.ndarray:
+    """Index k with cdf[k-1] <= u < cdf[k], cdf the running sum of q taken
+    left to right (FP64)."""
+    cdf = np.cumsum(np.asarray(q, dtype=np.float64))
+    u = np.asarray(uniforms, dtype=np.float64) * cdf[-1]
+    return np.minimum(np.searchsorted(cdf, u, side="right"), len(q) - 1)
