@@ -1,0 +1,208 @@
+/*
+ * fftdg — FFT translational scan for binding potentials of mean force
+ * (BPMF) and standard binding free energies on AMD Instinct MI355X (gfx950).
+ *
+ * Method: Nguyen, Zhou & Minh, "Using the Fast Fourier Transform in Binding
+ * Free Energy Calculations".  For every rigid ligand configuration (conformer
+ * x random rotation about its centroid), the ligand's electrostatic and
+ * Lennard-Jones weights (Eqs. 3-6) and its occupancy (Eq. 10) are spread onto
+ * grids, correlated with precomputed receptor grids through the FFT (Eqs.
+ * 8-9), giving the interaction energy at every grid translation; translations
+ * whose ligand box leaves the receptor grid are discarded and sterically
+ * clashing ones are infinite; the energies are exponentially averaged into
+ * the BPMF (Eq. 2) and over receptor snapshots into the standard binding
+ * free energy (Eqs. 12-13).
+ *
+ * Conventions (all calls):
+ *   - units: Angstrom, elementary charge, kcal/mol, Kelvin; sigma is the
+ *     r_min-form Lennard-Jones radius (the pair minimum -eps_ij sits at
+ *     r = sigma_ij, Eqs. 5-6);
+ *   - 3-D arrays are [z][y][x] with x fastest; grid point (x,y,z) sits at
+ *     origin + h*(x,y,z);
+ *   - "_dev" pointers are device memory on the context's device, "_host"
+ *     pointers are host memory; the caller owns every pointer it passes in;
+ *   - device work is ordered on the context's stream and is asynchronous
+ *     unless a call says it synchronizes;
+ *   - every call returns FFTDG_OK (0) or a negative status; on failure
+ *     fftdg_last_error() describes it; no call throws or aborts;
+ *   - one context must not be used by two host threads at once.
+ */
+#ifndef FFTDG_H
+#define FFTDG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FFTDG_VERSION 10000
+
+/* status codes */
+#define FFTDG_OK 0
+#define FFTDG_E_INVALID (-1) /* null pointer, bad size/offset, unsupported n_fft, non-finite input, T <= 0, ... */
+#define FFTDG_E_NOVALID (-2) /* a ligand has no box-valid translation in any configuration */
+#define FFTDG_E_NOMEM (-3)   /* device or host allocation failed, or a workspace limit was exceeded */
+#define FFTDG_E_DEVICE (-4)  /* any HIP runtime error, including "no device" */
+#define FFTDG_E_STATE (-5)   /* call out of order (e.g. scan before set_receptors) */
+
+/* precision of grids, FFTs and energies */
+#define FFTDG_F32 0
+#define FFTDG_F64 1
+
+/* clash handling (readings of the exclusion and occupancy rules of the
+ * FFT-based BPMF estimation section) */
+#define FFTDG_OCC 0 /* three energy grids zeroed inside 2^-1/6 sigma, plus an occupancy grid; clash -> +inf */
+#define FFTDG_CAP 1 /* three energy grids, LJ repulsion kept inside 2^-1/6 sigma and clamped; no clash test */
+
+typedef struct fftdg_ctx fftdg_ctx;
+
+/* Grid description (FFT-based BPMF estimation section).
+ *   n_rec  receptor grid edge in points (the ligand box must fit inside)
+ *   n_fft  FFT edge, n_fft >= n_rec; receptor grids are zero-padded to it.
+ *          Supported: 32, 64, 128 (FFTDG_F32); 32, 64 (FFTDG_F64).
+ *          In FFTDG_OCC mode choose n_fft >= n_rec + occupancy radius so
+ *          that the periodic wrap only meets padding.
+ *   h      grid spacing (A), origin position of point (0,0,0) (A)
+ *   ljr_cap  FFTDG_CAP only: LJ-repulsive grid values are clamped to it
+ *          (kcal/mol per unit ligand weight)
+ *   occ_f  FFTDG_OCC only: occupancy radius rho_i = occ_f 2^-1/6 sigma_i
+ *          for ligand and receptor atoms (the paper's literal rule is 1). */
+typedef struct {
+    int32_t n_rec;
+    int32_t n_fft;
+    double h;
+    double origin[3];
+    int32_t precision;
+    int32_t clash_mode;
+    double ljr_cap;
+    double occ_f;
+} fftdg_grid_desc;
+
+/* A batch of ligands and their rigid configurations (host memory).
+ *   ligand l owns atoms atom_off[l] .. atom_off[l+1]-1 (n_l atoms, <= 256),
+ *   conformers conf_off[l] .. conf_off[l+1]-1 and configurations
+ *   cfg_off[l] .. cfg_off[l+1]-1;
+ *   q, sigma, eps: per atom (e, A, kcal/mol);
+ *   conf_xyz: the conformers' coordinates, ligand by ligand, conformer by
+ *     conformer, atom by atom, [.][3] doubles (A);
+ *   cfg_conf[c]: conformer of configuration c, local to its ligand;
+ *   cfg_quat[c][4]: rotation (w,x,y,z) about the conformer's unweighted
+ *     centroid ("Ligand Sampling"); need not be normalised, must be non-zero;
+ *   cfg_select: NULL = scan every configuration; else scan only those with
+ *     cfg_select[c] != 0 (the others still count their translations in the
+ *     sample size, as importance sampling over configurations needs). */
+typedef struct {
+    int32_t n_lig;
+    const int32_t *atom_off;
+    const int32_t *conf_off;
+    const int32_t *cfg_off;
+    const double *q;
+    const double *sigma;
+    const double *eps;
+    const double *conf_xyz;
+    const int32_t *cfg_conf;
+    const double *cfg_quat;
+    const uint8_t *cfg_select;
+} fftdg_batch;
+
+/* Per-(snapshot, configuration) partial of the sample mean of Eq. 2, over
+ * the configuration's box-valid translations.  x = -Psi/kT;
+ *   m = max x over finite samples (-inf if none), s = sum exp(x - m),
+ *   psi_min = min Psi (+inf if none), n_valid = box-valid translations
+ *   (clashes included), n_finite = non-clashing ones, argmin = linear index
+ *   (tz*Vy + ty)*Vx + tx of psi_min (lowest on ties, -1 if none).
+ * m, s, psi_min are computed in the context precision. */
+typedef struct {
+    double m;
+    double s;
+    double psi_min;
+    int32_t n_valid;
+    int32_t n_finite;
+    int32_t argmin;
+    int32_t scanned; /* 1 if the configuration was scanned */
+} fftdg_partial;
+
+/* Per-ligand result of fftdg_reduce. */
+typedef struct {
+    double dG;        /* Eq. 13, kcal/mol (+inf if every snapshot's BPMF is +inf) */
+    double v_site;    /* A^3: h^3 x mean over configurations of box-valid translations */
+    double psi_min;   /* min interaction energy over snapshots and configurations */
+    int64_t n_finite; /* non-clashing samples over snapshots */
+    int64_t n_samples; /* box-valid samples per snapshot (sum over configurations) */
+} fftdg_ligand_result;
+
+int fftdg_version(void);
+const char *fftdg_status_string(int status);
+
+/* Create a context on HIP device `device`, ordering work on `hip_stream`
+ * (a hipStream_t, or NULL for the default stream).  Validates g.
+ * Errors: E_INVALID (g), E_DEVICE (no device / HIP error), E_NOMEM. */
+int fftdg_create(fftdg_ctx **out, const fftdg_grid_desc *g, int device, void *hip_stream);
+void fftdg_destroy(fftdg_ctx *ctx);
+const char *fftdg_last_error(const fftdg_ctx *ctx);
+int fftdg_set_stream(fftdg_ctx *ctx, void *hip_stream);
+
+/* Receptor grids of Eq. 7 (ELE = 332.05 q/r, LJr = sqrt(eps) sigma^6/r^12,
+ * LJa = sqrt(eps) sigma^3/r^6, with the exclusion rule of the clash mode) and
+ * the receptor occupancy grid of Eq. 10, built on the GPU in FP64 from
+ * receptor atoms (xyz_dev [n_atoms][3], q/sigma/eps_dev [n_atoms], all
+ * double, device).  Writes grids_dev [3][n_rec^3] in the context precision
+ * and, in FFTDG_OCC mode, occ_dev [n_rec^3] (0/1 bytes; may be NULL in CAP).
+ * Asynchronous. */
+int fftdg_receptor_grids(fftdg_ctx *ctx, int32_t n_atoms, const double *xyz_dev,
+                         const double *q_dev, const double *sigma_dev, const double *eps_dev,
+                         void *grids_dev, uint8_t *occ_dev);
+
+/* Precompute the receptor spectra FT(G_R) of Eq. 9 for n_snap snapshots.
+ *   grids_dev [n_snap][3][n_rec^3] (context precision, device)
+ *   occ_dev   [n_snap][n_rec^3] bytes (device), required in OCC, ignored in CAP
+ *   w_host    [n_snap] snapshot weights W of Eq. 13 (normalised internally,
+ *             must be >= 0 with a positive sum); NULL = uniform.
+ * The library owns the spectra; the caller may free its grids once the
+ * stream has passed this call.  Replaces any previous receptor set. */
+int fftdg_set_receptors(fftdg_ctx *ctx, int32_t n_snap, const void *grids_dev,
+                        const uint8_t *occ_dev, const double *w_host);
+
+/* The scan (Eqs. 2, 8-10): places every configuration of the batch (host,
+ * FP64, exact integer box), runs the FFT correlation against every receptor
+ * snapshot and writes out_dev[snap * n_cfg_total + c] (device) for all
+ * snapshots and configurations.  Temperature T_K > 0.  Asynchronous: keep
+ * out_dev alive until the stream passes this call.
+ * Errors: E_STATE (no receptors), E_INVALID, E_NOVALID (a ligand without
+ * any box-valid translation), E_NOMEM, E_DEVICE. */
+int fftdg_scan(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, fftdg_partial *out_dev);
+
+/* Raw interaction energy Psi (Eq. 8, before clash masking) at every
+ * box-valid translation of one configuration `cfg` (index into the batch)
+ * against snapshot `snap`: psi_dev [Vz][Vy][Vx] in the context precision,
+ * clash_dev [Vz][Vy][Vx] bytes (NULL allowed; all 0 in CAP mode).  shape_host
+ * receives {Vz, Vy, Vx}; call with psi_dev == NULL to query the shape only.
+ * Synchronizes the stream. */
+int fftdg_energy_grid(fftdg_ctx *ctx, int32_t snap, const fftdg_batch *b, int32_t cfg,
+                      double T_K, void *psi_dev, uint8_t *clash_dev, int32_t *shape_host);
+
+/* Placement of configuration `cfg` as the scan does it: lattice coordinates
+ * U_host [n_atoms][3] (grid units x 2^16) and the box extents box_host[3]
+ * (x, y, z).  Host only. */
+int fftdg_place(fftdg_ctx *ctx, const fftdg_batch *b, int32_t cfg, int32_t *U_host,
+                int32_t *box_host);
+
+/* FP64 exponential averages on the GPU (Eqs. 2, 12, 13):
+ *   ln Z_{l,s} = LSE over configurations c of ligand l of
+ *                ln(w_c) + m_{s,c} + ln s_{s,c}   (w_c = 1 if cfg_weight_dev
+ *                is NULL; else cfg_weight_dev[c] >= 0, e.g. multiplicity/(K q_c)
+ *                for importance sampling)
+ *   B_{l,s}    = -kT (ln Z_{l,s} - ln sum_c n_valid_c)
+ *   dG_l       = -kT ln sum_s W_s exp(-B_{l,s}/kT) - kT ln(V_site C0),
+ *                V_site = h^3 mean_c n_valid_c, C0 = 1 M.
+ * p_dev as written by fftdg_scan for the same batch.  Writes B_host
+ * [n_lig][n_snap] and res_host [n_lig] (host).  Synchronizes the stream. */
+int fftdg_reduce(fftdg_ctx *ctx, const fftdg_batch *b, const fftdg_partial *p_dev,
+                 const double *cfg_weight_dev, double T_K, double *B_host,
+                 fftdg_ligand_result *res_host);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* FFTDG_H */

@@ -1,0 +1,246 @@
+"""ctypes binding of libfftdg.so (argument marshalling only).
+
+Every step of the scan runs in the library's HIP kernels; PyTorch only
+provides device memory (tensors) and the stream.  If the shared library is
+missing, `load()` raises: there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfftdg.so")
+
+OK, E_INVALID, E_NOVALID, E_NOMEM, E_DEVICE, E_STATE = 0, -1, -2, -3, -4, -5
+F32, F64 = 0, 1
+OCC, CAP = 0, 1
+
+PARTIAL_DTYPE = np.dtype([("m", "<f8"), ("s", "<f8"), ("psi_min", "<f8"), ("n_valid", "<i4"),
+                          ("n_finite", "<i4"), ("argmin", "<i4"), ("scanned", "<i4")])
+RESULT_DTYPE = np.dtype([("dG", "<f8"), ("v_site", "<f8"), ("psi_min", "<f8"), ("n_finite", "<i8"),
+                         ("n_samples", "<i8")])
+
+
+class FFTDGError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fftdg error {code}: {msg}")
+        self.code = code
+
+
+class GridDesc(ctypes.Structure):
+    _fields_ = [("n_rec", ctypes.c_int32), ("n_fft", ctypes.c_int32), ("h", ctypes.c_double),
+                ("origin", ctypes.c_double * 3), ("precision", ctypes.c_int32),
+                ("clash_mode", ctypes.c_int32), ("ljr_cap", ctypes.c_double), ("occ_f", ctypes.c_double)]
+
+
+class BatchC(ctypes.Structure):
+    _fields_ = [("n_lig", ctypes.c_int32), ("atom_off", ctypes.c_void_p), ("conf_off", ctypes.c_void_p),
+                ("cfg_off", ctypes.c_void_p), ("q", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
+                ("eps", ctypes.c_void_p), ("conf_xyz", ctypes.c_void_p), ("cfg_conf", ctypes.c_void_p),
+                ("cfg_quat", ctypes.c_void_p), ("cfg_select", ctypes.c_void_p)]
+
+
+EXPORTS = ["fftdg_version", "fftdg_status_string", "fftdg_create", "fftdg_destroy", "fftdg_last_error",
+           "fftdg_set_stream", "fftdg_receptor_grids", "fftdg_set_receptors", "fftdg_scan",
+           "fftdg_energy_grid", "fftdg_place", "fftdg_reduce"]
+
+_lib = None
+
+
+def load():
+    """Load libfftdg.so from the package directory (raises if absent)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is not built; run paper_1708_07045_amd/build.py "
+                          "(or __graft_entry__.build()) first")
+    L = ctypes.CDLL(LIB_PATH)
+    p, i32, d = ctypes.c_void_p, ctypes.c_int32, ctypes.c_double
+    L.fftdg_version.restype = ctypes.c_int
+    L.fftdg_status_string.argtypes = [ctypes.c_int]
+    L.fftdg_status_string.restype = ctypes.c_char_p
+    L.fftdg_create.argtypes = [ctypes.POINTER(p), ctypes.POINTER(GridDesc), ctypes.c_int, p]
+    L.fftdg_destroy.argtypes = [p]
+    L.fftdg_destroy.restype = None
+    L.fftdg_last_error.argtypes = [p]
+    L.fftdg_last_error.restype = ctypes.c_char_p
+    L.fftdg_set_stream.argtypes = [p, p]
+    L.fftdg_receptor_grids.argtypes = [p, i32, p, p, p, p, p, p]
+    L.fftdg_set_receptors.argtypes = [p, i32, p, p, p]
+    L.fftdg_scan.argtypes = [p, ctypes.POINTER(BatchC), d, p]
+    L.fftdg_energy_grid.argtypes = [p, i32, ctypes.POINTER(BatchC), i32, d, p, p, p]
+    L.fftdg_place.argtypes = [p, ctypes.POINTER(BatchC), i32, p, p]
+    L.fftdg_reduce.argtypes = [p, ctypes.POINTER(BatchC), p, p, d, p, p]
+    for name in EXPORTS:
+        if name not in ("fftdg_destroy", "fftdg_status_string", "fftdg_last_error"):
+            getattr(L, name).restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _ptr(a) -> Optional[int]:
+    if a is None:
+        return None
+    if isinstance(a, np.ndarray):
+        return a.ctypes.data
+    return a.data_ptr()  # torch tensor
+
+
+class Batch:
+    """Host arrays of a batch of ligands and configurations (fftdg_batch)."""
+
+    def __init__(self, ligands: Sequence, select: Optional[np.ndarray] = None):
+        n_lig = len(ligands)
+        self.n_lig = n_lig
+        self.atom_off = np.zeros(n_lig + 1, np.int32)
+        self.conf_off = np.zeros(n_lig + 1, np.int32)
+        self.cfg_off = np.zeros(n_lig + 1, np.int32)
+        for l, L in enumerate(ligands):
+            self.atom_off[l + 1] = self.atom_off[l] + L.n_atoms
+            self.conf_off[l + 1] = self.conf_off[l] + L.conformers.shape[0]
+            self.cfg_off[l + 1] = self.cfg_off[l] + L.n_cfg
+        cat = lambda xs, dt: np.ascontiguousarray(np.concatenate(xs), dtype=dt)
+        self.q = cat([L.q for L in ligands], np.float64)
+        self.sigma = cat([L.sigma for L in ligands], np.float64)
+        self.eps = cat([L.eps for L in ligands], np.float64)
+        self.conf_xyz = cat([L.conformers.reshape(-1, 3) for L in ligands], np.float64)
+        self.cfg_conf = cat([L.cfg_conf for L in ligands], np.int32)
+        self.cfg_quat = cat([L.cfg_quat for L in ligands], np.float64)
+        self.select = None if select is None else np.ascontiguousarray(select, np.uint8)
+        self.n_cfg = int(self.cfg_off[-1])
+        self.c = BatchC(n_lig, _ptr(self.atom_off), _ptr(self.conf_off), _ptr(self.cfg_off), _ptr(self.q),
+                        _ptr(self.sigma), _ptr(self.eps), _ptr(self.conf_xyz), _ptr(self.cfg_conf),
+                        _ptr(self.cfg_quat), _ptr(self.select))
+
+    def with_select(self, select: Optional[np.ndarray]) -> "Batch":
+        b = object.__new__(Batch)
+        b.__dict__.update(self.__dict__)
+        b.select = None if select is None else np.ascontiguousarray(select, np.uint8)
+        b.c = BatchC(*[getattr(self.c, f) for f, _ in BatchC._fields_])
+        b.c.cfg_select = _ptr(b.select)
+        return b
+
+
+class FFTDG:
+    """One library context (one device, one stream)."""
+
+    def __init__(self, n_rec: int, n_fft: int, h: float, origin, precision: str = "f32",
+                 clash_mode: str = "occ", ljr_cap: float = 10.0, occ_f: float = 0.5, device: int = 0,
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.L = load()
+        self.precision = precision
+        self.clash_mode = clash_mode
+        self.n_rec, self.n_fft, self.h = n_rec, n_fft, h
+        self.dtype = torch.float32 if precision == "f32" else torch.float64
+        self.device = torch.device("cuda", device)
+        g = GridDesc(n_rec, n_fft, h, (ctypes.c_double * 3)(*[float(x) for x in origin]),
+                     F32 if precision == "f32" else F64, OCC if clash_mode == "occ" else CAP,
+                     ljr_cap, occ_f)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        h_ = ctypes.c_void_p()
+        rc = self.L.fftdg_create(ctypes.byref(h_), ctypes.byref(g), device, ctypes.c_void_p(stream))
+        if rc != OK:
+            raise FFTDGError(rc, "fftdg_create failed (" + self.L.fftdg_status_string(rc).decode() + ")")
+        self.h_ctx = h_
+        self.n_snap = 0
+
+    @classmethod
+    def from_workload(cls, w, device: int = 0, precision: Optional[str] = None):
+        return cls(w.n_rec, w.n_fft, w.h, w.origin, precision or w.precision, w.clash_mode, w.ljr_cap,
+                   w.occ_f, device)
+
+    def close(self):
+        if getattr(self, "h_ctx", None):
+            self.L.fftdg_destroy(self.h_ctx)
+            self.h_ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc: int):
+        if rc != OK:
+            raise FFTDGError(rc, self.L.fftdg_last_error(self.h_ctx).decode())
+
+    def set_stream(self, stream_handle: int):
+        self._check(self.L.fftdg_set_stream(self.h_ctx, ctypes.c_void_p(stream_handle)))
+
+    # ---------------------------------------------------------------- receptor
+    def receptor_grids(self, xyz, q, sigma, eps):
+        """Eq. 7 / Eq. 10 grids of one receptor snapshot on the GPU."""
+        t = self.torch
+        dev = lambda a: t.as_tensor(np.ascontiguousarray(a, np.float64), device=self.device)
+        X, Q, S, E = dev(xyz), dev(q), dev(sigma), dev(eps)
+        n = self.n_rec
+        grids = t.empty((3, n, n, n), dtype=self.dtype, device=self.device)
+        occ = t.empty((n, n, n), dtype=t.uint8, device=self.device) if self.clash_mode == "occ" else None
+        self._check(self.L.fftdg_receptor_grids(self.h_ctx, int(X.shape[0]), _ptr(X), _ptr(Q), _ptr(S), _ptr(E),
+                                                _ptr(grids), _ptr(occ)))
+        self._keep = (X, Q, S, E)
+        return grids, occ
+
+    def set_receptors(self, grids, occ=None, weights=None):
+        """grids: tensor [n_snap][3][n^3] (or [3][n^3]); occ: [n_snap][n^3] uint8."""
+        n_snap = grids.shape[0] if grids.dim() == 5 else 1
+        w = None if weights is None else np.ascontiguousarray(weights, np.float64)
+        self._check(self.L.fftdg_set_receptors(self.h_ctx, n_snap, _ptr(grids.contiguous()),
+                                               _ptr(occ.contiguous()) if occ is not None else None,
+                                               _ptr(w)))
+        self.n_snap = n_snap
+
+    # ---------------------------------------------------------------- scan
+    def alloc_partials(self, batch: Batch):
+        return self.torch.empty(self.n_snap * batch.n_cfg * PARTIAL_DTYPE.itemsize, dtype=self.torch.uint8,
+                                device=self.device)
+
+    def scan(self, batch: Batch, T: float, out=None):
+        """Partials [n_snap * n_cfg] (device bytes of fftdg_partial)."""
+        if out is None:
+            out = self.alloc_partials(batch)
+        self._check(self.L.fftdg_scan(self.h_ctx, ctypes.byref(batch.c), float(T), _ptr(out)))
+        return out
+
+    @staticmethod
+    def partials_numpy(buf, n_snap: int, n_cfg: int) -> np.ndarray:
+        a = buf.cpu().numpy().view(PARTIAL_DTYPE)
+        return a.reshape(n_snap, n_cfg)
+
+    def energy_grid(self, snap: int, batch: Batch, cfg: int, T: float = 300.0):
+        shape = np.zeros(3, np.int32)
+        self._check(self.L.fftdg_energy_grid(self.h_ctx, snap, ctypes.byref(batch.c), cfg, float(T), None, None,
+                                             _ptr(shape)))
+        t = self.torch
+        psi = t.zeros(tuple(int(s) for s in shape), dtype=self.dtype, device=self.device)
+        clash = t.zeros(tuple(int(s) for s in shape), dtype=t.uint8, device=self.device)
+        if psi.numel() > 0:
+            self._check(self.L.fftdg_energy_grid(self.h_ctx, snap, ctypes.byref(batch.c), cfg, float(T),
+                                                 _ptr(psi), _ptr(clash), _ptr(shape)))
+        return psi, clash
+
+    def place(self, batch: Batch, cfg: int):
+        l = int(np.searchsorted(batch.cfg_off, cfg, side="right") - 1)
+        na = int(batch.atom_off[l + 1] - batch.atom_off[l])
+        U = np.zeros((na, 3), np.int32)
+        box = np.zeros(3, np.int32)
+        self._check(self.L.fftdg_place(self.h_ctx, ctypes.byref(batch.c), cfg, _ptr(U), _ptr(box)))
+        return U, box
+
+    def reduce(self, batch: Batch, partials, T: float, cfg_weight=None):
+        B = np.zeros((batch.n_lig, self.n_snap), np.float64)
+        res = np.zeros(batch.n_lig, RESULT_DTYPE)
+        w = None
+        if cfg_weight is not None:
+            w = self.torch.as_tensor(np.ascontiguousarray(cfg_weight, np.float64), device=self.device)
+        self._check(self.L.fftdg_reduce(self.h_ctx, ctypes.byref(batch.c), _ptr(partials), _ptr(w), float(T),
+                                        _ptr(B), _ptr(res)))
+        return B, res

@@ -1,0 +1,40 @@
+// Host-side view of the kernel launchers (one set per precision and FFT edge).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/fftdg.h"
+#include "scan_types.hpp"
+
+namespace fftdg {
+
+struct KernelSet {
+    int n_fft;
+    int cbytes;   // bytes per complex element
+    int ppbytes;  // bytes per plane partial
+    int np;       // complex elements per half-plane, n_fft * (n_fft/2 + 1)
+    // receptor spectra of one snapshot: grids [3][n_rec^3] (+ occ [n_rec^3])
+    // -> rspec [n_ch][N][np]; rxy is scratch [n_ch][n_rec][np]
+    hipError_t (*rec_spectra)(hipStream_t, const void *grids, const uint8_t *occ, int n_rec, int n_ch,
+                              const void *tw, void *rxy, void *rspec);
+    hipError_t (*fwd)(hipStream_t, const FwdItem *items, int n_items, const CfgDev *cfgs, const int32_t *ulat,
+                      const void *gam, const double *thr, const void *tw, void *ws);
+    hipError_t (*zprod)(hipStream_t, bool occ, const CfgDev *cfgs, const int32_t *zcfg, int nz, const void *ws,
+                        const void *rspec, const void *tw, void *wsi);
+    hipError_t (*inv)(hipStream_t, bool occ, const InvItem *items, int n_items, const CfgDev *cfgs,
+                      const void *wsi, double beta, const void *tw, void *pp, void *psi_out,
+                      uint8_t *clash_out);
+    hipError_t (*merge)(hipStream_t, const CfgDev *cfgs, int n_cfg, const void *pp, fftdg_partial *out);
+};
+
+const KernelSet *kernel_set(int precision, int n_fft);
+
+hipError_t launch_reduce(hipStream_t st, const fftdg_partial *p, int64_t n_cfg_total, int n_snap, int n_lig,
+                         const int32_t *cfg_off, const double *cfg_w, const double *W, double kT, double h3,
+                         double c0, double *B, LigRed *res);
+
+hipError_t launch_receptor_grids(hipStream_t st, int precision, int n_atoms, const double *xyz, const double *q,
+                                 const double *sg, const double *ep, int n_rec, double h, const double *origin,
+                                 int mode, double cap, double occ_f, void *grids, uint8_t *occ);
+
+}  // namespace fftdg

@@ -1,0 +1,738 @@
+// C-ABI runtime of libfftdg: context, validation, ligand placement, work
+// planning and kernel launches.  See include/fftdg.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "../../include/fftdg.h"
+#include "kernels.hpp"
+#include "scan_types.hpp"
+
+using namespace fftdg;
+
+namespace {
+
+constexpr double kR = 1.987204259e-3;       // kcal mol^-1 K^-1
+constexpr double kC0 = 6.02214076e-4;       // 1 mol/L in A^-3
+constexpr double kLat = 65536.0;            // placement lattice: 2^16 points per grid unit
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t n = 0;
+};
+
+}  // namespace
+
+struct fftdg_ctx {
+    fftdg_grid_desc g{};
+    int device = 0;
+    hipStream_t stream = nullptr;
+    std::string err;
+    const KernelSet *ks = nullptr;
+    int n_ch = 3;  // receptor/ligand channels: 3 energy (+1 occupancy)
+    DevBuf tw, rspec, rxy, ws_fwd, ws_inv, pp, tables, red_B, red_res, red_off, red_W;
+    int n_snap = 0;
+    std::vector<double> W;
+    void *pinned = nullptr;
+    size_t pinned_n = 0;
+    hipEvent_t staging_ev = nullptr;
+    bool staging_used = false;
+    int chunk_cfgs = 256;
+    size_t ws_limit = (size_t)24 << 30;
+};
+
+namespace {
+
+int set_err(fftdg_ctx *c, int code, const std::string &msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(ctx, expr)                                                                     \
+    do {                                                                                      \
+        hipError_t e_ = (expr);                                                               \
+        if (e_ != hipSuccess)                                                                 \
+            return set_err(ctx, FFTDG_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int reserve(fftdg_ctx *c, DevBuf &b, size_t bytes) {
+    if (bytes <= b.n) return FFTDG_OK;
+    if (b.p) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) return set_err(c, FFTDG_E_DEVICE, std::string("hipStreamSynchronize: ") + hipGetErrorString(e));
+        (void)hipFree(b.p);
+        b.p = nullptr;
+        b.n = 0;
+    }
+    size_t want = bytes + bytes / 8 + 256;
+    hipError_t e = hipMalloc(&b.p, want);
+    if (e != hipSuccess) {
+        b.p = nullptr;
+        (void)hipGetLastError();
+        return set_err(c, FFTDG_E_NOMEM, "device allocation of " + std::to_string(want) + " bytes failed");
+    }
+    b.n = want;
+    return FFTDG_OK;
+}
+
+int reserve_pinned(fftdg_ctx *c, size_t bytes) {
+    if (c->staging_used) {
+        hipError_t e = hipEventSynchronize(c->staging_ev);
+        if (e != hipSuccess) return set_err(c, FFTDG_E_DEVICE, std::string("hipEventSynchronize: ") + hipGetErrorString(e));
+        c->staging_used = false;
+    }
+    if (bytes <= c->pinned_n) return FFTDG_OK;
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    c->pinned = nullptr;
+    c->pinned_n = 0;
+    size_t want = bytes + bytes / 4 + 4096;
+    if (hipHostMalloc(&c->pinned, want, hipHostMallocDefault) != hipSuccess) {
+        c->pinned = nullptr;
+        (void)hipGetLastError();
+        return set_err(c, FFTDG_E_NOMEM, "pinned host allocation failed");
+    }
+    c->pinned_n = want;
+    return FFTDG_OK;
+}
+
+bool is_fin(double v) { return std::isfinite(v); }
+
+long long isqrt_lt(long long rem) {  // largest s >= 0 with s*s < rem (rem >= 1)
+    long long s = (long long)std::sqrt((double)rem);
+    while (s > 0 && s * s >= rem) --s;
+    while ((s + 1) * (s + 1) < rem) ++s;
+    return s;
+}
+long long floordiv(long long a, long long b) {
+    long long q = a / b;
+    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+
+// Placement (Ligand Sampling; placement and box rule of the FFT-based BPMF
+// section): rotate about the unweighted centroid by the normalised
+// quaternion, shift the lowest coordinate to 2 spacings, round to the 2^-16
+// lattice; box_d = ceil(max u_d) + 2.  Returns false for a zero or
+// non-finite quaternion or coordinates beyond the lattice range.
+bool place_one(const double *X, int n, const double *quat, double h, int32_t *U, int *box) {
+    const double nq = std::sqrt(quat[0] * quat[0] + quat[1] * quat[1] + quat[2] * quat[2] + quat[3] * quat[3]);
+    if (!(nq > 0.0) || !is_fin(nq)) return false;
+    const double w = quat[0] / nq, x = quat[1] / nq, y = quat[2] / nq, z = quat[3] / nq;
+    const double R[3][3] = {{1.0 - 2.0 * (y * y + z * z), 2.0 * (x * y - w * z), 2.0 * (x * z + w * y)},
+                            {2.0 * (x * y + w * z), 1.0 - 2.0 * (x * x + z * z), 2.0 * (y * z - w * x)},
+                            {2.0 * (x * z - w * y), 2.0 * (y * z + w * x), 1.0 - 2.0 * (x * x + y * y)}};
+    double c[3] = {0, 0, 0};
+    for (int i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) c[d] += X[3 * i + d];
+    for (int d = 0; d < 3; ++d) c[d] /= n;
+    double mn[3] = {INFINITY, INFINITY, INFINITY};
+    std::vector<double> Y(3 * (size_t)n);
+    for (int i = 0; i < n; ++i) {
+        const double v[3] = {X[3 * i] - c[0], X[3 * i + 1] - c[1], X[3 * i + 2] - c[2]};
+        for (int d = 0; d < 3; ++d) {
+            Y[3 * i + d] = R[d][0] * v[0] + R[d][1] * v[1] + R[d][2] * v[2];
+            if (Y[3 * i + d] < mn[d]) mn[d] = Y[3 * i + d];
+        }
+    }
+    long long mx[3] = {0, 0, 0};
+    for (int i = 0; i < n; ++i)
+        for (int d = 0; d < 3; ++d) {
+            const double v = (Y[3 * i + d] - mn[d]) / h + 2.0;
+            if (!(v < 30000.0)) return false;
+            const long long L = std::llround(v * kLat);
+            U[3 * i + d] = (int32_t)L;
+            if (L > mx[d]) mx[d] = L;
+        }
+    for (int d = 0; d < 3; ++d) box[d] = (int)(-floordiv(-mx[d], 65536LL)) + 2;
+    return true;
+}
+
+template <typename T>
+size_t csize() {
+    return 2 * sizeof(T);
+}
+
+struct Plan {
+    // per configuration (batch order)
+    std::vector<CfgDev> cfg;
+    std::vector<int32_t> U;        // lattice coords, [sum atoms][3]
+    std::vector<int32_t> cfg_lig;  // ligand of each configuration
+    // chunks: contiguous configuration ranges
+    struct Chunk {
+        int c0, c1;               // configurations [c0, c1)
+        size_t fwd0, nfwd;        // fwd items
+        size_t inv0, ninv;        // inv items
+        size_t z0, nz;            // scanned configurations (local indices)
+        int64_t ws_fwd, ws_inv;   // complex elements used
+        int pp;                   // plane partial slots used
+    };
+    std::vector<Chunk> chunks;
+    std::vector<FwdItem> fwd;
+    std::vector<InvItem> inv;
+    std::vector<int32_t> zcfg;
+    int64_t max_fwd = 0, max_inv = 0;
+    int max_pp = 0;
+};
+
+int validate_batch(fftdg_ctx *ctx, const fftdg_batch *b) {
+    if (!b) return set_err(ctx, FFTDG_E_INVALID, "batch is NULL");
+    if (b->n_lig <= 0) return set_err(ctx, FFTDG_E_INVALID, "n_lig must be > 0");
+    if (!b->atom_off || !b->conf_off || !b->cfg_off || !b->q || !b->sigma || !b->eps || !b->conf_xyz ||
+        !b->cfg_conf || !b->cfg_quat)
+        return set_err(ctx, FFTDG_E_INVALID, "batch has a NULL array");
+    if (b->atom_off[0] != 0 || b->conf_off[0] != 0 || b->cfg_off[0] != 0)
+        return set_err(ctx, FFTDG_E_INVALID, "offsets must start at 0");
+    for (int l = 0; l < b->n_lig; ++l) {
+        const int na = b->atom_off[l + 1] - b->atom_off[l];
+        const int nc = b->conf_off[l + 1] - b->conf_off[l];
+        const int ng = b->cfg_off[l + 1] - b->cfg_off[l];
+        if (na <= 0 || na > 256) return set_err(ctx, FFTDG_E_INVALID, "ligand " + std::to_string(l) + ": atom count must be 1..256");
+        if (nc <= 0) return set_err(ctx, FFTDG_E_INVALID, "ligand " + std::to_string(l) + ": no conformers");
+        if (ng <= 0) return set_err(ctx, FFTDG_E_INVALID, "ligand " + std::to_string(l) + ": no configurations");
+    }
+    const int na = b->atom_off[b->n_lig];
+    for (int i = 0; i < na; ++i) {
+        if (!is_fin(b->q[i]) || !is_fin(b->sigma[i]) || !is_fin(b->eps[i]) || b->sigma[i] <= 0 || b->eps[i] < 0)
+            return set_err(ctx, FFTDG_E_INVALID, "atom " + std::to_string(i) + ": non-finite or out-of-range parameter");
+    }
+    size_t rows = 0;
+    for (int l = 0; l < b->n_lig; ++l)
+        rows += (size_t)(b->conf_off[l + 1] - b->conf_off[l]) * (b->atom_off[l + 1] - b->atom_off[l]);
+    for (size_t i = 0; i < 3 * rows; ++i)
+        if (!is_fin(b->conf_xyz[i])) return set_err(ctx, FFTDG_E_INVALID, "non-finite conformer coordinate");
+    const int ncfg = b->cfg_off[b->n_lig];
+    for (int l = 0; l < b->n_lig; ++l) {
+        const int nc = b->conf_off[l + 1] - b->conf_off[l];
+        for (int c = b->cfg_off[l]; c < b->cfg_off[l + 1]; ++c)
+            if (b->cfg_conf[c] < 0 || b->cfg_conf[c] >= nc)
+                return set_err(ctx, FFTDG_E_INVALID, "configuration " + std::to_string(c) + ": conformer index out of range");
+    }
+    for (int i = 0; i < 4 * ncfg; ++i)
+        if (!is_fin(b->cfg_quat[i])) return set_err(ctx, FFTDG_E_INVALID, "non-finite quaternion");
+    return FFTDG_OK;
+}
+
+double occ_threshold(const fftdg_grid_desc &g, double sigma) {
+    const double rho = g.occ_f * std::pow(2.0, -1.0 / 6.0) * sigma / g.h;
+    return std::ceil(rho * rho * 4294967296.0);
+}
+
+// Place every configuration and build the chunked work lists.
+int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg, Plan &P) {
+    const fftdg_grid_desc &g = ctx->g;
+    const int N = g.n_fft, n_rec = g.n_rec;
+    const bool occ = g.clash_mode == FFTDG_OCC;
+    const int ncfg = b->cfg_off[b->n_lig];
+    P.cfg.assign(ncfg, CfgDev{});
+    P.cfg_lig.assign(ncfg, 0);
+    // atom / conformer-row offsets
+    std::vector<size_t> xyz_row(b->n_lig);
+    size_t rows = 0;
+    for (int l = 0; l < b->n_lig; ++l) {
+        xyz_row[l] = rows;
+        rows += (size_t)(b->conf_off[l + 1] - b->conf_off[l]) * (b->atom_off[l + 1] - b->atom_off[l]);
+    }
+    std::vector<size_t> ubase(ncfg + 1, 0);
+    for (int l = 0; l < b->n_lig; ++l)
+        for (int c = b->cfg_off[l]; c < b->cfg_off[l + 1]; ++c) {
+            P.cfg_lig[c] = l;
+            ubase[c + 1] = b->atom_off[l + 1] - b->atom_off[l];
+        }
+    for (int c = 0; c < ncfg; ++c) ubase[c + 1] += ubase[c];
+    P.U.assign(3 * ubase[ncfg], 0);
+    std::vector<double> thr(b->atom_off[b->n_lig]);
+    std::vector<long long> reach(thr.size());
+    for (size_t i = 0; i < thr.size(); ++i) {
+        thr[i] = occ ? occ_threshold(g, b->sigma[i]) : 0.0;
+        reach[i] = occ && thr[i] >= 1.0 ? isqrt_lt((long long)thr[i]) : -1;
+    }
+    std::atomic<int> bad(-1), bad_geom(-1);
+    auto work = [&](int c_begin, int c_end) {
+        for (int c = c_begin; c < c_end; ++c) {
+            const int l = P.cfg_lig[c];
+            const int na = b->atom_off[l + 1] - b->atom_off[l];
+            const double *X = b->conf_xyz + 3 * (xyz_row[l] + (size_t)b->cfg_conf[c] * na);
+            int32_t *U = P.U.data() + 3 * ubase[c];
+            int box[3];
+            CfgDev &d = P.cfg[c];
+            d.u_base = (int32_t)ubase[c];
+            d.atom_base = b->atom_off[l];
+            d.n_atoms = na;
+            d.global_cfg = c;
+            if (!place_one(X, na, b->cfg_quat + 4 * c, g.h, U, box)) {
+                int exp = -1;
+                bad.compare_exchange_strong(exp, c);
+                continue;
+            }
+            long long nv = 1;
+            for (int k = 0; k < 3; ++k) {
+                d.V[k] = std::max(n_rec - box[k], 0);
+                nv *= d.V[k];
+            }
+            d.n_valid = (int32_t)nv;
+            const bool sel = (!only_one && (!b->cfg_select || b->cfg_select[c])) || (only_one && c == one_cfg);
+            d.scanned = (sel && nv > 0) ? 1 : 0;
+            // energy channel planes and rows (trilinear corners floor(u), floor(u)+1)
+            int zlo = 1 << 30, zhi = -(1 << 30), ylo = 1 << 30, yhi = -(1 << 30);
+            long long ozlo = 1LL << 40, ozhi = -(1LL << 40), oylo = 1LL << 40, oyhi = -(1LL << 40);
+            for (int i = 0; i < na; ++i) {
+                const int az = U[3 * i + 2] >> 16, ay = U[3 * i + 1] >> 16;
+                zlo = std::min(zlo, az);
+                zhi = std::max(zhi, az + 1);
+                ylo = std::min(ylo, ay);
+                yhi = std::max(yhi, ay + 1);
+                if (occ) {
+                    const long long s = reach[b->atom_off[l] + i];
+                    if (s < 0) continue;
+                    ozlo = std::min(ozlo, -floordiv(-(U[3 * i + 2] - s), 65536LL));
+                    ozhi = std::max(ozhi, floordiv(U[3 * i + 2] + s, 65536LL));
+                    oylo = std::min(oylo, -floordiv(-(U[3 * i + 1] - s), 65536LL));
+                    oyhi = std::max(oyhi, floordiv(U[3 * i + 1] + s, 65536LL));
+                    if (2 * s / 65536 + 2 >= N) {
+                        int exp = -1;
+                        bad_geom.compare_exchange_strong(exp, c);
+                    }
+                }
+            }
+            d.ze0 = zlo;
+            d.Le = zhi - zlo + 1;
+            d.ye0 = ylo;
+            d.Lye = yhi - ylo + 1;
+            if (occ && ozhi >= ozlo) {
+                d.zo0 = (int32_t)ozlo;
+                d.Lo = (int32_t)(ozhi - ozlo + 1);
+                d.yo0 = (int32_t)oylo;
+                d.Lyo = (int32_t)(oyhi - oylo + 1);
+            } else {
+                d.zo0 = 0;
+                d.Lo = 0;
+                d.yo0 = 0;
+                d.Lyo = 0;
+            }
+            if (d.scanned && (d.Le > N || d.Lye > N || d.Lo > N || d.Lyo > N)) {
+                int exp = -1;
+                bad_geom.compare_exchange_strong(exp, c);
+            }
+        }
+    };
+    const int nthr = std::max(1, std::min<int>((int)std::thread::hardware_concurrency(), ncfg / 64 + 1));
+    if (nthr <= 1) {
+        work(0, ncfg);
+    } else {
+        std::vector<std::thread> th;
+        const int per = (ncfg + nthr - 1) / nthr;
+        for (int t = 0; t < nthr; ++t) {
+            const int a = t * per, e = std::min(ncfg, a + per);
+            if (a < e) th.emplace_back(work, a, e);
+        }
+        for (auto &t : th) t.join();
+    }
+    if (bad.load() >= 0)
+        return set_err(ctx, FFTDG_E_INVALID, "configuration " + std::to_string(bad.load()) +
+                                                 ": zero or non-finite quaternion, or ligand far larger than the grid");
+    if (bad_geom.load() >= 0)
+        return set_err(ctx, FFTDG_E_INVALID, "configuration " + std::to_string(bad_geom.load()) +
+                                                 ": occupancy extent of the ligand exceeds n_fft");
+    // every ligand needs at least one box-valid configuration
+    for (int l = 0; l < b->n_lig && !only_one; ++l) {
+        bool any = false;
+        for (int c = b->cfg_off[l]; c < b->cfg_off[l + 1] && !any; ++c) any = P.cfg[c].n_valid > 0;
+        if (!any)
+            return set_err(ctx, FFTDG_E_NOVALID, "ligand " + std::to_string(l) +
+                                                     " has no box-valid translation in any configuration");
+    }
+    // chunks
+    const int64_t NP = ctx->ks->np;
+    const int nout = occ ? 2 : 1;
+    const int64_t limit_c = (int64_t)(ctx->ws_limit / (size_t)ctx->ks->cbytes);
+    int c = 0;
+    while (c < ncfg) {
+        Plan::Chunk ch{};
+        ch.c0 = c;
+        ch.fwd0 = P.fwd.size();
+        ch.inv0 = P.inv.size();
+        ch.z0 = P.zcfg.size();
+        int nscan = 0;
+        int64_t wf = 0, wi = 0;
+        int pp = 0;
+        while (c < ncfg) {
+            CfgDev &d = P.cfg[c];
+            if (d.scanned) {
+                const int64_t f = (int64_t)(3 * d.Le + (occ ? d.Lo : 0)) * NP;
+                const int64_t iv = (int64_t)nout * d.V[2] * NP;
+                if (nscan > 0 && (nscan >= ctx->chunk_cfgs || wf + f + wi + iv > limit_c)) break;
+                d.off_fwd = wf;
+                d.off_inv = wi;
+                d.pp_base = pp;
+                const int local = c - ch.c0;
+                for (int k = 0; k < 3; ++k)
+                    for (int p = 0; p < d.Le; ++p) P.fwd.push_back(FwdItem{local, k, p, 0});
+                if (occ)
+                    for (int p = 0; p < d.Lo; ++p) P.fwd.push_back(FwdItem{local, 3, p, 0});
+                for (int tz = 0; tz < d.V[2]; ++tz) P.inv.push_back(InvItem{local, tz});
+                P.zcfg.push_back(local);
+                wf += f;
+                wi += iv;
+                pp += d.V[2];
+                ++nscan;
+            } else {
+                d.off_fwd = d.off_inv = 0;
+                d.pp_base = 0;
+            }
+            ++c;
+        }
+        ch.c1 = c;
+        ch.nfwd = P.fwd.size() - ch.fwd0;
+        ch.ninv = P.inv.size() - ch.inv0;
+        ch.nz = P.zcfg.size() - ch.z0;
+        ch.ws_fwd = wf;
+        ch.ws_inv = wi;
+        ch.pp = pp;
+        P.max_fwd = std::max(P.max_fwd, wf);
+        P.max_inv = std::max(P.max_inv, wi);
+        P.max_pp = std::max(P.max_pp, pp);
+        P.chunks.push_back(ch);
+    }
+    return FFTDG_OK;
+}
+
+template <typename T>
+void fill_gamma(const fftdg_batch *b, T *gam) {
+    const int na = b->atom_off[b->n_lig];
+    for (int i = 0; i < na; ++i) {
+        const double s3 = b->sigma[i] * b->sigma[i] * b->sigma[i];
+        const double se = std::sqrt(b->eps[i]);
+        gam[3 * i + 0] = (T)b->q[i];
+        gam[3 * i + 1] = (T)(se * s3 * s3);
+        gam[3 * i + 2] = (T)(-2.0 * se * s3);
+    }
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// Upload the plan and run it; psi/clash export for the energy-grid call.
+int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, fftdg_partial *out,
+             int snap_only, void *psi_out, uint8_t *clash_out) {
+    const fftdg_grid_desc &g = ctx->g;
+    const bool occ = g.clash_mode == FFTDG_OCC;
+    const int ncfg = b->cfg_off[b->n_lig];
+    const int na = b->atom_off[b->n_lig];
+    const size_t tsz = g.precision == FFTDG_F32 ? sizeof(float) : sizeof(double);
+    // table layout
+    const size_t o_cfg = 0;
+    const size_t o_u = align256(o_cfg + sizeof(CfgDev) * P.cfg.size());
+    const size_t o_fwd = align256(o_u + sizeof(int32_t) * P.U.size());
+    const size_t o_inv = align256(o_fwd + sizeof(FwdItem) * P.fwd.size());
+    const size_t o_z = align256(o_inv + sizeof(InvItem) * P.inv.size());
+    const size_t o_gam = align256(o_z + sizeof(int32_t) * P.zcfg.size());
+    const size_t o_thr = align256(o_gam + tsz * 3 * na);
+    const size_t total = align256(o_thr + sizeof(double) * na);
+    int rc;
+    if ((rc = reserve_pinned(ctx, total))) return rc;
+    if ((rc = reserve(ctx, ctx->tables, total))) return rc;
+    char *h = (char *)ctx->pinned;
+    std::memcpy(h + o_cfg, P.cfg.data(), sizeof(CfgDev) * P.cfg.size());
+    std::memcpy(h + o_u, P.U.data(), sizeof(int32_t) * P.U.size());
+    if (!P.fwd.empty()) std::memcpy(h + o_fwd, P.fwd.data(), sizeof(FwdItem) * P.fwd.size());
+    if (!P.inv.empty()) std::memcpy(h + o_inv, P.inv.data(), sizeof(InvItem) * P.inv.size());
+    if (!P.zcfg.empty()) std::memcpy(h + o_z, P.zcfg.data(), sizeof(int32_t) * P.zcfg.size());
+    if (g.precision == FFTDG_F32)
+        fill_gamma<float>(b, (float *)(h + o_gam));
+    else
+        fill_gamma<double>(b, (double *)(h + o_gam));
+    double *thr = (double *)(h + o_thr);
+    for (int i = 0; i < na; ++i) thr[i] = occ ? occ_threshold(g, b->sigma[i]) : 0.0;
+    const size_t cb = (size_t)ctx->ks->cbytes;
+    if ((rc = reserve(ctx, ctx->ws_fwd, cb * (size_t)std::max<int64_t>(P.max_fwd, 1)))) return rc;
+    if ((rc = reserve(ctx, ctx->ws_inv, cb * (size_t)std::max<int64_t>(P.max_inv, 1)))) return rc;
+    if ((rc = reserve(ctx, ctx->pp, (size_t)ctx->ks->ppbytes * (size_t)std::max(P.max_pp, 1)))) return rc;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->tables.p, h, total, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipEventRecord(ctx->staging_ev, ctx->stream));
+    ctx->staging_used = true;
+    char *d = (char *)ctx->tables.p;
+    const CfgDev *dcfg = (const CfgDev *)(d + o_cfg);
+    const int32_t *du = (const int32_t *)(d + o_u);
+    const FwdItem *dfwd = (const FwdItem *)(d + o_fwd);
+    const InvItem *dinv = (const InvItem *)(d + o_inv);
+    const int32_t *dz = (const int32_t *)(d + o_z);
+    const void *dgam = (const void *)(d + o_gam);
+    const double *dthr = (const double *)(d + o_thr);
+    const double beta = 1.0 / (kR * T_K);
+    const size_t spec_per_snap = (size_t)ctx->n_ch * g.n_fft * ctx->ks->np * cb;
+    const KernelSet *ks = ctx->ks;
+    for (const Plan::Chunk &ch : P.chunks) {
+        const CfgDev *ccfg = dcfg + ch.c0;
+        HIPCHK(ctx, ks->fwd(ctx->stream, dfwd + ch.fwd0, (int)ch.nfwd, ccfg, du, dgam, dthr, ctx->tw.p, ctx->ws_fwd.p));
+        for (int s = 0; s < ctx->n_snap; ++s) {
+            if (snap_only >= 0 && s != snap_only) continue;
+            const char *rs = (const char *)ctx->rspec.p + spec_per_snap * s;
+            HIPCHK(ctx, ks->zprod(ctx->stream, occ, ccfg, dz + ch.z0, (int)ch.nz, ctx->ws_fwd.p, rs, ctx->tw.p,
+                                  ctx->ws_inv.p));
+            HIPCHK(ctx, ks->inv(ctx->stream, occ, dinv + ch.inv0, (int)ch.ninv, ccfg, ctx->ws_inv.p, beta, ctx->tw.p,
+                                ctx->pp.p, psi_out, clash_out));
+            if (out)
+                HIPCHK(ctx, ks->merge(ctx->stream, ccfg, ch.c1 - ch.c0, ctx->pp.p, out + (size_t)s * ncfg));
+        }
+    }
+    return FFTDG_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int fftdg_version(void) { return FFTDG_VERSION; }
+
+const char *fftdg_status_string(int s) {
+    switch (s) {
+    case FFTDG_OK: return "ok";
+    case FFTDG_E_INVALID: return "invalid argument";
+    case FFTDG_E_NOVALID: return "no box-valid translation";
+    case FFTDG_E_NOMEM: return "out of memory";
+    case FFTDG_E_DEVICE: return "device error";
+    case FFTDG_E_STATE: return "call out of order";
+    default: return "unknown status";
+    }
+}
+
+const char *fftdg_last_error(const fftdg_ctx *ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
+
+int fftdg_create(fftdg_ctx **out, const fftdg_grid_desc *g, int device, void *hip_stream) {
+    if (!out) return FFTDG_E_INVALID;
+    *out = nullptr;
+    if (!g) return FFTDG_E_INVALID;
+    fftdg_ctx tmp;
+    auto fail = [&](int code, const std::string &m) {
+        std::fprintf(stderr, "fftdg_create: %s\n", m.c_str());
+        return code;
+    };
+    if (g->precision != FFTDG_F32 && g->precision != FFTDG_F64) return fail(FFTDG_E_INVALID, "precision must be FFTDG_F32 or FFTDG_F64");
+    if (g->clash_mode != FFTDG_OCC && g->clash_mode != FFTDG_CAP) return fail(FFTDG_E_INVALID, "clash_mode must be FFTDG_OCC or FFTDG_CAP");
+    const KernelSet *ks = kernel_set(g->precision, g->n_fft);
+    if (!ks) return fail(FFTDG_E_INVALID, "unsupported n_fft for this precision (F32: 32/64/128, F64: 32/64)");
+    if (g->n_rec < 4 || g->n_rec > g->n_fft) return fail(FFTDG_E_INVALID, "need 4 <= n_rec <= n_fft");
+    if (!(g->h > 0.0) || !is_fin(g->h)) return fail(FFTDG_E_INVALID, "h must be finite and > 0");
+    for (int d = 0; d < 3; ++d)
+        if (!is_fin(g->origin[d])) return fail(FFTDG_E_INVALID, "origin must be finite");
+    if (g->clash_mode == FFTDG_CAP && (!(g->ljr_cap > 0.0) || !is_fin(g->ljr_cap)))
+        return fail(FFTDG_E_INVALID, "ljr_cap must be finite and > 0 in CAP mode");
+    if (g->clash_mode == FFTDG_OCC && (!(g->occ_f > 0.0) || !is_fin(g->occ_f)))
+        return fail(FFTDG_E_INVALID, "occ_f must be finite and > 0 in OCC mode");
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
+        (void)hipGetLastError();
+        return fail(FFTDG_E_DEVICE, "no HIP device");
+    }
+    if (device < 0 || device >= ndev) return fail(FFTDG_E_INVALID, "device index out of range");
+    fftdg_ctx *c = new (std::nothrow) fftdg_ctx();
+    if (!c) return FFTDG_E_NOMEM;
+    c->g = *g;
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->ks = ks;
+    c->n_ch = g->clash_mode == FFTDG_OCC ? 4 : 3;
+    if (hipSetDevice(device) != hipSuccess || hipEventCreateWithFlags(&c->staging_ev, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return fail(FFTDG_E_DEVICE, "hipSetDevice/hipEventCreate failed");
+    }
+    // twiddles w_N^k = exp(-2 pi i k / N), FP64 then rounded once
+    const int N = g->n_fft;
+    std::vector<char> tw((size_t)N * ks->cbytes);
+    for (int k = 0; k < N; ++k) {
+        const double a = 2.0 * M_PI * (double)k / (double)N;
+        const double re = std::cos(a), im = -std::sin(a);
+        if (g->precision == FFTDG_F32) {
+            float *f = (float *)tw.data();
+            f[2 * k] = (float)re;
+            f[2 * k + 1] = (float)im;
+        } else {
+            double *f = (double *)tw.data();
+            f[2 * k] = re;
+            f[2 * k + 1] = im;
+        }
+    }
+    int rc = reserve(c, c->tw, tw.size());
+    if (rc) {
+        fftdg_destroy(c);
+        return rc;
+    }
+    if (hipMemcpy(c->tw.p, tw.data(), tw.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        (void)hipGetLastError();
+        fftdg_destroy(c);
+        return fail(FFTDG_E_DEVICE, "twiddle upload failed");
+    }
+    *out = c;
+    return FFTDG_OK;
+}
+
+void fftdg_destroy(fftdg_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipStreamSynchronize(c->stream);
+    DevBuf *bufs[] = {&c->tw, &c->rspec, &c->rxy, &c->ws_fwd, &c->ws_inv, &c->pp, &c->tables,
+                      &c->red_B, &c->red_res, &c->red_off, &c->red_W};
+    for (DevBuf *b : bufs)
+        if (b->p) (void)hipFree(b->p);
+    if (c->pinned) (void)hipHostFree(c->pinned);
+    if (c->staging_ev) (void)hipEventDestroy(c->staging_ev);
+    delete c;
+}
+
+int fftdg_set_stream(fftdg_ctx *ctx, void *s) {
+    if (!ctx) return FFTDG_E_INVALID;
+    ctx->stream = (hipStream_t)s;
+    return FFTDG_OK;
+}
+
+int fftdg_receptor_grids(fftdg_ctx *ctx, int32_t n_atoms, const double *xyz, const double *q, const double *sg,
+                         const double *ep, void *grids, uint8_t *occ) {
+    if (!ctx) return FFTDG_E_INVALID;
+    if (n_atoms <= 0 || !xyz || !q || !sg || !ep || !grids)
+        return set_err(ctx, FFTDG_E_INVALID, "receptor_grids: bad atom count or NULL pointer");
+    if (ctx->g.clash_mode == FFTDG_OCC && !occ) return set_err(ctx, FFTDG_E_INVALID, "receptor_grids: occ_dev required in OCC mode");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, launch_receptor_grids(ctx->stream, ctx->g.precision, n_atoms, xyz, q, sg, ep, ctx->g.n_rec, ctx->g.h,
+                                      ctx->g.origin, ctx->g.clash_mode == FFTDG_CAP ? 1 : 0, ctx->g.ljr_cap,
+                                      ctx->g.occ_f, grids, ctx->g.clash_mode == FFTDG_OCC ? occ : nullptr));
+    return FFTDG_OK;
+}
+
+int fftdg_set_receptors(fftdg_ctx *ctx, int32_t n_snap, const void *grids, const uint8_t *occ, const double *w) {
+    if (!ctx) return FFTDG_E_INVALID;
+    if (n_snap <= 0 || !grids) return set_err(ctx, FFTDG_E_INVALID, "set_receptors: n_snap must be > 0 and grids non-NULL");
+    const bool is_occ = ctx->g.clash_mode == FFTDG_OCC;
+    if (is_occ && !occ) return set_err(ctx, FFTDG_E_INVALID, "set_receptors: occupancy grids required in OCC mode");
+    std::vector<double> W(n_snap, 1.0);
+    if (w) {
+        double s = 0.0;
+        for (int i = 0; i < n_snap; ++i) {
+            if (!is_fin(w[i]) || w[i] < 0.0) return set_err(ctx, FFTDG_E_INVALID, "set_receptors: weights must be finite and >= 0");
+            s += w[i];
+        }
+        if (!(s > 0.0)) return set_err(ctx, FFTDG_E_INVALID, "set_receptors: weights sum to 0");
+        for (int i = 0; i < n_snap; ++i) W[i] = w[i] / s;
+    } else {
+        for (int i = 0; i < n_snap; ++i) W[i] = 1.0 / n_snap;
+    }
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const fftdg_grid_desc &g = ctx->g;
+    const size_t cb = ctx->ks->cbytes;
+    const size_t per_snap = (size_t)ctx->n_ch * g.n_fft * ctx->ks->np * cb;
+    int rc;
+    if ((rc = reserve(ctx, ctx->rspec, per_snap * n_snap))) return rc;
+    if ((rc = reserve(ctx, ctx->rxy, (size_t)ctx->n_ch * g.n_rec * ctx->ks->np * cb))) return rc;
+    const size_t n3 = (size_t)g.n_rec * g.n_rec * g.n_rec;
+    const size_t tsz = g.precision == FFTDG_F32 ? 4 : 8;
+    for (int s = 0; s < n_snap; ++s) {
+        HIPCHK(ctx, ctx->ks->rec_spectra(ctx->stream, (const char *)grids + s * 3 * n3 * tsz,
+                                         is_occ ? occ + s * n3 : nullptr, g.n_rec, ctx->n_ch, ctx->tw.p, ctx->rxy.p,
+                                         (char *)ctx->rspec.p + s * per_snap));
+    }
+    ctx->n_snap = n_snap;
+    ctx->W = W;
+    return FFTDG_OK;
+}
+
+int fftdg_scan(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, fftdg_partial *out) {
+    if (!ctx) return FFTDG_E_INVALID;
+    if (ctx->n_snap <= 0) return set_err(ctx, FFTDG_E_STATE, "scan before set_receptors");
+    if (!out) return set_err(ctx, FFTDG_E_INVALID, "scan: out_dev is NULL");
+    if (!(T_K > 0.0) || !is_fin(T_K)) return set_err(ctx, FFTDG_E_INVALID, "scan: temperature must be finite and > 0");
+    int rc = validate_batch(ctx, b);
+    if (rc) return rc;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    Plan P;
+    if ((rc = build_plan(ctx, b, false, -1, P))) return rc;
+    return run_plan(ctx, b, P, T_K, out, -1, nullptr, nullptr);
+}
+
+int fftdg_energy_grid(fftdg_ctx *ctx, int32_t snap, const fftdg_batch *b, int32_t cfg, double T_K, void *psi,
+                      uint8_t *clash, int32_t *shape) {
+    if (!ctx) return FFTDG_E_INVALID;
+    int rc = validate_batch(ctx, b);
+    if (rc) return rc;
+    const int ncfg = b->cfg_off[b->n_lig];
+    if (cfg < 0 || cfg >= ncfg) return set_err(ctx, FFTDG_E_INVALID, "energy_grid: configuration index out of range");
+    if (!shape) return set_err(ctx, FFTDG_E_INVALID, "energy_grid: shape_host is NULL");
+    if (!(T_K > 0.0) || !is_fin(T_K)) return set_err(ctx, FFTDG_E_INVALID, "energy_grid: temperature must be > 0");
+    // placement of this configuration only
+    const int l = (int)(std::upper_bound(b->cfg_off, b->cfg_off + b->n_lig + 1, cfg) - b->cfg_off) - 1;
+    fftdg_batch one = *b;
+    (void)l;
+    Plan P;
+    if ((rc = build_plan(ctx, &one, true, cfg, P))) return rc;
+    const CfgDev &d = P.cfg[cfg];
+    shape[0] = d.V[2];
+    shape[1] = d.V[1];
+    shape[2] = d.V[0];
+    if (!psi) return FFTDG_OK;
+    if (ctx->n_snap <= 0) return set_err(ctx, FFTDG_E_STATE, "energy_grid before set_receptors");
+    if (snap < 0 || snap >= ctx->n_snap) return set_err(ctx, FFTDG_E_INVALID, "energy_grid: snapshot out of range");
+    if (d.n_valid <= 0) return FFTDG_OK;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    if ((rc = run_plan(ctx, b, P, T_K, nullptr, snap, psi, clash))) return rc;
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return FFTDG_OK;
+}
+
+int fftdg_place(fftdg_ctx *ctx, const fftdg_batch *b, int32_t cfg, int32_t *U, int32_t *box) {
+    if (!ctx) return FFTDG_E_INVALID;
+    int rc = validate_batch(ctx, b);
+    if (rc) return rc;
+    const int ncfg = b->cfg_off[b->n_lig];
+    if (cfg < 0 || cfg >= ncfg || !U || !box) return set_err(ctx, FFTDG_E_INVALID, "place: bad index or NULL output");
+    const int l = (int)(std::upper_bound(b->cfg_off, b->cfg_off + b->n_lig + 1, cfg) - b->cfg_off) - 1;
+    const int na = b->atom_off[l + 1] - b->atom_off[l];
+    size_t row = 0;
+    for (int k = 0; k < l; ++k) row += (size_t)(b->conf_off[k + 1] - b->conf_off[k]) * (b->atom_off[k + 1] - b->atom_off[k]);
+    const double *X = b->conf_xyz + 3 * (row + (size_t)b->cfg_conf[cfg] * na);
+    int bx[3];
+    if (!place_one(X, na, b->cfg_quat + 4 * cfg, ctx->g.h, U, bx))
+        return set_err(ctx, FFTDG_E_INVALID, "place: zero or non-finite quaternion");
+    for (int d = 0; d < 3; ++d) box[d] = bx[d];
+    return FFTDG_OK;
+}
+
+int fftdg_reduce(fftdg_ctx *ctx, const fftdg_batch *b, const fftdg_partial *p, const double *cfg_w, double T_K,
+                 double *B_host, fftdg_ligand_result *res_host) {
+    if (!ctx) return FFTDG_E_INVALID;
+    if (ctx->n_snap <= 0) return set_err(ctx, FFTDG_E_STATE, "reduce before set_receptors");
+    if (!b || b->n_lig <= 0 || !b->cfg_off) return set_err(ctx, FFTDG_E_INVALID, "reduce: bad batch");
+    if (!p || !B_host || !res_host) return set_err(ctx, FFTDG_E_INVALID, "reduce: NULL pointer");
+    if (!(T_K > 0.0) || !is_fin(T_K)) return set_err(ctx, FFTDG_E_INVALID, "reduce: temperature must be > 0");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const int nl = b->n_lig, ns = ctx->n_snap;
+    int rc;
+    if ((rc = reserve(ctx, ctx->red_off, sizeof(int32_t) * (nl + 1)))) return rc;
+    if ((rc = reserve(ctx, ctx->red_W, sizeof(double) * ns))) return rc;
+    if ((rc = reserve(ctx, ctx->red_B, sizeof(double) * (size_t)nl * ns))) return rc;
+    if ((rc = reserve(ctx, ctx->red_res, sizeof(LigRed) * nl))) return rc;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->red_off.p, b->cfg_off, sizeof(int32_t) * (nl + 1), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->red_W.p, ctx->W.data(), sizeof(double) * ns, hipMemcpyHostToDevice, ctx->stream));
+    const double kT = kR * T_K;
+    const double h3 = ctx->g.h * ctx->g.h * ctx->g.h;
+    HIPCHK(ctx, launch_reduce(ctx->stream, p, b->cfg_off[nl], ns, nl, (const int32_t *)ctx->red_off.p, cfg_w,
+                              (const double *)ctx->red_W.p, kT, h3, kC0, (double *)ctx->red_B.p,
+                              (LigRed *)ctx->red_res.p));
+    std::vector<LigRed> r(nl);
+    HIPCHK(ctx, hipMemcpyAsync(B_host, ctx->red_B.p, sizeof(double) * (size_t)nl * ns, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(r.data(), ctx->red_res.p, sizeof(LigRed) * nl, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (int l = 0; l < nl; ++l) {
+        res_host[l].dG = r[l].dG;
+        res_host[l].v_site = r[l].v_site;
+        res_host[l].psi_min = r[l].psi_min;
+        res_host[l].n_finite = r[l].n_finite;
+        res_host[l].n_samples = r[l].n_samples;
+    }
+    return FFTDG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,995 @@
+// gfx950 kernels of the FFT translational scan.
+//
+// Data path for one ligand configuration (Eqs. 8-9, FFT-based BPMF section):
+//   k_lig_fwd_xy  per (channel, ligand z-plane): spread the atoms' weights
+//                 (trilinear, Eqs. 4-6) or occupancy balls (Eq. 10) of that
+//                 plane straight into registers, R2C FFT along x, C2C FFT
+//                 along y, write the half-plane (HBM).  Only planes that hold
+//                 ligand data are transformed (z-pruned input).
+//   k_zprod       per (tile of z-pencils, configuration): forward FFT along
+//                 z, multiply with the receptor spectra and sum the energy
+//                 channels (Eq. 9), inverse FFT along z, keep only the valid
+//                 z-translations (z-pruned output).
+//   k_inv_xy_lse  per (configuration, valid z-translation): inverse FFT along
+//                 y then C2R along x; clash mask from the occupancy channel;
+//                 max-shifted log-sum-exp, minimum and counts of Eq. 2 over
+//                 the plane's box-valid translations.
+//   k_merge       per configuration: merge its plane partials.
+//   k_reduce      per ligand, FP64: exponential averages over configurations
+//                 (Eq. 2) and snapshots (Eq. 13).
+// Receptor spectra (Eq. 9, FT(G_R)) are built once per snapshot by
+// k_rec_xy + k_rec_z with the same transforms.  k_receptor_grids evaluates
+// Eq. 7 and Eq. 10 from receptor atoms in FP64.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdint.h>
+
+#include "../../include/fftdg.h"
+#include "fft_device.hpp"
+#include "kernels.hpp"
+#include "scan_types.hpp"
+
+namespace fftdg {
+
+constexpr int NT = 256;
+constexpr int MAXA = 256;
+
+template <typename T, int N>
+struct Geo {
+    static constexpr int R1 = Shape<N>::R1, R2 = Shape<N>::R2, M = R2 / R1;
+    static constexpr int H = N / 2 + 1;  // half-spectrum columns
+    static constexpr int S = H + 1;      // LDS row stride (complex elements)
+    static constexpr int NP = N * H;     // complex values per half-plane
+    static constexpr int U = NT / R1;    // FFT units per workgroup
+};
+
+__device__ __forceinline__ int pmod(int a, int n) {
+    int r = a % n;
+    return r < 0 ? r + n : r;
+}
+__device__ __forceinline__ long long floordiv(long long a, long long b) {
+    long long q = a / b;
+    return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
+}
+// largest s >= 0 with s*s < rem (rem >= 1)
+__device__ __forceinline__ long long isqrt_lt(long long rem) {
+    long long s = (long long)sqrt((double)rem);
+    while (s > 0 && s * s >= rem) --s;
+    while ((s + 1) * (s + 1) < rem) ++s;
+    return s;
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void load_tw(typename Cx<T>::t *tw, const typename Cx<T>::t *g) {
+    for (int i = threadIdx.x; i < N; i += NT) tw[i] = g[i];
+}
+
+// ------------------------------------------------------------------ fills
+// A fill produces, for lane n1 of the unit that owns storage rows (r, r+1),
+// the real values at x = n1 + R1*n2 of row r (into re) and row r+1 (into im).
+
+template <typename T>
+struct EAtom {
+    int ax, ay;
+    T fx, fy, w;  // w = gamma_ch * (z weight)
+};
+struct OAtom {
+    long long Ux, Uy, remz;  // remz = thr - (2^16 z - Uz)^2 > 0
+};
+
+template <typename T, int N>
+struct LigEnergyFill {
+    const EAtom<T> *list;
+    int n, y0;
+    __device__ void rows(int r, int n1, T *re, T *im, bool live, bool has_b) const {
+        constexpr int R1 = Shape<N>::R1, R2 = Shape<N>::R2;
+#pragma unroll
+        for (int i = 0; i < R2; ++i) re[i] = im[i] = (T)0;
+        if (!live) return;
+        const int ya = y0 + r, yb = ya + 1;
+        for (int a = 0; a < n; ++a) {
+            const EAtom<T> e = list[a];
+            const T wa = (e.ay == ya) ? (T)1 - e.fy : ((e.ay + 1 == ya) ? e.fy : (T)0);
+            T wb = (e.ay == yb) ? (T)1 - e.fy : ((e.ay + 1 == yb) ? e.fy : (T)0);
+            if (!has_b) wb = (T)0;
+            if (wa == (T)0 && wb == (T)0) continue;
+            const T w0 = e.w * ((T)1 - e.fx), w1 = e.w * e.fx;
+#pragma unroll
+            for (int i = 0; i < R2; ++i) {
+                const int x = n1 + R1 * i;
+                const T cx = (x == e.ax) ? w0 : ((x == e.ax + 1) ? w1 : (T)0);
+                re[i] += wa * cx;
+                im[i] += wb * cx;
+            }
+        }
+    }
+};
+
+template <typename T, int N>
+struct LigOccFill {
+    const OAtom *list;
+    int n, y0;
+    __device__ void rows(int r, int n1, T *re, T *im, bool live, bool has_b) const {
+        constexpr int R1 = Shape<N>::R1, R2 = Shape<N>::R2;
+#pragma unroll
+        for (int i = 0; i < R2; ++i) re[i] = im[i] = (T)0;
+        if (!live) return;
+        for (int a = 0; a < n; ++a) {
+            const OAtom e = list[a];
+#pragma unroll
+            for (int row = 0; row < 2; ++row) {
+                if (row == 1 && !has_b) continue;
+                const long long yt = (long long)(y0 + r + row);
+                const long long dy = yt * 65536LL - e.Uy;
+                const long long rem = e.remz - dy * dy;
+                if (rem <= 0) continue;
+                const long long s = isqrt_lt(rem);
+                const long long xlo = -floordiv(-(e.Ux - s), 65536LL);  // ceil
+                const long long xhi = floordiv(e.Ux + s, 65536LL);
+                const int span = (int)(xhi - xlo);
+                if (span < 0) continue;
+                const int xl = pmod((int)xlo, N);
+#pragma unroll
+                for (int i = 0; i < R2; ++i) {
+                    const int x = n1 + R1 * i;
+                    const int d = pmod(x - xl, N);
+                    if (d <= span) {
+                        if (row == 0) re[i] = (T)1; else im[i] = (T)1;
+                    }
+                }
+            }
+        }
+    }
+};
+
+template <typename T, int N, typename Src>
+struct DenseFill {
+    const Src *plane;  // [n_rec][n_rec] plane of the receptor grid
+    int n_rec;
+    __device__ void rows(int r, int n1, T *re, T *im, bool live, bool has_b) const {
+        constexpr int R1 = Shape<N>::R1, R2 = Shape<N>::R2;
+#pragma unroll
+        for (int i = 0; i < R2; ++i) {
+            const int x = n1 + R1 * i;
+            const bool okx = live && x < n_rec;
+            re[i] = (okx && r < n_rec) ? (T)plane[r * n_rec + x] : (T)0;
+            im[i] = (okx && has_b && r + 1 < n_rec) ? (T)plane[(r + 1) * n_rec + x] : (T)0;
+        }
+    }
+};
+
+// ------------------------------------------------------- xy forward of a plane
+// Rows r = 0..Ly-1 of the plane hold data (true y = y0 + r); every other
+// row is zero.  Writes the 2-D half spectrum [N][H] (ky, kx) to `out`.
+template <typename T, int N, class Fill>
+__device__ void xy_forward(const Fill &fill, int y0, int Ly, typename Cx<T>::t *Pl,
+                           const typename Cx<T>::t *tw, typename Cx<T>::t *out) {
+    using C2 = typename Cx<T>::t;
+    using G = Geo<T, N>;
+    constexpr int R1 = G::R1, R2 = G::R2, M = G::M, S = G::S, H = G::H, U = G::U;
+    const int unit = threadIdx.x / R1, n1 = threadIdx.x % R1;
+    T re[R2], im[R2];
+
+    // Phase A: x transform of row pairs packed as one complex sequence.
+    const int npairs = (Ly + 1) / 2;
+    const int rounds_a = (npairs + U - 1) / U;
+    for (int rd = 0; rd < rounds_a; ++rd) {
+        const int r = 2 * (unit + U * rd);
+        const bool live = r < Ly;
+        fill.rows(r, n1, re, im, live, r + 1 < Ly);
+        C2 *row = Pl + (live ? r * S : 0);
+        fft_unit<T, N, false>(re, im, n1, row, 1, tw, live);
+        __syncthreads();
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < M; ++i)
+#pragma unroll
+                for (int k1 = 0; k1 < R1; ++k1) row[spec_index<N>(n1, i, k1)] = C2{re[i * R1 + k1], im[i * R1 + k1]};
+        }
+        __syncthreads();
+        // unpack Z = A + iB (A, B the spectra of rows r and r+1), k = 0..N/2
+        constexpr int Q = (N / 2) / R1 + 1;
+        C2 A[Q], B[Q];
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int k = n1 + R1 * q;
+            if (live && k <= N / 2) {
+                const C2 zk = row[k], zn = row[(N - k) & (N - 1)];
+                A[q] = C2{(T)0.5 * (zk.x + zn.x), (T)0.5 * (zk.y - zn.y)};
+                B[q] = C2{(T)0.5 * (zk.y + zn.y), (T)-0.5 * (zk.x - zn.x)};
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int k = n1 + R1 * q;
+            if (live && k <= N / 2) {
+                row[k] = A[q];
+                row[S + k] = B[q];
+            }
+        }
+    }
+    __syncthreads();
+
+    // Phase B: y transform of columns; kx = 0 and kx = N/2 (both real
+    // columns) travel together as column 0.
+    constexpr int rounds_b = (N / 2 + U - 1) / U;
+    for (int rd = 0; rd < rounds_b; ++rd) {
+        const int c = unit + U * rd;
+        const bool live = c < N / 2;
+#pragma unroll
+        for (int i = 0; i < R2; ++i) {
+            const int rr = pmod(n1 + R1 * i - y0, N);
+            re[i] = im[i] = (T)0;
+            if (live && rr < Ly) {
+                if (c == 0) {
+                    re[i] = Pl[rr * S].x;
+                    im[i] = Pl[rr * S + N / 2].x;
+                } else {
+                    const C2 v = Pl[rr * S + c];
+                    re[i] = v.x;
+                    im[i] = v.y;
+                }
+            }
+        }
+        C2 *col = Pl + (live ? c : 0);
+        fft_unit<T, N, false>(re, im, n1, col, S, tw, live);
+        __syncthreads();
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < M; ++i)
+#pragma unroll
+                for (int k1 = 0; k1 < R1; ++k1) col[spec_index<N>(n1, i, k1) * S] = C2{re[i * R1 + k1], im[i * R1 + k1]};
+        }
+        __syncthreads();
+        constexpr int QY = N / R1;
+        C2 F0[QY], F1[QY];
+        const bool unpack = live && c == 0;
+#pragma unroll
+        for (int q = 0; q < QY; ++q) {
+            if (unpack) {
+                const int ky = n1 + R1 * q;
+                const C2 x1 = Pl[ky * S], x2 = Pl[((N - ky) & (N - 1)) * S];
+                F0[q] = C2{(T)0.5 * (x1.x + x2.x), (T)0.5 * (x1.y - x2.y)};
+                F1[q] = C2{(T)0.5 * (x1.y + x2.y), (T)-0.5 * (x1.x - x2.x)};
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < QY; ++q) {
+            if (unpack) {
+                const int ky = n1 + R1 * q;
+                Pl[ky * S] = F0[q];
+                Pl[ky * S + N / 2] = F1[q];
+            }
+        }
+    }
+    __syncthreads();
+
+    // Phase C: store [ky][kx] contiguously.
+    for (int e = threadIdx.x; e < G::NP; e += NT) {
+        const int ky = e / H, kx = e - ky * H;
+        out[e] = Pl[ky * S + kx];
+    }
+}
+
+// ------------------------------------------------------------------ kernels
+template <typename T, int N>
+__global__ __launch_bounds__(NT) void k_lig_fwd_xy(const FwdItem *__restrict__ items,
+                                                    const CfgDev *__restrict__ cfgs,
+                                                    const int32_t *__restrict__ ulat,
+                                                    const T *__restrict__ gam,
+                                                    const double *__restrict__ thr,
+                                                    const typename Cx<T>::t *__restrict__ twg,
+                                                    typename Cx<T>::t *__restrict__ ws) {
+    using C2 = typename Cx<T>::t;
+    using G = Geo<T, N>;
+    __shared__ C2 Pl[N * G::S];
+    __shared__ C2 tw[N];
+    __shared__ union {
+        EAtom<T> e[MAXA];
+        OAtom o[MAXA];
+    } L;
+    __shared__ int nl;
+    const FwdItem it = items[blockIdx.x];
+    const CfgDev c = cfgs[it.cfg];
+    load_tw<T, N>(tw, twg);
+    const bool occ = it.ch == 3;
+    const int zt = (occ ? c.zo0 : c.ze0) + it.p;
+    const int y0 = occ ? c.yo0 : c.ye0;
+    const int Ly = occ ? c.Lyo : c.Lye;
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        int base = 0;
+        for (int a0 = 0; a0 < c.n_atoms; a0 += 64) {
+            const int a = a0 + lane;
+            bool take = false;
+            EAtom<T> ea{};
+            OAtom oa{};
+            if (a < c.n_atoms) {
+                const int32_t *U = ulat + 3 * (c.u_base + a);
+                if (!occ) {
+                    const int az = U[2] >> 16;
+                    const T fz = (T)(U[2] & 0xffff) * (T)(1.0 / 65536.0);
+                    take = (az == zt) || (az + 1 == zt);
+                    const T wz = (az == zt) ? (T)1 - fz : fz;
+                    ea.ax = U[0] >> 16;
+                    ea.ay = U[1] >> 16;
+                    ea.fx = (T)(U[0] & 0xffff) * (T)(1.0 / 65536.0);
+                    ea.fy = (T)(U[1] & 0xffff) * (T)(1.0 / 65536.0);
+                    ea.w = gam[3 * (c.atom_base + a) + it.ch] * wz;
+                } else {
+                    const long long dz = (long long)zt * 65536LL - U[2];
+                    const long long remz = (long long)thr[c.atom_base + a] - dz * dz;
+                    take = remz > 0;
+                    oa.Ux = U[0];
+                    oa.Uy = U[1];
+                    oa.remz = remz;
+                }
+            }
+            const unsigned long long m = __ballot(take);
+            const int pos = base + __popcll(m & ((1ULL << lane) - 1ULL));
+            if (take) {
+                if (!occ) L.e[pos] = ea; else L.o[pos] = oa;
+            }
+            base += __popcll(m);
+        }
+        if (lane == 0) nl = base;
+    }
+    __syncthreads();
+    const int64_t slot = occ ? (int64_t)3 * c.Le + it.p : (int64_t)it.ch * c.Le + it.p;
+    C2 *out = ws + c.off_fwd + slot * G::NP;
+    if (occ) {
+        LigOccFill<T, N> f{L.o, nl, y0};
+        xy_forward<T, N>(f, y0, Ly, Pl, tw, out);
+    } else {
+        LigEnergyFill<T, N> f{L.e, nl, y0};
+        xy_forward<T, N>(f, y0, Ly, Pl, tw, out);
+    }
+}
+
+// Receptor xy pass: block b -> (channel, z) over n_ch * n_rec planes.
+template <typename T, int N>
+__global__ __launch_bounds__(NT) void k_rec_xy(const T *__restrict__ grids, const uint8_t *__restrict__ occ,
+                                                int n_rec, const typename Cx<T>::t *__restrict__ twg,
+                                                typename Cx<T>::t *__restrict__ rxy) {
+    using C2 = typename Cx<T>::t;
+    using G = Geo<T, N>;
+    __shared__ C2 Pl[N * G::S];
+    __shared__ C2 tw[N];
+    load_tw<T, N>(tw, twg);
+    __syncthreads();
+    const int ch = blockIdx.x / n_rec, z = blockIdx.x % n_rec;
+    const int64_t n2 = (int64_t)n_rec * n_rec;
+    C2 *out = rxy + ((int64_t)ch * n_rec + z) * G::NP;
+    if (ch < 3) {
+        DenseFill<T, N, T> f{grids + (int64_t)ch * n2 * n_rec + z * n2, n_rec};
+        xy_forward<T, N>(f, 0, n_rec, Pl, tw, out);
+    } else {
+        DenseFill<T, N, uint8_t> f{occ + z * n2, n_rec};
+        xy_forward<T, N>(f, 0, n_rec, Pl, tw, out);
+    }
+}
+
+// Receptor z pass: block b -> (channel, tile of pencils); all N outputs kept.
+template <typename T, int N>
+__global__ __launch_bounds__(NT) void k_rec_z(const typename Cx<T>::t *__restrict__ rxy, int n_rec, int n_tiles,
+                                               const typename Cx<T>::t *__restrict__ twg,
+                                               typename Cx<T>::t *__restrict__ rspec) {
+    using C2 = typename Cx<T>::t;
+    using G = Geo<T, N>;
+    constexpr int R1 = G::R1, R2 = G::R2, M = G::M, P = G::U;
+    __shared__ C2 buf[N * P];
+    __shared__ C2 tw[N];
+    load_tw<T, N>(tw, twg);
+    const int ch = blockIdx.x / n_tiles, tile = blockIdx.x % n_tiles;
+    const int n1 = threadIdx.x / P, p = threadIdx.x % P;
+    const int pen = tile * P + p;
+    const bool ok = pen < G::NP;
+    T re[R2], im[R2];
+#pragma unroll
+    for (int i = 0; i < R2; ++i) {
+        const int z = n1 + R1 * i;
+        re[i] = im[i] = (T)0;
+        if (ok && z < n_rec) {
+            const C2 v = rxy[((int64_t)ch * n_rec + z) * G::NP + pen];
+            re[i] = v.x;
+            im[i] = v.y;
+        }
+    }
+    fft_unit<T, N, false>(re, im, n1, buf + p, P, tw, true);
+    if (ok) {
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) {
+                const int k = spec_index<N>(n1, i, k1);
+                rspec[((int64_t)ch * N + k) * G::NP + pen] = C2{re[i * R1 + k1], im[i * R1 + k1]};
+            }
+    }
+}
+
+// z pass of the scan.  Block -> (tile, configuration) with an XCD-aware
+// order: blocks land on the 8 XCDs round-robin, so block b is given the
+// logical index (b % 8) * (nb / 8) + b / 8 and each XCD sweeps a contiguous
+// range of tiles, all configurations of a tile back to back, keeping its
+// share of the receptor spectra in its own L2.
+template <typename T, int N, bool OCC>
+__global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, const int32_t *__restrict__ zcfg,
+                                               int nz, int n_tiles, const typename Cx<T>::t *__restrict__ ws,
+                                               const typename Cx<T>::t *__restrict__ rspec,
+                                               const typename Cx<T>::t *__restrict__ twg,
+                                               typename Cx<T>::t *__restrict__ wsi) {
+    using C2 = typename Cx<T>::t;
+    using G = Geo<T, N>;
+    constexpr int R1 = G::R1, R2 = G::R2, M = G::M, P = G::U, NP = G::NP;
+    constexpr int NIN = OCC ? 4 : 3;
+    __shared__ C2 buf[N * P];
+    __shared__ C2 tw[N];
+    const int nb = gridDim.x, b = blockIdx.x;
+    const int L = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
+    if (L >= n_tiles * nz) return;
+    const int tile = L / nz, zi = L % nz;
+    const CfgDev c = cfgs[zcfg[zi]];
+    load_tw<T, N>(tw, twg);
+    const int n1 = threadIdx.x / P, p = threadIdx.x % P;
+    const int pen = tile * P + p;
+    const bool ok = pen < NP;
+    T er[R2], ei[R2], orr[R2], oi[R2];
+#pragma unroll
+    for (int i = 0; i < R2; ++i) er[i] = ei[i] = orr[i] = oi[i] = (T)0;
+#pragma unroll
+    for (int ch = 0; ch < NIN; ++ch) {
+        const bool occ = ch == 3;
+        const int zs = occ ? c.zo0 : c.ze0, Lz = occ ? c.Lo : c.Le;
+        const C2 *src = ws + c.off_fwd + (int64_t)(occ ? 3 * c.Le : ch * c.Le) * NP + pen;
+        T re[R2], im[R2];
+#pragma unroll
+        for (int i = 0; i < R2; ++i) {
+            const int s = pmod(n1 + R1 * i - zs, N);
+            re[i] = im[i] = (T)0;
+            if (ok && s < Lz) {
+                const C2 v = src[(int64_t)s * NP];
+                re[i] = v.x;
+                im[i] = v.y;
+            }
+        }
+        fft_unit<T, N, false>(re, im, n1, buf + p, P, tw, true);
+        const C2 *R = rspec + (int64_t)ch * N * NP + pen;
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) {
+                const int k = spec_index<N>(n1, i, k1);
+                const C2 r = ok ? R[(int64_t)k * NP] : C2{(T)0, (T)0};
+                const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
+                // R * conj(L)
+                const T pr = r.x * lr + r.y * li;
+                const T pi = r.y * lr - r.x * li;
+                if (occ) {
+                    orr[i * R1 + k1] += pr;
+                    oi[i * R1 + k1] += pi;
+                } else {
+                    er[i * R1 + k1] += pr;
+                    ei[i * R1 + k1] += pi;
+                }
+            }
+    }
+    const int Vz = c.V[2];
+    fft_unit_rev<T, N, true>(er, ei, n1, buf + p, P, tw, true);
+    C2 *dst = wsi + c.off_inv + pen;
+#pragma unroll
+    for (int i = 0; i < R2; ++i) {
+        const int tz = n1 + R1 * i;
+        if (ok && tz < Vz) dst[(int64_t)tz * NP] = C2{er[i], ei[i]};
+    }
+    if (OCC) {
+        fft_unit_rev<T, N, true>(orr, oi, n1, buf + p, P, tw, true);
+        dst += (int64_t)Vz * NP;
+#pragma unroll
+        for (int i = 0; i < R2; ++i) {
+            const int tz = n1 + R1 * i;
+            if (ok && tz < Vz) dst[(int64_t)tz * NP] = C2{orr[i], oi[i]};
+        }
+    }
+}
+
+template <typename T>
+struct LseAcc {
+    T m, s, pmin;
+    int n, amin;
+    __device__ void init() {
+        m = -(T)INFINITY;
+        s = (T)0;
+        pmin = (T)INFINITY;
+        n = 0;
+        amin = -1;
+    }
+    __device__ void add(T x, T psi, int lin) {
+        if (x > m) {
+            s = s * exp(m - x) + (T)1;
+            m = x;
+        } else {
+            s += exp(x - m);
+        }
+        if (psi < pmin || (psi == pmin && lin < amin)) {
+            pmin = psi;
+            amin = lin;
+        }
+        ++n;
+    }
+    __device__ void merge(const LseAcc &o) {
+        if (o.n == 0) return;
+        if (n == 0) {
+            *this = o;
+            return;
+        }
+        const T mm = m > o.m ? m : o.m;
+        s = s * exp(m - mm) + o.s * exp(o.m - mm);
+        m = mm;
+        if (o.pmin < pmin || (o.pmin == pmin && o.amin < amin)) {
+            pmin = o.pmin;
+            amin = o.amin;
+        }
+        n += o.n;
+    }
+};
+
+// Inverse xy + clash mask + Eq. 2 partials for one valid z-translation.
+template <typename T, int N, bool OCC>
+__global__ __launch_bounds__(NT) void k_inv_xy_lse(const InvItem *__restrict__ items, const CfgDev *__restrict__ cfgs,
+                                                    const typename Cx<T>::t *__restrict__ wsi, T beta, T inv_n3,
+                                                    const typename Cx<T>::t *__restrict__ twg,
+                                                    PlanePartial<T> *__restrict__ pp, T *__restrict__ psi_out,
+                                                    uint8_t *__restrict__ clash_out) {
+    using C2 = typename Cx<T>::t;
+    using G = Geo<T, N>;
+    constexpr int R1 = G::R1, R2 = G::R2, M = G::M, S = G::S, U = G::U, NP = G::NP;
+    __shared__ C2 Pl[N * S];
+    __shared__ C2 tw[N];
+    __shared__ uint32_t cmask[(N * N + 31) / 32];
+    __shared__ LseAcc<T> red[NT];
+    const InvItem it = items[blockIdx.x];
+    const CfgDev c = cfgs[it.cfg];
+    const int Vx = c.V[0], Vy = c.V[1], Vz = c.V[2], tz = it.tz;
+    load_tw<T, N>(tw, twg);
+    for (int i = threadIdx.x; i < (N * N + 31) / 32; i += NT) cmask[i] = 0u;
+    const int unit = threadIdx.x / R1, n1 = threadIdx.x % R1;
+    LseAcc<T> acc;
+    acc.init();
+    constexpr int NCH = OCC ? 2 : 1;
+    for (int pass = 0; pass < NCH; ++pass) {
+        const int och = OCC ? 1 - pass : 0;  // occupancy first
+        const C2 *src = wsi + c.off_inv + ((int64_t)och * Vz + tz) * NP;
+        __syncthreads();
+        for (int e = threadIdx.x; e < NP; e += NT) {
+            const int ky = e / G::H, kx = e - ky * G::H;
+            Pl[ky * S + kx] = src[e];
+        }
+        __syncthreads();
+        T re[R2], im[R2];
+        // inverse y on columns (kx = 0 and N/2 packed into column 0), keep y < Vy
+        constexpr int rounds_b = (N / 2 + U - 1) / U;
+        for (int rd = 0; rd < rounds_b; ++rd) {
+            const int col = unit + U * rd;
+            const bool live = col < N / 2;
+#pragma unroll
+            for (int i = 0; i < R2; ++i) {
+                const int ky = n1 + R1 * i;
+                re[i] = im[i] = (T)0;
+                if (live) {
+                    if (col == 0) {
+                        const C2 a = Pl[ky * S], bq = Pl[ky * S + N / 2];
+                        re[i] = a.x - bq.y;
+                        im[i] = a.y + bq.x;
+                    } else {
+                        const C2 v = Pl[ky * S + col];
+                        re[i] = v.x;
+                        im[i] = v.y;
+                    }
+                }
+            }
+            C2 *cp = Pl + (live ? col : 0);
+            fft_unit<T, N, true>(re, im, n1, cp, S, tw, live);
+            __syncthreads();
+            if (live) {
+#pragma unroll
+                for (int i = 0; i < M; ++i)
+#pragma unroll
+                    for (int k1 = 0; k1 < R1; ++k1) {
+                        const int y = spec_index<N>(n1, i, k1);
+                        if (y < Vy) {
+                            if (col == 0) {
+                                Pl[y * S] = C2{re[i * R1 + k1], (T)0};
+                                Pl[y * S + N / 2] = C2{im[i * R1 + k1], (T)0};
+                            } else {
+                                Pl[y * S + col] = C2{re[i * R1 + k1], im[i * R1 + k1]};
+                            }
+                        }
+                    }
+            }
+        }
+        __syncthreads();
+        // inverse x (C2R) of row pairs (y, y+1), y < Vy
+        const int npairs = (Vy + 1) / 2;
+        const int rounds_a = (npairs + U - 1) / U;
+        for (int rd = 0; rd < rounds_a; ++rd) {
+            const int y = 2 * (unit + U * rd);
+            const bool live = y < Vy;
+            C2 *row = Pl + (live ? y * S : 0);
+#pragma unroll
+            for (int i = 0; i < R2; ++i) {
+                const int k = n1 + R1 * i;
+                re[i] = im[i] = (T)0;
+                if (live) {
+                    C2 a, bq;
+                    if (k <= N / 2) {
+                        a = row[k];
+                        bq = row[S + k];
+                        if (k == 0 || k == N / 2) {
+                            a.y = (T)0;
+                            bq.y = (T)0;
+                        }
+                    } else {
+                        a = row[N - k];
+                        bq = row[S + N - k];
+                        a.y = -a.y;
+                        bq.y = -bq.y;
+                    }
+                    re[i] = a.x - bq.y;
+                    im[i] = a.y + bq.x;
+                }
+            }
+            fft_unit<T, N, true>(re, im, n1, row, 1, tw, live);
+            if (live) {
+#pragma unroll
+                for (int i = 0; i < M; ++i)
+#pragma unroll
+                    for (int k1 = 0; k1 < R1; ++k1) {
+                        const int x = spec_index<N>(n1, i, k1);
+                        if (x >= Vx) continue;
+#pragma unroll
+                        for (int h = 0; h < 2; ++h) {
+                            const int yy = y + h;
+                            if (yy >= Vy) continue;
+                            const T v = (h ? im[i * R1 + k1] : re[i * R1 + k1]) * inv_n3;
+                            const int bit = yy * Vx + x;
+                            if (OCC && och == 1) {
+                                if (v >= (T)0.5) atomicOr(&cmask[bit >> 5], 1u << (bit & 31));
+                            } else {
+                                const int lin = (tz * Vy + yy) * Vx + x;
+                                const bool cl = OCC ? ((cmask[bit >> 5] >> (bit & 31)) & 1u) : false;
+                                if (psi_out) psi_out[lin] = v;
+                                if (clash_out) clash_out[lin] = cl ? 1 : 0;
+                                if (!cl) acc.add(-beta * v, v, lin);
+                            }
+                        }
+                    }
+            }
+        }
+    }
+    // workgroup reduction in a fixed tree
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            LseAcc<T> a = red[threadIdx.x];
+            a.merge(red[threadIdx.x + w]);
+            red[threadIdx.x] = a;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const LseAcc<T> a = red[0];
+        PlanePartial<T> o;
+        o.m = a.m;
+        o.s = a.s;
+        o.psi_min = a.pmin;
+        o.n_finite = a.n;
+        o.argmin = a.amin;
+        pp[c.pp_base + tz] = o;
+    }
+}
+
+// Per configuration: merge its plane partials (fixed order, working precision).
+template <typename T>
+__global__ void k_merge(const CfgDev *__restrict__ cfgs, int n_cfg, const PlanePartial<T> *__restrict__ pp,
+                        fftdg_partial *__restrict__ out) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_cfg) return;
+    const CfgDev c = cfgs[i];
+    LseAcc<T> a;
+    a.init();
+    if (c.scanned) {
+        for (int tz = 0; tz < c.V[2]; ++tz) {
+            const PlanePartial<T> p = pp[c.pp_base + tz];
+            LseAcc<T> b;
+            b.m = p.m;
+            b.s = p.s;
+            b.pmin = p.psi_min;
+            b.n = p.n_finite;
+            b.amin = p.argmin;
+            a.merge(b);
+        }
+    }
+    fftdg_partial o;
+    o.m = (double)a.m;
+    o.s = (double)a.s;
+    o.psi_min = (double)a.pmin;
+    o.n_valid = c.n_valid;
+    o.n_finite = a.n;
+    o.argmin = a.amin;
+    o.scanned = c.scanned;
+    out[c.global_cfg] = o;
+}
+
+// FP64 exponential averages per ligand (one workgroup per ligand).
+__global__ __launch_bounds__(NT) void k_reduce(const fftdg_partial *__restrict__ p, int64_t n_cfg_total,
+                                                int n_snap, const int32_t *__restrict__ cfg_off,
+                                                const double *__restrict__ cfg_w, const double *__restrict__ W,
+                                                double kT, double h3, double c0, double *__restrict__ B,
+                                                LigRed *__restrict__ res) {
+    __shared__ double sd[NT];
+    __shared__ long long sl[NT];
+    __shared__ long long sf[NT];
+    const int lig = blockIdx.x;
+    const int c0i = cfg_off[lig], c1i = cfg_off[lig + 1];
+    const int t = threadIdx.x;
+    double pmin_all = INFINITY;
+    long long nfin_all = 0, nsamp = 0;
+    double gmax = -INFINITY;
+    double Bs_local[1];
+    (void)Bs_local;
+    for (int s = 0; s < n_snap; ++s) {
+        const fftdg_partial *ps = p + (int64_t)s * n_cfg_total;
+        double mx = -INFINITY;
+        long long nv = 0, nf = 0;
+        for (int c = c0i + t; c < c1i; c += NT) {
+            const fftdg_partial q = ps[c];
+            nv += q.n_valid;
+            nf += q.n_finite;
+            if (q.psi_min < pmin_all) pmin_all = q.psi_min;
+            const double w = cfg_w ? cfg_w[c] : 1.0;
+            if (q.n_finite > 0 && w > 0.0) {
+                const double x = log(w) + q.m + log(q.s);
+                if (x > mx) mx = x;
+            }
+        }
+        sd[t] = mx;
+        sl[t] = nv;
+        sf[t] = nf;
+        __syncthreads();
+        for (int w = NT / 2; w > 0; w >>= 1) {
+            if (t < w) {
+                sd[t] = sd[t] > sd[t + w] ? sd[t] : sd[t + w];
+                sl[t] += sl[t + w];
+                sf[t] += sf[t + w];
+            }
+            __syncthreads();
+        }
+        const double M = sd[0];
+        const long long NV = sl[0], NF = sf[0];
+        __syncthreads();
+        double sum = 0.0;
+        if (M > -INFINITY) {
+            for (int c = c0i + t; c < c1i; c += NT) {
+                const fftdg_partial q = ps[c];
+                const double w = cfg_w ? cfg_w[c] : 1.0;
+                if (q.n_finite > 0 && w > 0.0) sum += exp(log(w) + q.m + log(q.s) - M);
+            }
+        }
+        sd[t] = sum;
+        __syncthreads();
+        for (int w = NT / 2; w > 0; w >>= 1) {
+            if (t < w) sd[t] += sd[t + w];
+            __syncthreads();
+        }
+        if (t == 0) {
+            double Bs = INFINITY;
+            if (M > -INFINITY && NV > 0) Bs = -kT * (M + log(sd[0]) - log((double)NV));
+            B[(int64_t)lig * n_snap + s] = Bs;
+            nfin_all += NF;
+            nsamp = NV;
+        }
+        __syncthreads();
+    }
+    // psi_min over threads
+    sd[t] = pmin_all;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (t < w) sd[t] = sd[t] < sd[t + w] ? sd[t] : sd[t + w];
+        __syncthreads();
+    }
+    if (t == 0) {
+        const double pm = sd[0];
+        // Eq. 13 over snapshots (sequential, n_snap is small)
+        for (int s = 0; s < n_snap; ++s) {
+            const double Bs = B[(int64_t)lig * n_snap + s];
+            if (W[s] > 0.0 && Bs < INFINITY) {
+                const double x = log(W[s]) - Bs / kT;
+                if (x > gmax) gmax = x;
+            }
+        }
+        double sum = 0.0;
+        if (gmax > -INFINITY)
+            for (int s = 0; s < n_snap; ++s) {
+                const double Bs = B[(int64_t)lig * n_snap + s];
+                if (W[s] > 0.0 && Bs < INFINITY) sum += exp(log(W[s]) - Bs / kT - gmax);
+            }
+        const int ncfg = c1i - c0i;
+        const double vs = ncfg > 0 ? h3 * (double)nsamp / (double)ncfg : 0.0;
+        LigRed r;
+        r.v_site = vs;
+        r.dG = (gmax > -INFINITY && vs > 0.0) ? -kT * (gmax + log(sum)) - kT * log(vs * c0) : INFINITY;
+        r.psi_min = pm;
+        r.n_finite = nfin_all;
+        r.n_samples = nsamp;
+        res[lig] = r;
+    }
+}
+
+// Eq. 7 receptor grids and Eq. 10 occupancy from atoms, FP64, one thread per
+// grid point, atoms staged through LDS in order.
+#pragma clang fp contract(off)
+template <typename T>
+__global__ __launch_bounds__(NT) void k_receptor_grids(int n_atoms, const double *__restrict__ xyz,
+                                                        const double *__restrict__ q, const double *__restrict__ sg,
+                                                        const double *__restrict__ ep, int n_rec, double h, double ox,
+                                                        double oy, double oz, int mode, double cap, double occ_f,
+                                                        T *__restrict__ grids, uint8_t *__restrict__ occ) {
+    __shared__ double ax[NT], ay[NT], az[NT], aq[NT], as[NT], ae[NT];
+    const long long n3 = (long long)n_rec * n_rec * n_rec;
+    const long long idx = (long long)blockIdx.x * NT + threadIdx.x;
+    const bool ok = idx < n3;
+    const int x = ok ? (int)(idx % n_rec) : 0;
+    const int y = ok ? (int)((idx / n_rec) % n_rec) : 0;
+    const int z = ok ? (int)(idx / ((long long)n_rec * n_rec)) : 0;
+    const double px = ox + h * x, py = oy + h * y, pz = oz + h * z;
+    const double k6 = pow(2.0, -1.0 / 6.0);
+    double ele = 0.0, ljr = 0.0, lja = 0.0;
+    int hit = 0;
+    for (int a0 = 0; a0 < n_atoms; a0 += NT) {
+        __syncthreads();
+        const int a = a0 + threadIdx.x;
+        if (a < n_atoms) {
+            ax[threadIdx.x] = xyz[3 * a];
+            ay[threadIdx.x] = xyz[3 * a + 1];
+            az[threadIdx.x] = xyz[3 * a + 2];
+            aq[threadIdx.x] = q[a];
+            as[threadIdx.x] = sg[a];
+            ae[threadIdx.x] = ep[a];
+        }
+        __syncthreads();
+        const int na = min(NT, n_atoms - a0);
+        for (int j = 0; j < na; ++j) {
+            const double dx = ax[j] - px, dy = ay[j] - py, dz = az[j] - pz;
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            const double rex = k6 * as[j];
+            if (r < occ_f * rex) hit = 1;
+            const double s3 = as[j] * as[j] * as[j];
+            const double se = sqrt(ae[j]);
+            const double r6 = r * r * r * r * r * r;
+            if (r >= rex) {
+                ele += 332.05 * aq[j] / r;
+                lja += se * s3 / r6;
+                ljr += se * s3 * s3 / (r6 * r6);
+            } else if (mode == 1) {
+                ljr += se * s3 * s3 / (r6 * r6);
+            }
+        }
+    }
+    if (!ok) return;
+    if (mode == 1 && ljr > cap) ljr = cap;
+    grids[idx] = (T)ele;
+    grids[n3 + idx] = (T)ljr;
+    grids[2 * n3 + idx] = (T)lja;
+    if (occ) occ[idx] = (uint8_t)hit;
+}
+#pragma clang fp contract(on)
+
+// ------------------------------------------------------------------ launchers
+template <typename T, int N>
+struct Launch {
+    using C2 = typename Cx<T>::t;
+    using G = Geo<T, N>;
+    static hipError_t rec_spectra(hipStream_t st, const void *grids, const uint8_t *occ, int n_rec, int n_ch,
+                                  const void *tw, void *rxy, void *rspec) {
+        hipLaunchKernelGGL((k_rec_xy<T, N>), dim3(n_ch * n_rec), dim3(NT), 0, st, (const T *)grids, occ, n_rec,
+                           (const C2 *)tw, (C2 *)rxy);
+        const int n_tiles = (G::NP + G::U - 1) / G::U;
+        hipLaunchKernelGGL((k_rec_z<T, N>), dim3(n_ch * n_tiles), dim3(NT), 0, st, (const C2 *)rxy, n_rec, n_tiles,
+                           (const C2 *)tw, (C2 *)rspec);
+        return hipGetLastError();
+    }
+    static hipError_t fwd(hipStream_t st, const FwdItem *items, int n_items, const CfgDev *cfgs, const int32_t *ulat,
+                          const void *gam, const double *thr, const void *tw, void *ws) {
+        if (n_items <= 0) return hipSuccess;
+        hipLaunchKernelGGL((k_lig_fwd_xy<T, N>), dim3(n_items), dim3(NT), 0, st, items, cfgs, ulat, (const T *)gam,
+                           thr, (const C2 *)tw, (C2 *)ws);
+        return hipGetLastError();
+    }
+    static hipError_t zprod(hipStream_t st, bool occ, const CfgDev *cfgs, const int32_t *zcfg, int nz,
+                            const void *ws, const void *rspec, const void *tw, void *wsi) {
+        if (nz <= 0) return hipSuccess;
+        const int n_tiles = (G::NP + G::U - 1) / G::U;
+        long long nb = (long long)n_tiles * nz;
+        nb = (nb + 7) / 8 * 8;
+        if (occ)
+            hipLaunchKernelGGL((k_zprod<T, N, true>), dim3((unsigned)nb), dim3(NT), 0, st, cfgs, zcfg, nz, n_tiles,
+                               (const C2 *)ws, (const C2 *)rspec, (const C2 *)tw, (C2 *)wsi);
+        else
+            hipLaunchKernelGGL((k_zprod<T, N, false>), dim3((unsigned)nb), dim3(NT), 0, st, cfgs, zcfg, nz, n_tiles,
+                               (const C2 *)ws, (const C2 *)rspec, (const C2 *)tw, (C2 *)wsi);
+        return hipGetLastError();
+    }
+    static hipError_t inv(hipStream_t st, bool occ, const InvItem *items, int n_items, const CfgDev *cfgs,
+                          const void *wsi, double beta, const void *tw, void *pp, void *psi_out, uint8_t *clash_out) {
+        if (n_items <= 0) return hipSuccess;
+        const T b = (T)beta, s = (T)(1.0 / ((double)N * N * N));
+        if (occ)
+            hipLaunchKernelGGL((k_inv_xy_lse<T, N, true>), dim3(n_items), dim3(NT), 0, st, items, cfgs,
+                               (const C2 *)wsi, b, s, (const C2 *)tw, (PlanePartial<T> *)pp, (T *)psi_out, clash_out);
+        else
+            hipLaunchKernelGGL((k_inv_xy_lse<T, N, false>), dim3(n_items), dim3(NT), 0, st, items, cfgs,
+                               (const C2 *)wsi, b, s, (const C2 *)tw, (PlanePartial<T> *)pp, (T *)psi_out, clash_out);
+        return hipGetLastError();
+    }
+    static hipError_t merge(hipStream_t st, const CfgDev *cfgs, int n_cfg, const void *pp, fftdg_partial *out) {
+        if (n_cfg <= 0) return hipSuccess;
+        hipLaunchKernelGGL((k_merge<T>), dim3((n_cfg + 127) / 128), dim3(128), 0, st, cfgs, n_cfg,
+                           (const PlanePartial<T> *)pp, out);
+        return hipGetLastError();
+    }
+};
+
+template <typename T, int N>
+static const KernelSet *make_set() {
+    static const KernelSet s = {
+        N,
+        (int)sizeof(typename Cx<T>::t),
+        (int)sizeof(PlanePartial<T>),
+        Geo<T, N>::NP,
+        Launch<T, N>::rec_spectra,
+        Launch<T, N>::fwd,
+        Launch<T, N>::zprod,
+        Launch<T, N>::inv,
+        Launch<T, N>::merge,
+    };
+    return &s;
+}
+
+const KernelSet *kernel_set(int precision, int n_fft) {
+    if (precision == FFTDG_F32) {
+        if (n_fft == 32) return make_set<float, 32>();
+        if (n_fft == 64) return make_set<float, 64>();
+        if (n_fft == 128) return make_set<float, 128>();
+    } else if (precision == FFTDG_F64) {
+        if (n_fft == 32) return make_set<double, 32>();
+        if (n_fft == 64) return make_set<double, 64>();
+    }
+    return nullptr;
+}
+
+hipError_t launch_reduce(hipStream_t st, const fftdg_partial *p, int64_t n_cfg_total, int n_snap, int n_lig,
+                         const int32_t *cfg_off, const double *cfg_w, const double *W, double kT, double h3,
+                         double c0, double *B, LigRed *res) {
+    hipLaunchKernelGGL(k_reduce, dim3(n_lig), dim3(NT), 0, st, p, n_cfg_total, n_snap, cfg_off, cfg_w, W, kT, h3,
+                       c0, B, res);
+    return hipGetLastError();
+}
+
+hipError_t launch_receptor_grids(hipStream_t st, int precision, int n_atoms, const double *xyz, const double *q,
+                                 const double *sg, const double *ep, int n_rec, double h, const double *origin,
+                                 int mode, double cap, double occ_f, void *grids, uint8_t *occ) {
+    const long long n3 = (long long)n_rec * n_rec * n_rec;
+    const unsigned nb = (unsigned)((n3 + NT - 1) / NT);
+    if (precision == FFTDG_F32)
+        hipLaunchKernelGGL(k_receptor_grids<float>, dim3(nb), dim3(NT), 0, st, n_atoms, xyz, q, sg, ep, n_rec, h,
+                           origin[0], origin[1], origin[2], mode, cap, occ_f, (float *)grids, occ);
+    else
+        hipLaunchKernelGGL(k_receptor_grids<double>, dim3(nb), dim3(NT), 0, st, n_atoms, xyz, q, sg, ep, n_rec, h,
+                           origin[0], origin[1], origin[2], mode, cap, occ_f, (double *)grids, occ);
+    return hipGetLastError();
+}
+
+}  // namespace fftdg

@@ -1,0 +1,94 @@
+"""The C-ABI library loads, exports every declared symbol and rejects bad
+arguments on the host (no compute call, no GPU needed)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import paper_1708_07045_amd as fd
+from paper_1708_07045_amd._lib import GridDesc
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "fftdg.h")
+
+
+def _declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(fftdg_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = fd.load()
+    names = _declared()
+    assert len(names) >= 12
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(fd.EXPORTS) <= set(names)
+
+
+def test_version_and_status_strings():
+    L = fd.load()
+    assert L.fftdg_version() == 10000
+    for code in (0, -1, -2, -3, -4, -5):
+        assert L.fftdg_status_string(code)
+    assert L.fftdg_status_string(-99) == b"unknown status"
+
+
+def _desc(**kw):
+    d = dict(n_rec=96, n_fft=128, h=0.25, origin=(0.0, 0.0, 0.0), precision=fd.F32, clash_mode=fd.OCC,
+             ljr_cap=10.0, occ_f=0.5)
+    d.update(kw)
+    return GridDesc(d["n_rec"], d["n_fft"], d["h"], (ctypes.c_double * 3)(*d["origin"]), d["precision"],
+                    d["clash_mode"], d["ljr_cap"], d["occ_f"])
+
+
+@pytest.mark.parametrize("kw", [
+    dict(n_fft=96),                      # unsupported FFT edge
+    dict(n_fft=256),                     # 256 is not built
+    dict(precision=fd.F64, n_fft=128),   # FP64 limited to 32/64
+    dict(n_rec=200),                     # n_rec > n_fft
+    dict(n_rec=2),
+    dict(h=0.0),
+    dict(h=float("nan")),
+    dict(origin=(0.0, float("inf"), 0.0)),
+    dict(precision=7),
+    dict(clash_mode=9),
+    dict(clash_mode=fd.CAP, ljr_cap=-1.0),
+    dict(occ_f=0.0),
+])
+def test_create_rejects_bad_descriptions(kw):
+    L = fd.load()
+    h = ctypes.c_void_p()
+    g = _desc(**kw)
+    assert L.fftdg_create(ctypes.byref(h), ctypes.byref(g), 0, None) == fd._lib.E_INVALID
+    assert not h.value
+
+
+def test_create_null_arguments():
+    L = fd.load()
+    h = ctypes.c_void_p()
+    assert L.fftdg_create(None, ctypes.byref(_desc()), 0, None) == fd._lib.E_INVALID
+    assert L.fftdg_create(ctypes.byref(h), None, 0, None) == fd._lib.E_INVALID
+
+
+def test_create_without_device_reports_device_error():
+    try:
+        import torch
+        if torch.cuda.is_available():
+            pytest.skip("a GPU is present")
+    except ImportError:
+        pass
+    L = fd.load()
+    h = ctypes.c_void_p()
+    assert L.fftdg_create(ctypes.byref(h), ctypes.byref(_desc()), 0, None) == fd._lib.E_DEVICE
+
+
+def test_calls_with_null_context():
+    L = fd.load()
+    assert L.fftdg_scan(None, None, 300.0, None) == fd._lib.E_INVALID
+    assert L.fftdg_reduce(None, None, None, None, 300.0, None, None) == fd._lib.E_INVALID
+    assert L.fftdg_set_receptors(None, 1, None, None, None) == fd._lib.E_INVALID
+    assert L.fftdg_last_error(None) == b"context is NULL"
+    L.fftdg_destroy(None)

@@ -1,0 +1,279 @@
+"""Parity of the HIP path (through the C-ABI) with the FP64 oracle.
+
+Tolerances (written here, derived in the design doc):
+  FP64 path: raw energies normwise <= 1e-10, B and dG <= 1e-8 kcal/mol.
+  FP32 path: raw energies ||dPsi||_2 / ||Psi||_2 <= 1e-5 and
+             max|dPsi| <= 1e-5 * max|Psi| over the box-valid translations;
+             clash masks and box extents bit-exact;
+             B and dG within 0.01 kcal/mol.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import estimators as est
+from workload import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL_F32 = 1e-5
+TOL_F64 = 1e-10
+
+
+def _ctx(w, precision=None):
+    import paper_1708_07045_amd as fd
+    return fd.FFTDG.from_workload(w, precision=precision)
+
+
+def _gpu_setup(w, precision=None, snaps=None):
+    """Context with GPU-built receptor grids for all (or the chosen) snapshots."""
+    import torch
+    ctx = _ctx(w, precision)
+    snaps = range(w.receptor.n_snap) if snaps is None else snaps
+    gs, os_ = [], []
+    for s in snaps:
+        g, o = ctx.receptor_grids(w.receptor.xyz[s], w.receptor.q, w.receptor.sigma, w.receptor.eps)
+        gs.append(g)
+        os_.append(o)
+    grids = torch.stack(gs)
+    occ = torch.stack(os_) if w.clash_mode == "occ" else None
+    ctx.set_receptors(grids, occ, w.receptor.weights[list(snaps)])
+    torch.cuda.synchronize()
+    return ctx, grids, occ
+
+
+def _batch(w, select=None):
+    import paper_1708_07045_amd as fd
+    return fd.Batch(w.ligands, select)
+
+
+def _norm_err(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300), np.max(np.abs(a - b)) / max(np.max(np.abs(b)), 1e-300)
+
+
+def _announce(msg):
+    print(msg, flush=True)
+
+
+# ------------------------------------------------------------------ grids
+@pytest.mark.parametrize("cfgname", ["c1", "c2"])
+def test_receptor_grids_match_oracle(cfgname):
+    w = synth.config1() if cfgname == "c1" else synth.config2(n_rot=1, n_conf=1)
+    _announce(f"receptor grids {cfgname}")
+    # FP64 contexts support n_fft <= 64; the 128^3 case is built in FP32
+    prec, tol = ("f64", 1e-12) if cfgname == "c1" else ("f32", 2.0 ** -23)
+    ctx = _ctx(w, prec)
+    g, o = ctx.receptor_grids(w.receptor.xyz[0], w.receptor.q, w.receptor.sigma, w.receptor.eps)
+    go, oo = oracle.receptor_grids(w)
+    gg = g.cpu().numpy().reshape(go.shape).astype(np.float64)
+    for ch in range(3):
+        # element-wise relative error (FP32: one rounding of the FP64 value)
+        rel = np.max(np.abs(gg[ch] - go[ch]) / np.maximum(np.abs(go[ch]), 1e-300))
+        assert rel <= tol, (ch, rel)
+    if w.clash_mode == "occ":
+        np.testing.assert_array_equal(o.cpu().numpy().reshape(oo.shape), oo)
+
+
+# ------------------------------------------------------------------ placement
+def test_placement_bit_exact():
+    w = synth.config2(n_rot=40, n_conf=2)
+    ctx = _ctx(w)
+    b = _batch(w)
+    for c in range(0, w.ligands[0].n_cfg, 3):
+        U, box = ctx.place(b, c)
+        u, obox = oracle.place_cfg(w, 0, c)
+        np.testing.assert_array_equal(U, np.round(u * 65536).astype(np.int64))
+        np.testing.assert_array_equal(box, obox)
+
+
+# ------------------------------------------------------------------ energies
+def _energy_parity(w, cfgs, precision, tol, grids_o=None):
+    ctx, grids, occ = _gpu_setup(w, precision)
+    b = _batch(w)
+    go, oo = grids_o if grids_o is not None else oracle.receptor_grids(w)
+    worst = 0.0
+    for c in cfgs:
+        _announce(f"energy parity {w.name[:3]} {precision} cfg {c}")
+        psi, clash = ctx.energy_grid(0, b, c, w.T)
+        r = oracle.config_eval(w, go, oo, 0, c)
+        assert psi.shape == r["psi"].shape
+        if r["psi"].size == 0:
+            continue
+        e2, emax = _norm_err(psi.cpu().numpy(), r["psi"])
+        worst = max(worst, e2, emax)
+        assert e2 <= tol and emax <= tol, (c, e2, emax)
+        if r["clash"] is not None:
+            np.testing.assert_array_equal(clash.cpu().numpy(), r["clash"])
+        else:
+            assert int(clash.sum()) == 0
+    return worst
+
+
+def test_energy_c1_fp64_cap():
+    w = synth.config1()
+    _energy_parity(w, [0, 1, 17, 42, 99], "f64", TOL_F64)
+
+
+def test_energy_c2_fp32_occ():
+    w = synth.config2(n_rot=12, n_conf=8)
+    _energy_parity(w, [0, 13, 27, 40, 66, 95], "f32", TOL_F32)
+
+
+def test_energy_c2_fp32_cap_and_fp64_n64():
+    """Ragged smaller grids: 40^3 receptor in a 64^3 FFT, both precisions."""
+    w = synth.config2(n_rot=4, n_conf=2)
+    w.n_rec, w.n_fft = 60, 64
+    w.origin = -0.5 * (60 - 1) * w.h * np.ones(3)
+    for prec, tol in [("f32", TOL_F32), ("f64", TOL_F64)]:
+        _energy_parity(w, [0, 3, 5], prec, tol)
+    w.clash_mode = "cap"
+    _energy_parity(w, [1, 6], "f32", 2e-5)
+
+
+def test_single_point_charge_gpu():
+    """One ligand atom of charge 1 (no LJ) at an integer lattice position
+    reproduces the shifted receptor ELE grid."""
+    w = synth.tiny(seed=3, n_rec=30, n_fft=32, h=0.5, n_rec_atoms=80, n_lig_atoms=1, n_cfg=2,
+                   clash_mode="cap", precision="f64", r_ball=6.0)
+    L = w.ligands[0]
+    L.q[:] = 1.0
+    L.eps[:] = 0.0
+    ctx, grids, _ = _gpu_setup(w, "f64")
+    b = _batch(w)
+    psi, _ = ctx.energy_grid(0, b, 0, w.T)
+    g = grids[0, 0].cpu().numpy()
+    Vz, Vy, Vx = psi.shape
+    # a single atom is placed at u = (2,2,2)
+    np.testing.assert_allclose(psi.cpu().numpy(), g[2:2 + Vz, 2:2 + Vy, 2:2 + Vx], rtol=1e-12, atol=1e-11)
+    ctx32, grids32, _ = _gpu_setup(w, "f32")
+    psi32, _ = ctx32.energy_grid(0, b, 0, w.T)
+    g32 = grids32[0, 0].cpu().numpy()
+    e2, emax = _norm_err(psi32.cpu().numpy(), g32[2:2 + Vz, 2:2 + Vy, 2:2 + Vx])
+    assert e2 < 1e-6 and emax < 1e-6
+
+
+# ------------------------------------------------------------------ partials, B, dG
+def _scan_parity(w, precision, tolB, ncheck=None):
+    import torch
+    ctx, grids, occ = _gpu_setup(w, precision)
+    b = _batch(w)
+    _announce(f"scan {w.name[:3]} {precision} n_cfg={b.n_cfg} n_snap={w.receptor.n_snap}")
+    buf = ctx.scan(b, w.T)
+    torch.cuda.synchronize()
+    P = ctx.partials_numpy(buf, ctx.n_snap, b.n_cfg)
+    B, res = ctx.reduce(b, buf, w.T)
+    kt = est.kT(w.T)
+    for l in range(len(w.ligands)):
+        c0, c1 = b.cfg_off[l], b.cfg_off[l + 1]
+        Bo = []
+        for s in range(w.receptor.n_snap):
+            go, oo = oracle.receptor_grids(w, s)
+            parts, boxes = oracle.scan(w, go, oo, lig_idx=l)
+            g = P[s, c0:c1]
+            np.testing.assert_array_equal(g["n_valid"], parts[:, 2].astype(np.int64))
+            np.testing.assert_array_equal(g["n_finite"], parts[:, 3].astype(np.int64))
+            fin = parts[:, 3] > 0
+            # per-configuration log Z and minimum
+            lz_g = np.where(fin, g["m"] + np.log(np.where(fin, g["s"], 1.0)), -np.inf)
+            lz_o = est.log_z(parts)
+            assert np.max(np.abs(kt * (lz_g[fin] - lz_o[fin]))) < tolB
+            assert np.max(np.abs(g["psi_min"][fin] - parts[fin, 4])) < tolB
+            Bo.append(est.bpmf(parts, w.T))
+            assert abs(B[l, s] - Bo[-1]) < tolB, (l, s, B[l, s], Bo[-1])
+        vs = est.v_site(boxes, w.n_rec, w.h)
+        dg = est.dg_standard(np.array(Bo), w.receptor.weights, vs, w.T)
+        assert abs(res["v_site"][l] - vs) <= 1e-9 * vs
+        assert abs(res["dG"][l] - dg) < tolB, (res["dG"][l], dg)
+    return P, B, res
+
+
+def test_scan_c1_fp64():
+    _scan_parity(synth.config1(), "f64", 1e-8)
+
+
+def test_scan_c2_subset_fp32():
+    w = synth.subset(synth.config2(), 96, stride=83)
+    _scan_parity(w, "f32", 0.01)
+
+
+def test_scan_batched_uneven_ligands_two_snapshots():
+    """Ragged batch: 5 ligands of 8..40 atoms with different configuration
+    counts against 2 jittered snapshots (small chunk to cross chunk edges)."""
+    w = synth.config3(n_ligands=5, n_snap=2, cfg_scale=0.02)
+    P, B, res = _scan_parity(w, "f32", 0.01)
+    assert P.shape[0] == 2
+
+
+def test_cfg_select_and_empty_configs():
+    """cfg_select scans a subset; unscanned configurations still count their
+    translations; a configuration whose box exceeds the grid has n_valid 0."""
+    import torch
+    w = synth.config2(n_rot=10, n_conf=2)
+    sel = np.zeros(20, np.uint8)
+    sel[::3] = 1
+    ctx, grids, occ = _gpu_setup(w)
+    b = _batch(w, sel)
+    P = ctx.partials_numpy(ctx.scan(b, w.T), 1, 20)[0]
+    assert np.all(P["scanned"] == sel)
+    assert np.all(P["n_finite"][sel == 0] == 0)
+    go, oo = oracle.receptor_grids(w)
+    parts, _ = oracle.scan(w, go, oo)
+    np.testing.assert_array_equal(P["n_valid"], parts[:, 2].astype(np.int64))
+    np.testing.assert_array_equal(P["n_finite"][sel == 1], parts[sel == 1, 3].astype(np.int64))
+    # a ligand that does not fit anywhere -> E_NOVALID
+    import paper_1708_07045_amd as fd
+    big = synth.config2(n_rot=2, n_conf=1)
+    big.ligands[0].conformers = big.ligands[0].conformers * 4.0
+    with pytest.raises(fd.FFTDGError) as ei:
+        ctx.scan(_batch(big), w.T)
+    assert ei.value.code == fd._lib.E_NOVALID
+
+
+def test_all_clash_gives_infinite_bpmf():
+    """A receptor whose occupancy grid is full: every translation clashes,
+    B = +inf and dG = +inf (a result, not an error)."""
+    import torch
+    w = synth.config2(n_rot=3, n_conf=1)
+    ctx = _ctx(w)
+    g, o = ctx.receptor_grids(w.receptor.xyz[0], w.receptor.q, w.receptor.sigma, w.receptor.eps)
+    o.fill_(1)
+    ctx.set_receptors(g[None], o[None])
+    b = _batch(w)
+    buf = ctx.scan(b, w.T)
+    P = ctx.partials_numpy(buf, 1, b.n_cfg)[0]
+    assert np.all(P["n_finite"] == 0) and np.all(P["n_valid"] > 0)
+    B, res = ctx.reduce(b, buf, w.T)
+    assert math.isinf(B[0, 0]) and math.isinf(res["dG"][0])
+
+
+def test_importance_weights_reduce():
+    """Reduce with per-configuration weights equals the oracle's weighted form."""
+    import torch
+    w = synth.subset(synth.config2(), 40, stride=200)
+    ctx, grids, occ = _gpu_setup(w)
+    b = _batch(w)
+    buf = ctx.scan(b, w.T)
+    rng = np.random.default_rng(3)
+    wt = rng.uniform(0.0, 3.0, b.n_cfg)
+    wt[::7] = 0.0
+    B, _ = ctx.reduce(b, buf, w.T, cfg_weight=wt)
+    go, oo = oracle.receptor_grids(w)
+    parts, _ = oracle.scan(w, go, oo)
+    lz = est.log_z(parts)
+    ok = (wt > 0) & np.isfinite(lz)
+    Bo = -est.kT(w.T) * (est.lse(np.log(wt[ok]) + lz[ok]) - math.log(parts[:, 2].sum()))
+    assert abs(B[0, 0] - Bo) < 0.01
+
+
+def test_rescan_is_deterministic():
+    import torch
+    w = synth.subset(synth.config2(), 32, stride=100)
+    ctx, grids, occ = _gpu_setup(w)
+    b = _batch(w)
+    a = ctx.scan(b, w.T).cpu().numpy()
+    c = ctx.scan(b, w.T).cpu().numpy()
+    np.testing.assert_array_equal(a, c)
