@@ -202,6 +202,31 @@ int fftdg_reduce(fftdg_ctx *ctx, const fftdg_batch *b, const fftdg_partial *p_de
                  const double *cfg_weight_dev, double T_K, double *B_host,
                  fftdg_ligand_result *res_host);
 
+/* Kernel timing with HIP events recorded on the context's stream around
+ * every launch the library makes (for benchmarks).  Kernel ids:
+ *   0 ligand xy forward   1 z-pencil product   2 inverse xy + log-sum-exp
+ *   3 plane merge         4 receptor spectra   5 FP64 reduce
+ * fftdg_profile(ctx, 1) clears the counters and starts recording; 0 stops.
+ * fftdg_profile_read synchronizes the stream and returns, for kernel id k,
+ * the summed event time (ms), the launch count and the algorithmic HBM
+ * bytes those launches must move (inputs read once, outputs written once;
+ * the per-launch figures are documented with the kernels). */
+#define FFTDG_K_FWD 0
+#define FFTDG_K_ZPROD 1
+#define FFTDG_K_INV 2
+#define FFTDG_K_MERGE 3
+#define FFTDG_K_SPECTRA 4
+#define FFTDG_K_REDUCE 5
+#define FFTDG_N_KERNELS 6
+int fftdg_profile(fftdg_ctx *ctx, int enable);
+int fftdg_profile_read(fftdg_ctx *ctx, int32_t kernel_id, double *ms_host, int64_t *launches_host,
+                       double *alg_bytes_host);
+
+/* Work-partition knob: configurations per chunk of work (default 256);
+ * each chunk's forward planes and inverse planes live in device workspace
+ * at the same time.  Values < 1 are rejected. */
+int fftdg_set_chunk(fftdg_ctx *ctx, int32_t configs_per_chunk);
+
 #ifdef __cplusplus
 }
 #endif

@@ -46,7 +46,10 @@ class BatchC(ctypes.Structure):
 
 EXPORTS = ["fftdg_version", "fftdg_status_string", "fftdg_create", "fftdg_destroy", "fftdg_last_error",
            "fftdg_set_stream", "fftdg_receptor_grids", "fftdg_set_receptors", "fftdg_scan",
-           "fftdg_energy_grid", "fftdg_place", "fftdg_reduce"]
+           "fftdg_energy_grid", "fftdg_place", "fftdg_reduce", "fftdg_profile", "fftdg_profile_read",
+           "fftdg_set_chunk"]
+
+KERNEL_NAMES = ["lig_fwd_xy", "zprod", "inv_xy_lse", "merge", "rec_spectra", "reduce"]
 
 _lib = None
 
@@ -76,6 +79,9 @@ def load():
     L.fftdg_energy_grid.argtypes = [p, i32, ctypes.POINTER(BatchC), i32, d, p, p, p]
     L.fftdg_place.argtypes = [p, ctypes.POINTER(BatchC), i32, p, p]
     L.fftdg_reduce.argtypes = [p, ctypes.POINTER(BatchC), p, p, d, p, p]
+    L.fftdg_profile.argtypes = [p, ctypes.c_int]
+    L.fftdg_profile_read.argtypes = [p, i32, p, p, p]
+    L.fftdg_set_chunk.argtypes = [p, i32]
     for name in EXPORTS:
         if name not in ("fftdg_destroy", "fftdg_status_string", "fftdg_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -171,6 +177,22 @@ class FFTDG:
     def _check(self, rc: int):
         if rc != OK:
             raise FFTDGError(rc, self.L.fftdg_last_error(self.h_ctx).decode())
+
+    def set_chunk(self, n: int):
+        self._check(self.L.fftdg_set_chunk(self.h_ctx, int(n)))
+
+    def profile(self, enable: bool = True):
+        self._check(self.L.fftdg_profile(self.h_ctx, 1 if enable else 0))
+
+    def profile_read(self):
+        """{kernel name: (ms, launches, algorithmic bytes)} since profile(True)."""
+        out = {}
+        for k, name in enumerate(KERNEL_NAMES):
+            ms, n, b = ctypes.c_double(), ctypes.c_int64(), ctypes.c_double()
+            self._check(self.L.fftdg_profile_read(self.h_ctx, k, ctypes.byref(ms), ctypes.byref(n),
+                                                  ctypes.byref(b)))
+            out[name] = (ms.value, n.value, b.value)
+        return out
 
     def set_stream(self, stream_handle: int):
         self._check(self.L.fftdg_set_stream(self.h_ctx, ctypes.c_void_p(stream_handle)))

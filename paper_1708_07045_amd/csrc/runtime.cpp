@@ -46,6 +46,18 @@ struct fftdg_ctx {
     bool staging_used = false;
     int chunk_cfgs = 256;
     size_t ws_limit = (size_t)24 << 30;
+    // profiling
+    bool prof = false;
+    struct Rec {
+        int k;
+        hipEvent_t a, b;
+        double bytes;
+    };
+    std::vector<Rec> recs;
+    std::vector<hipEvent_t> ev_pool;
+    double prof_ms[FFTDG_N_KERNELS] = {0};
+    int64_t prof_n[FFTDG_N_KERNELS] = {0};
+    double prof_bytes[FFTDG_N_KERNELS] = {0};
 };
 
 namespace {
@@ -61,6 +73,32 @@ int set_err(fftdg_ctx *c, int code, const std::string &msg) {
         if (e_ != hipSuccess)                                                                 \
             return set_err(ctx, FFTDG_E_DEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
+
+hipEvent_t pool_event(fftdg_ctx *c) {
+    if (!c->ev_pool.empty()) {
+        hipEvent_t e = c->ev_pool.back();
+        c->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
+    }
+    return e;
+}
+
+// Launch `fn` (returning hipError_t) bracketed by profiling events.
+template <class F>
+hipError_t timed(fftdg_ctx *c, int k, double bytes, F &&fn) {
+    if (!c->prof) return fn();
+    hipEvent_t a = pool_event(c), b = pool_event(c);
+    if (a) (void)hipEventRecord(a, c->stream);
+    hipError_t e = fn();
+    if (b) (void)hipEventRecord(b, c->stream);
+    if (a && b) c->recs.push_back(fftdg_ctx::Rec{k, a, b, bytes});
+    return e;
+}
 
 int reserve(fftdg_ctx *c, DevBuf &b, size_t bytes) {
     if (bytes <= b.n) return FFTDG_OK;
@@ -466,18 +504,34 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     const double beta = 1.0 / (kR * T_K);
     const size_t spec_per_snap = (size_t)ctx->n_ch * g.n_fft * ctx->ks->np * cb;
     const KernelSet *ks = ctx->ks;
+    const double pb = (double)ctx->ks->ppbytes;
     for (const Plan::Chunk &ch : P.chunks) {
         const CfgDev *ccfg = dcfg + ch.c0;
-        HIPCHK(ctx, ks->fwd(ctx->stream, dfwd + ch.fwd0, (int)ch.nfwd, ccfg, du, dgam, dthr, ctx->tw.p, ctx->ws_fwd.p));
+        // algorithmic bytes: forward planes written once (fwd), read once and
+        // inverse planes written once plus one read of the receptor spectra
+        // (z product), inverse planes read once (inverse xy), plane partials
+        // read and configuration partials written (merge)
+        const double b_fwd = (double)ch.ws_fwd * cb;
+        const double b_inv = (double)ch.ws_inv * cb;
+        HIPCHK(ctx, timed(ctx, FFTDG_K_FWD, b_fwd, [&] {
+                   return ks->fwd(ctx->stream, dfwd + ch.fwd0, (int)ch.nfwd, ccfg, du, dgam, dthr, ctx->tw.p,
+                                  ctx->ws_fwd.p);
+               }));
         for (int s = 0; s < ctx->n_snap; ++s) {
             if (snap_only >= 0 && s != snap_only) continue;
             const char *rs = (const char *)ctx->rspec.p + spec_per_snap * s;
-            HIPCHK(ctx, ks->zprod(ctx->stream, occ, ccfg, dz + ch.z0, (int)ch.nz, ctx->ws_fwd.p, rs, ctx->tw.p,
-                                  ctx->ws_inv.p));
-            HIPCHK(ctx, ks->inv(ctx->stream, occ, dinv + ch.inv0, (int)ch.ninv, ccfg, ctx->ws_inv.p, beta, ctx->tw.p,
-                                ctx->pp.p, psi_out, clash_out));
+            HIPCHK(ctx, timed(ctx, FFTDG_K_ZPROD, b_fwd + b_inv + (double)spec_per_snap, [&] {
+                       return ks->zprod(ctx->stream, occ, ccfg, dz + ch.z0, (int)ch.nz, ctx->ws_fwd.p, rs, ctx->tw.p,
+                                        ctx->ws_inv.p);
+                   }));
+            HIPCHK(ctx, timed(ctx, FFTDG_K_INV, b_inv + pb * ch.pp, [&] {
+                       return ks->inv(ctx->stream, occ, dinv + ch.inv0, (int)ch.ninv, ccfg, ctx->ws_inv.p, beta,
+                                      ctx->tw.p, ctx->pp.p, psi_out, clash_out);
+                   }));
             if (out)
-                HIPCHK(ctx, ks->merge(ctx->stream, ccfg, ch.c1 - ch.c0, ctx->pp.p, out + (size_t)s * ncfg));
+                HIPCHK(ctx, timed(ctx, FFTDG_K_MERGE, pb * ch.pp + sizeof(fftdg_partial) * (double)(ch.c1 - ch.c0), [&] {
+                           return ks->merge(ctx->stream, ccfg, ch.c1 - ch.c0, ctx->pp.p, out + (size_t)s * ncfg);
+                       }));
         }
     }
     return FFTDG_OK;
@@ -582,6 +636,11 @@ void fftdg_destroy(fftdg_ctx *c) {
         if (b->p) (void)hipFree(b->p);
     if (c->pinned) (void)hipHostFree(c->pinned);
     if (c->staging_ev) (void)hipEventDestroy(c->staging_ev);
+    for (auto &r : c->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
     delete c;
 }
 
@@ -630,10 +689,15 @@ int fftdg_set_receptors(fftdg_ctx *ctx, int32_t n_snap, const void *grids, const
     if ((rc = reserve(ctx, ctx->rxy, (size_t)ctx->n_ch * g.n_rec * ctx->ks->np * cb))) return rc;
     const size_t n3 = (size_t)g.n_rec * g.n_rec * g.n_rec;
     const size_t tsz = g.precision == FFTDG_F32 ? 4 : 8;
+    // bytes: grids read, xy planes written and read back, spectra written
+    const double b_spec = (double)(3 * n3 * tsz + (is_occ ? n3 : 0)) +
+                          2.0 * ctx->n_ch * g.n_rec * (double)ctx->ks->np * cb + (double)per_snap;
     for (int s = 0; s < n_snap; ++s) {
-        HIPCHK(ctx, ctx->ks->rec_spectra(ctx->stream, (const char *)grids + s * 3 * n3 * tsz,
-                                         is_occ ? occ + s * n3 : nullptr, g.n_rec, ctx->n_ch, ctx->tw.p, ctx->rxy.p,
-                                         (char *)ctx->rspec.p + s * per_snap));
+        HIPCHK(ctx, timed(ctx, FFTDG_K_SPECTRA, b_spec, [&] {
+                   return ctx->ks->rec_spectra(ctx->stream, (const char *)grids + s * 3 * n3 * tsz,
+                                               is_occ ? occ + s * n3 : nullptr, g.n_rec, ctx->n_ch, ctx->tw.p,
+                                               ctx->rxy.p, (char *)ctx->rspec.p + s * per_snap);
+               }));
     }
     ctx->n_snap = n_snap;
     ctx->W = W;
@@ -718,9 +782,11 @@ int fftdg_reduce(fftdg_ctx *ctx, const fftdg_batch *b, const fftdg_partial *p, c
     HIPCHK(ctx, hipMemcpyAsync(ctx->red_W.p, ctx->W.data(), sizeof(double) * ns, hipMemcpyHostToDevice, ctx->stream));
     const double kT = kR * T_K;
     const double h3 = ctx->g.h * ctx->g.h * ctx->g.h;
-    HIPCHK(ctx, launch_reduce(ctx->stream, p, b->cfg_off[nl], ns, nl, (const int32_t *)ctx->red_off.p, cfg_w,
-                              (const double *)ctx->red_W.p, kT, h3, kC0, (double *)ctx->red_B.p,
-                              (LigRed *)ctx->red_res.p));
+    HIPCHK(ctx, timed(ctx, FFTDG_K_REDUCE, (double)sizeof(fftdg_partial) * (double)b->cfg_off[nl] * ns, [&] {
+               return launch_reduce(ctx->stream, p, b->cfg_off[nl], ns, nl, (const int32_t *)ctx->red_off.p, cfg_w,
+                                    (const double *)ctx->red_W.p, kT, h3, kC0, (double *)ctx->red_B.p,
+                                    (LigRed *)ctx->red_res.p);
+           }));
     std::vector<LigRed> r(nl);
     HIPCHK(ctx, hipMemcpyAsync(B_host, ctx->red_B.p, sizeof(double) * (size_t)nl * ns, hipMemcpyDeviceToHost, ctx->stream));
     HIPCHK(ctx, hipMemcpyAsync(r.data(), ctx->red_res.p, sizeof(LigRed) * nl, hipMemcpyDeviceToHost, ctx->stream));
@@ -732,6 +798,53 @@ int fftdg_reduce(fftdg_ctx *ctx, const fftdg_batch *b, const fftdg_partial *p, c
         res_host[l].n_finite = r[l].n_finite;
         res_host[l].n_samples = r[l].n_samples;
     }
+    return FFTDG_OK;
+}
+
+int fftdg_profile(fftdg_ctx *ctx, int enable) {
+    if (!ctx) return FFTDG_E_INVALID;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (auto &r : ctx->recs) {
+        ctx->ev_pool.push_back(r.a);
+        ctx->ev_pool.push_back(r.b);
+    }
+    ctx->recs.clear();
+    for (int k = 0; k < FFTDG_N_KERNELS; ++k) {
+        ctx->prof_ms[k] = 0.0;
+        ctx->prof_n[k] = 0;
+        ctx->prof_bytes[k] = 0.0;
+    }
+    ctx->prof = enable != 0;
+    return FFTDG_OK;
+}
+
+int fftdg_profile_read(fftdg_ctx *ctx, int32_t k, double *ms, int64_t *n, double *bytes) {
+    if (!ctx) return FFTDG_E_INVALID;
+    if (k < 0 || k >= FFTDG_N_KERNELS || !ms || !n || !bytes)
+        return set_err(ctx, FFTDG_E_INVALID, "profile_read: bad kernel id or NULL output");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    for (auto &r : ctx->recs) {
+        float t = 0.f;
+        HIPCHK(ctx, hipEventElapsedTime(&t, r.a, r.b));
+        ctx->prof_ms[r.k] += t;
+        ctx->prof_n[r.k] += 1;
+        ctx->prof_bytes[r.k] += r.bytes;
+        ctx->ev_pool.push_back(r.a);
+        ctx->ev_pool.push_back(r.b);
+    }
+    ctx->recs.clear();
+    *ms = ctx->prof_ms[k];
+    *n = ctx->prof_n[k];
+    *bytes = ctx->prof_bytes[k];
+    return FFTDG_OK;
+}
+
+int fftdg_set_chunk(fftdg_ctx *ctx, int32_t n) {
+    if (!ctx) return FFTDG_E_INVALID;
+    if (n < 1) return set_err(ctx, FFTDG_E_INVALID, "set_chunk: configs_per_chunk must be >= 1");
+    ctx->chunk_cfgs = n;
     return FFTDG_OK;
 }
 
