@@ -60,6 +60,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--chunk", type=int, default=0, help="configurations per chunk (0 = library default)")
+    ap.add_argument("--energy-direct", type=int, default=-1, help="1/0: energy xy transforms fused (default: library)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
@@ -77,7 +78,9 @@ def main():
     log(f"workload: {w.name}; {w.n_cfg_total} configurations")
     ctx = fd.FFTDG.from_workload(w)
     if args.chunk:
-        ctx.set_chunk(args.chunk)
+        ctx.set_tuning(configs_per_chunk=args.chunk)
+    if args.energy_direct in (0, 1):
+        ctx.set_tuning(energy_xy_direct=args.energy_direct)
     grids, occ = ctx.receptor_grids(w.receptor.xyz[0], w.receptor.q, w.receptor.sigma, w.receptor.eps)
     grids, occ = grids[None].contiguous(), occ[None].contiguous()
     batch = fd.Batch(w.ligands)
@@ -144,7 +147,7 @@ def main():
         "config": {"workload": "T4L-sized plain scan: 2600-atom cavity receptor, 96^3 grid @ 0.25 A -> 128^3 FFT, "
                                "occupancy clash mode, 25-atom ligand x 8 conformers x 1000 rotations, 300 K",
                    "n_cfg": n_cfg, "n_fft": w.n_fft, "n_rec": w.n_rec, "clash_mode": w.clash_mode,
-                   "n_snap": 1, "parallelism": "single GPU"},
+                   "n_snap": 1, "parallelism": "single GPU", "tuning": ctx.get_tuning()},
         "translations_per_s": cfg_s * n_valid / n_cfg,
         "evaluated_translations_per_s": cfg_s * w.n_fft ** 3,
         "path_alg_bytes_per_cfg": path_bytes / n_cfg,

@@ -222,10 +222,22 @@ int fftdg_profile(fftdg_ctx *ctx, int enable);
 int fftdg_profile_read(fftdg_ctx *ctx, int32_t kernel_id, double *ms_host, int64_t *launches_host,
                        double *alg_bytes_host);
 
-/* Work-partition knob: configurations per chunk of work (default 256);
- * each chunk's forward planes and inverse planes live in device workspace
- * at the same time.  Values < 1 are rejected. */
-int fftdg_set_chunk(fftdg_ctx *ctx, int32_t configs_per_chunk);
+/* Execution schedule (results do not depend on it beyond rounding order of
+ * the FP32 transforms):
+ *   configs_per_chunk  configurations whose forward and inverse planes share
+ *                      device workspace at one time (>= 1, default 256);
+^ *   energy_xy_direct   1: the x/y transforms of the three energy
+ *                      channels are evaluated per atom inside the z-pencil
+ *                      kernel (the xy FFT of the trilinearly spread plane
+ *                      with its zero inputs pruned); 0: they go through the
+ *                      same LDS-staged xy FFT pass as the occupancy channel
+ *                      and through HBM (default). */
+typedef struct {
+    int32_t configs_per_chunk;
+    int32_t energy_xy_direct;
+} fftdg_tuning;
+int fftdg_get_tuning(const fftdg_ctx *ctx, fftdg_tuning *out);
+int fftdg_set_tuning(fftdg_ctx *ctx, const fftdg_tuning *t);
 
 #ifdef __cplusplus
 }

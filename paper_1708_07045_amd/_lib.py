@@ -37,6 +37,10 @@ class GridDesc(ctypes.Structure):
                 ("clash_mode", ctypes.c_int32), ("ljr_cap", ctypes.c_double), ("occ_f", ctypes.c_double)]
 
 
+class Tuning(ctypes.Structure):
+    _fields_ = [("configs_per_chunk", ctypes.c_int32), ("energy_xy_direct", ctypes.c_int32)]
+
+
 class BatchC(ctypes.Structure):
     _fields_ = [("n_lig", ctypes.c_int32), ("atom_off", ctypes.c_void_p), ("conf_off", ctypes.c_void_p),
                 ("cfg_off", ctypes.c_void_p), ("q", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
@@ -47,7 +51,7 @@ class BatchC(ctypes.Structure):
 EXPORTS = ["fftdg_version", "fftdg_status_string", "fftdg_create", "fftdg_destroy", "fftdg_last_error",
            "fftdg_set_stream", "fftdg_receptor_grids", "fftdg_set_receptors", "fftdg_scan",
            "fftdg_energy_grid", "fftdg_place", "fftdg_reduce", "fftdg_profile", "fftdg_profile_read",
-           "fftdg_set_chunk"]
+           "fftdg_get_tuning", "fftdg_set_tuning"]
 
 KERNEL_NAMES = ["lig_fwd_xy", "zprod", "inv_xy_lse", "merge", "rec_spectra", "reduce"]
 
@@ -81,7 +85,8 @@ def load():
     L.fftdg_reduce.argtypes = [p, ctypes.POINTER(BatchC), p, p, d, p, p]
     L.fftdg_profile.argtypes = [p, ctypes.c_int]
     L.fftdg_profile_read.argtypes = [p, i32, p, p, p]
-    L.fftdg_set_chunk.argtypes = [p, i32]
+    L.fftdg_get_tuning.argtypes = [p, ctypes.POINTER(Tuning)]
+    L.fftdg_set_tuning.argtypes = [p, ctypes.POINTER(Tuning)]
     for name in EXPORTS:
         if name not in ("fftdg_destroy", "fftdg_status_string", "fftdg_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -178,8 +183,22 @@ class FFTDG:
         if rc != OK:
             raise FFTDGError(rc, self.L.fftdg_last_error(self.h_ctx).decode())
 
+    def get_tuning(self) -> dict:
+        t = Tuning()
+        self._check(self.L.fftdg_get_tuning(self.h_ctx, ctypes.byref(t)))
+        return {"configs_per_chunk": t.configs_per_chunk, "energy_xy_direct": t.energy_xy_direct}
+
+    def set_tuning(self, configs_per_chunk: Optional[int] = None, energy_xy_direct: Optional[int] = None):
+        cur = self.get_tuning()
+        if configs_per_chunk is not None:
+            cur["configs_per_chunk"] = int(configs_per_chunk)
+        if energy_xy_direct is not None:
+            cur["energy_xy_direct"] = int(energy_xy_direct)
+        t = Tuning(cur["configs_per_chunk"], cur["energy_xy_direct"])
+        self._check(self.L.fftdg_set_tuning(self.h_ctx, ctypes.byref(t)))
+
     def set_chunk(self, n: int):
-        self._check(self.L.fftdg_set_chunk(self.h_ctx, int(n)))
+        self.set_tuning(configs_per_chunk=n)
 
     def profile(self, enable: bool = True):
         self._check(self.L.fftdg_profile(self.h_ctx, 1 if enable else 0))

@@ -122,33 +122,49 @@ __device__ __forceinline__ void cmul_tw(T &r, T &i, typename Cx<T>::t w, bool co
     i = ni;
 }
 
+// Orders LDS traffic between the lanes of one wavefront.  A wavefront's LDS
+// instructions execute in program order, so only the compiler has to be kept
+// from moving loads and stores across this point.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Forward-structured length-N transform by one unit (R1 lanes).
 //   in : lane n1 holds x[n1 + R1*n2] in (re,im)[n2]
 //   out: lane j holds X[R2*k1 + j*M + i] in (re,im)[i*R1 + k1]
 // INV selects the sign of the exponent (no scaling).
-// ex[e * es], e in [0, N): this unit's LDS exchange area.  `live` = false
-// makes the unit skip its LDS traffic (it must still reach the barriers).
-// Every thread of the workgroup must call this with the same N.
+// ex[e * es + (e / R2) * pad], e in [0, N): this unit's private LDS exchange
+// area (the padding moves the blocks read by different lanes to different
+// LDS banks).  The R1
+// lanes of a unit must belong to one wavefront: the exchange is ordered with
+// wave_sync(), not with a workgroup barrier.  `live` = false makes the unit
+// skip its LDS traffic.
 template <typename T, int N, bool INV>
 __device__ __forceinline__ void fft_unit(T *re, T *im, int n1, typename Cx<T>::t *ex, int es,
-                                         const typename Cx<T>::t *tw, bool live) {
+                                         const typename Cx<T>::t *tw, bool live, int pad = 0) {
     using C2 = typename Cx<T>::t;
     constexpr int R1 = Shape<N>::R1, R2 = Shape<N>::R2, M = R2 / R1;
     dft_reg<R2, INV>(re, im);
 #pragma unroll
     for (int k2 = 1; k2 < R2; ++k2) cmul_tw(re[k2], im[k2], tw[n1 * k2], INV);
-    __syncthreads();  // the exchange area may still be read by a previous step
+    wave_sync();  // the exchange area may still be read by a previous step
     if (live) {
 #pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) ex[(k2 * R1 + n1) * es] = C2{re[k2], im[k2]};
+        for (int k2 = 0; k2 < R2; ++k2) {
+            const int e = k2 * R1 + n1;
+            ex[e * es + (e / R2) * pad] = C2{re[k2], im[k2]};
+        }
     }
-    __syncthreads();
+    wave_sync();
     if (live) {
 #pragma unroll
         for (int i = 0; i < M; ++i)
 #pragma unroll
             for (int a = 0; a < R1; ++a) {
-                C2 v = ex[((n1 * M + i) * R1 + a) * es];
+                const int e = (n1 * M + i) * R1 + a;
+                C2 v = ex[e * es + (e / R2) * pad];
                 re[i * R1 + a] = v.x;
                 im[i * R1 + a] = v.y;
             }
@@ -162,7 +178,7 @@ __device__ __forceinline__ void fft_unit(T *re, T *im, int n1, typename Cx<T>::t
 // x[n1 + R1*n2] in slot n2).  Same transform definition as fft_unit.
 template <typename T, int N, bool INV>
 __device__ __forceinline__ void fft_unit_rev(T *re, T *im, int n1, typename Cx<T>::t *ex, int es,
-                                             const typename Cx<T>::t *tw, bool live) {
+                                             const typename Cx<T>::t *tw, bool live, int pad = 0) {
     using C2 = typename Cx<T>::t;
     constexpr int R1 = Shape<N>::R1, R2 = Shape<N>::R2, M = R2 / R1;
     // R1-point DFT over k1 for each of this lane's k2 = j*M + i, giving
@@ -174,19 +190,22 @@ __device__ __forceinline__ void fft_unit_rev(T *re, T *im, int n1, typename Cx<T
 #pragma unroll
         for (int a = 1; a < R1; ++a) cmul_tw(re[i * R1 + a], im[i * R1 + a], tw[a * k2], INV);
     }
-    __syncthreads();
+    wave_sync();
     if (live) {
 #pragma unroll
         for (int i = 0; i < M; ++i)
 #pragma unroll
-            for (int a = 0; a < R1; ++a)
-                ex[((n1 * M + i) * R1 + a) * es] = C2{re[i * R1 + a], im[i * R1 + a]};
+            for (int a = 0; a < R1; ++a) {
+                const int e = (n1 * M + i) * R1 + a;
+                ex[e * es + (e / R2) * pad] = C2{re[i * R1 + a], im[i * R1 + a]};
+            }
     }
-    __syncthreads();
+    wave_sync();
     if (live) {
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2) {
-            C2 v = ex[(k2 * R1 + n1) * es];
+            const int e = k2 * R1 + n1;
+            C2 v = ex[e * es + (e / R2) * pad];
             re[k2] = v.x;
             im[k2] = v.y;
         }

@@ -19,11 +19,15 @@ struct KernelSet {
                               const void *tw, void *rxy, void *rspec);
     hipError_t (*fwd)(hipStream_t, const FwdItem *items, int n_items, const CfgDev *cfgs, const int32_t *ulat,
                       const void *gam, const double *thr, const void *tw, void *ws);
-    hipError_t (*zprod)(hipStream_t, bool occ, const CfgDev *cfgs, const int32_t *zcfg, int nz, const void *ws,
-                        const void *rspec, const void *tw, void *wsi);
+    // edirect: energy-channel xy transforms evaluated per atom inside the
+    // kernel (else read from forward planes written by fwd)
+    hipError_t (*zprod)(hipStream_t, bool occ, bool edirect, const CfgDev *cfgs, const int32_t *zcfg, int nz,
+                        const void *ws, const void *rspec, const void *tw, void *wsi, const int32_t *ulat,
+                        const void *gam);
+    // e_count (nullable): incremented once per energy plane transformed
     hipError_t (*inv)(hipStream_t, bool occ, const InvItem *items, int n_items, const CfgDev *cfgs,
                       const void *wsi, double beta, const void *tw, void *pp, void *psi_out,
-                      uint8_t *clash_out);
+                      uint8_t *clash_out, unsigned int *e_count);
     hipError_t (*merge)(hipStream_t, const CfgDev *cfgs, int n_cfg, const void *pp, fftdg_partial *out);
 };
 

@@ -45,6 +45,7 @@ struct fftdg_ctx {
     hipEvent_t staging_ev = nullptr;
     bool staging_used = false;
     int chunk_cfgs = 256;
+    bool edirect = false;
     size_t ws_limit = (size_t)24 << 30;
     // profiling
     bool prof = false;
@@ -58,6 +59,7 @@ struct fftdg_ctx {
     double prof_ms[FFTDG_N_KERNELS] = {0};
     int64_t prof_n[FFTDG_N_KERNELS] = {0};
     double prof_bytes[FFTDG_N_KERNELS] = {0};
+    DevBuf prof_cnt;  // energy planes transformed by the inverse-xy kernel
 };
 
 namespace {
@@ -402,15 +404,18 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
         while (c < ncfg) {
             CfgDev &d = P.cfg[c];
             if (d.scanned) {
-                const int64_t f = (int64_t)(3 * d.Le + (occ ? d.Lo : 0)) * NP;
+                const int e_planes = ctx->edirect ? 0 : 3 * d.Le;
+                d.occ_slot0 = e_planes;
+                const int64_t f = (int64_t)(e_planes + (occ ? d.Lo : 0)) * NP;
                 const int64_t iv = (int64_t)nout * d.V[2] * NP;
                 if (nscan > 0 && (nscan >= ctx->chunk_cfgs || wf + f + wi + iv > limit_c)) break;
                 d.off_fwd = wf;
                 d.off_inv = wi;
                 d.pp_base = pp;
                 const int local = c - ch.c0;
-                for (int k = 0; k < 3; ++k)
-                    for (int p = 0; p < d.Le; ++p) P.fwd.push_back(FwdItem{local, k, p, 0});
+                if (!ctx->edirect)
+                    for (int k = 0; k < 3; ++k)
+                        for (int p = 0; p < d.Le; ++p) P.fwd.push_back(FwdItem{local, k, p, 0});
                 if (occ)
                     for (int p = 0; p < d.Lo; ++p) P.fwd.push_back(FwdItem{local, 3, p, 0});
                 for (int tz = 0; tz < d.V[2]; ++tz) P.inv.push_back(InvItem{local, tz});
@@ -521,12 +526,16 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
             if (snap_only >= 0 && s != snap_only) continue;
             const char *rs = (const char *)ctx->rspec.p + spec_per_snap * s;
             HIPCHK(ctx, timed(ctx, FFTDG_K_ZPROD, b_fwd + b_inv + (double)spec_per_snap, [&] {
-                       return ks->zprod(ctx->stream, occ, ccfg, dz + ch.z0, (int)ch.nz, ctx->ws_fwd.p, rs, ctx->tw.p,
-                                        ctx->ws_inv.p);
+                       return ks->zprod(ctx->stream, occ, ctx->edirect, ccfg, dz + ch.z0, (int)ch.nz, ctx->ws_fwd.p,
+                                        rs, ctx->tw.p, ctx->ws_inv.p, du, dgam);
                    }));
-            HIPCHK(ctx, timed(ctx, FFTDG_K_INV, b_inv + pb * ch.pp, [&] {
+            // inverse xy: occupancy planes always, energy planes only where the
+            // plane has a clash-free translation (counted on the device)
+            const double b_inv_fixed = (occ ? 0.5 * b_inv : 0.0) + pb * ch.pp;
+            HIPCHK(ctx, timed(ctx, FFTDG_K_INV, b_inv_fixed, [&] {
                        return ks->inv(ctx->stream, occ, dinv + ch.inv0, (int)ch.ninv, ccfg, ctx->ws_inv.p, beta,
-                                      ctx->tw.p, ctx->pp.p, psi_out, clash_out);
+                                      ctx->tw.p, ctx->pp.p, psi_out, clash_out,
+                                      ctx->prof ? (unsigned int *)ctx->prof_cnt.p : nullptr);
                    }));
             if (out)
                 HIPCHK(ctx, timed(ctx, FFTDG_K_MERGE, pb * ch.pp + sizeof(fftdg_partial) * (double)(ch.c1 - ch.c0), [&] {
@@ -631,7 +640,7 @@ void fftdg_destroy(fftdg_ctx *c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     DevBuf *bufs[] = {&c->tw, &c->rspec, &c->rxy, &c->ws_fwd, &c->ws_inv, &c->pp, &c->tables,
-                      &c->red_B, &c->red_res, &c->red_off, &c->red_W};
+                      &c->red_B, &c->red_res, &c->red_off, &c->red_W, &c->prof_cnt};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->pinned) (void)hipHostFree(c->pinned);
@@ -815,6 +824,12 @@ int fftdg_profile(fftdg_ctx *ctx, int enable) {
         ctx->prof_n[k] = 0;
         ctx->prof_bytes[k] = 0.0;
     }
+    if (enable) {
+        int rc = reserve(ctx, ctx->prof_cnt, sizeof(unsigned int));
+        if (rc) return rc;
+        const unsigned int zero = 0;
+        HIPCHK(ctx, hipMemcpy(ctx->prof_cnt.p, &zero, sizeof(zero), hipMemcpyHostToDevice));
+    }
     ctx->prof = enable != 0;
     return FFTDG_OK;
 }
@@ -835,16 +850,34 @@ int fftdg_profile_read(fftdg_ctx *ctx, int32_t k, double *ms, int64_t *n, double
         ctx->ev_pool.push_back(r.b);
     }
     ctx->recs.clear();
+    if (ctx->prof_cnt.p) {
+        unsigned int cnt = 0;
+        HIPCHK(ctx, hipMemcpy(&cnt, ctx->prof_cnt.p, sizeof(cnt), hipMemcpyDeviceToHost));
+        const unsigned int zero = 0;
+        HIPCHK(ctx, hipMemcpy(ctx->prof_cnt.p, &zero, sizeof(zero), hipMemcpyHostToDevice));
+        ctx->prof_bytes[FFTDG_K_INV] += (double)cnt * ctx->ks->np * ctx->ks->cbytes;
+    }
     *ms = ctx->prof_ms[k];
     *n = ctx->prof_n[k];
     *bytes = ctx->prof_bytes[k];
     return FFTDG_OK;
 }
 
-int fftdg_set_chunk(fftdg_ctx *ctx, int32_t n) {
+int fftdg_get_tuning(const fftdg_ctx *ctx, fftdg_tuning *t) {
+    if (!ctx || !t) return FFTDG_E_INVALID;
+    t->configs_per_chunk = ctx->chunk_cfgs;
+    t->energy_xy_direct = ctx->edirect ? 1 : 0;
+    return FFTDG_OK;
+}
+
+int fftdg_set_tuning(fftdg_ctx *ctx, const fftdg_tuning *t) {
     if (!ctx) return FFTDG_E_INVALID;
-    if (n < 1) return set_err(ctx, FFTDG_E_INVALID, "set_chunk: configs_per_chunk must be >= 1");
-    ctx->chunk_cfgs = n;
+    if (!t) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: NULL");
+    if (t->configs_per_chunk < 1) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: configs_per_chunk must be >= 1");
+    if (t->energy_xy_direct != 0 && t->energy_xy_direct != 1)
+        return set_err(ctx, FFTDG_E_INVALID, "set_tuning: energy_xy_direct must be 0 or 1");
+    ctx->chunk_cfgs = t->configs_per_chunk;
+    ctx->edirect = t->energy_xy_direct != 0;
     return FFTDG_OK;
 }
 

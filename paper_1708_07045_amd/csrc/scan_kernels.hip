@@ -38,9 +38,39 @@ template <typename T, int N>
 struct Geo {
     static constexpr int R1 = Shape<N>::R1, R2 = Shape<N>::R2, M = R2 / R1;
     static constexpr int H = N / 2 + 1;  // half-spectrum columns
-    static constexpr int S = H + 1;      // LDS row stride (complex elements)
+    // LDS row stride (complex elements) of the xy kernels: a column pass has
+    // R1 lanes per unit on consecutive rows and the units of a wavefront on
+    // consecutive columns; 2*S = 8 (mod 64) words staggers successive rows
+    // by 8 banks so every bank is hit exactly twice by a wavefront's 512 B
+    // (two cycles, the minimum).
+    static constexpr int S = N == 128 ? 68 : (N == 64 ? 36 : 24);
+    // pad (complex elements per block of R2) of the row-pair exchanges,
+    // moving the lanes of a unit onto distinct bank pairs; the exchange of
+    // rows r, r+1 then spans N + (R1-1)*RPAD <= 2*S elements
+    static constexpr int RPAD = N == 32 ? 0 : 1;
     static constexpr int NP = N * H;     // complex values per half-plane
     static constexpr int U = NT / R1;    // FFT units per workgroup
+    // z-pencil kernels: each wavefront owns PW whole pencils (R1 lanes each);
+    // its exchange region holds N elements per pencil plus PAD complex per
+    // block of R2 elements.
+    static constexpr int PW = 64 / R1;
+    static constexpr int PAD = 8;
+    static constexpr int WREG = N * PW + R1 * PAD;
+};
+
+// Lane layout of the z-pencil kernels: wave w, lane l -> pencil w*PW + l%PW
+// of the tile, FFT lane n1 = l / PW.
+template <int N>
+struct ZLane {
+    int w, n1, pl, p;
+    __device__ ZLane() {
+        constexpr int PW = 64 / Shape<N>::R1;
+        w = threadIdx.x >> 6;
+        const int l = threadIdx.x & 63;
+        n1 = l / PW;
+        pl = l - n1 * PW;
+        p = w * PW + pl;
+    }
 };
 
 __device__ __forceinline__ int pmod(int a, int n) {
@@ -62,6 +92,53 @@ __device__ __forceinline__ long long isqrt_lt(long long rem) {
 template <typename T, int N>
 __device__ __forceinline__ void load_tw(typename Cx<T>::t *tw, const typename Cx<T>::t *g) {
     for (int i = threadIdx.x; i < N; i += NT) tw[i] = g[i];
+}
+
+// Copy one contiguous half-plane [N][H] between global memory and the LDS
+// layout [N][S].  Elements travel in aligned pairs (16 B for FP32) and every
+// load of a thread is issued before the first LDS store, so a plane costs
+// one memory round trip instead of one per element.  g must be 16-byte
+// aligned for FP32 (planes start at multiples of NP, which is even).
+template <typename T, int N, bool TO_LDS>
+__device__ __forceinline__ void plane_copy(typename Cx<T>::t *Pl, typename Cx<T>::t *g) {
+    using C2 = typename Cx<T>::t;
+    constexpr int H = N / 2 + 1, S = Geo<T, N>::S, NP = N * H;
+    constexpr int NPAIR = NP / 2;
+    constexpr int PER = (NPAIR + NT - 1) / NT;
+    struct alignas(2 * sizeof(C2)) Pair {
+        C2 a, b;
+    };
+    Pair v[PER];
+    if (TO_LDS) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int q = threadIdx.x + j * NT;
+            if (q < NPAIR) v[j] = reinterpret_cast<const Pair *>(g)[q];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < PER; ++j) {
+        const int q = threadIdx.x + j * NT;
+        if (q < NPAIR) {
+            const int e0 = 2 * q, e1 = 2 * q + 1;
+            const int y0 = e0 / H, x0 = e0 - y0 * H;
+            const int y1 = e1 / H, x1 = e1 - y1 * H;
+            if (TO_LDS) {
+                Pl[y0 * S + x0] = v[j].a;
+                Pl[y1 * S + x1] = v[j].b;
+            } else {
+                v[j].a = Pl[y0 * S + x0];
+                v[j].b = Pl[y1 * S + x1];
+            }
+        }
+    }
+    if (!TO_LDS) {
+#pragma unroll
+        for (int j = 0; j < PER; ++j) {
+            const int q = threadIdx.x + j * NT;
+            if (q < NPAIR) reinterpret_cast<Pair *>(g)[q] = v[j];
+        }
+    }
 }
 
 // ------------------------------------------------------------------ fills
@@ -167,6 +244,7 @@ __device__ void xy_forward(const Fill &fill, int y0, int Ly, typename Cx<T>::t *
     using C2 = typename Cx<T>::t;
     using G = Geo<T, N>;
     constexpr int R1 = G::R1, R2 = G::R2, M = G::M, S = G::S, H = G::H, U = G::U;
+    static_assert(N + (R1 - 1) * G::RPAD <= 2 * S && H <= S, "plane layout");
     const int unit = threadIdx.x / R1, n1 = threadIdx.x % R1;
     T re[R2], im[R2];
 
@@ -178,15 +256,15 @@ __device__ void xy_forward(const Fill &fill, int y0, int Ly, typename Cx<T>::t *
         const bool live = r < Ly;
         fill.rows(r, n1, re, im, live, r + 1 < Ly);
         C2 *row = Pl + (live ? r * S : 0);
-        fft_unit<T, N, false>(re, im, n1, row, 1, tw, live);
-        __syncthreads();
+        fft_unit<T, N, false>(re, im, n1, row, 1, tw, live, G::RPAD);
+        wave_sync();  // rows r, r+1 are private to this unit during phase A
         if (live) {
 #pragma unroll
             for (int i = 0; i < M; ++i)
 #pragma unroll
                 for (int k1 = 0; k1 < R1; ++k1) row[spec_index<N>(n1, i, k1)] = C2{re[i * R1 + k1], im[i * R1 + k1]};
         }
-        __syncthreads();
+        wave_sync();
         // unpack Z = A + iB (A, B the spectra of rows r and r+1), k = 0..N/2
         constexpr int Q = (N / 2) / R1 + 1;
         C2 A[Q], B[Q];
@@ -199,7 +277,7 @@ __device__ void xy_forward(const Fill &fill, int y0, int Ly, typename Cx<T>::t *
                 B[q] = C2{(T)0.5 * (zk.y + zn.y), (T)-0.5 * (zk.x - zn.x)};
             }
         }
-        __syncthreads();
+        wave_sync();
 #pragma unroll
         for (int q = 0; q < Q; ++q) {
             const int k = n1 + R1 * q;
@@ -234,14 +312,14 @@ __device__ void xy_forward(const Fill &fill, int y0, int Ly, typename Cx<T>::t *
         }
         C2 *col = Pl + (live ? c : 0);
         fft_unit<T, N, false>(re, im, n1, col, S, tw, live);
-        __syncthreads();
+        wave_sync();  // column c (and column N/2 for c = 0) is private to this unit
         if (live) {
 #pragma unroll
             for (int i = 0; i < M; ++i)
 #pragma unroll
                 for (int k1 = 0; k1 < R1; ++k1) col[spec_index<N>(n1, i, k1) * S] = C2{re[i * R1 + k1], im[i * R1 + k1]};
         }
-        __syncthreads();
+        wave_sync();
         constexpr int QY = N / R1;
         C2 F0[QY], F1[QY];
         const bool unpack = live && c == 0;
@@ -254,7 +332,7 @@ __device__ void xy_forward(const Fill &fill, int y0, int Ly, typename Cx<T>::t *
                 F1[q] = C2{(T)0.5 * (x1.y + x2.y), (T)-0.5 * (x1.x - x2.x)};
             }
         }
-        __syncthreads();
+        wave_sync();
 #pragma unroll
         for (int q = 0; q < QY; ++q) {
             if (unpack) {
@@ -267,10 +345,7 @@ __device__ void xy_forward(const Fill &fill, int y0, int Ly, typename Cx<T>::t *
     __syncthreads();
 
     // Phase C: store [ky][kx] contiguously.
-    for (int e = threadIdx.x; e < G::NP; e += NT) {
-        const int ky = e / H, kx = e - ky * H;
-        out[e] = Pl[ky * S + kx];
-    }
+    plane_copy<T, N, false>(Pl, out);
 }
 
 // ------------------------------------------------------------------ kernels
@@ -337,7 +412,7 @@ __global__ __launch_bounds__(NT) void k_lig_fwd_xy(const FwdItem *__restrict__ i
         if (lane == 0) nl = base;
     }
     __syncthreads();
-    const int64_t slot = occ ? (int64_t)3 * c.Le + it.p : (int64_t)it.ch * c.Le + it.p;
+    const int64_t slot = occ ? (int64_t)c.occ_slot0 + it.p : (int64_t)it.ch * c.Le + it.p;
     C2 *out = ws + c.off_fwd + slot * G::NP;
     if (occ) {
         LigOccFill<T, N> f{L.o, nl, y0};
@@ -379,12 +454,15 @@ __global__ __launch_bounds__(NT) void k_rec_z(const typename Cx<T>::t *__restric
     using C2 = typename Cx<T>::t;
     using G = Geo<T, N>;
     constexpr int R1 = G::R1, R2 = G::R2, M = G::M, P = G::U;
-    __shared__ C2 buf[N * P];
+    __shared__ C2 buf[4 * G::WREG];
     __shared__ C2 tw[N];
     load_tw<T, N>(tw, twg);
+    __syncthreads();
     const int ch = blockIdx.x / n_tiles, tile = blockIdx.x % n_tiles;
-    const int n1 = threadIdx.x / P, p = threadIdx.x % P;
-    const int pen = tile * P + p;
+    const ZLane<N> zl;
+    const int n1 = zl.n1;
+    C2 *ex = buf + zl.w * G::WREG + zl.pl;
+    const int pen = tile * P + zl.p;
     const bool ok = pen < G::NP;
     T re[R2], im[R2];
 #pragma unroll
@@ -397,7 +475,7 @@ __global__ __launch_bounds__(NT) void k_rec_z(const typename Cx<T>::t *__restric
             im[i] = v.y;
         }
     }
-    fft_unit<T, N, false>(re, im, n1, buf + p, P, tw, true);
+    fft_unit<T, N, false>(re, im, n1, ex, G::PW, tw, true, G::PAD);
     if (ok) {
 #pragma unroll
         for (int i = 0; i < M; ++i)
@@ -409,74 +487,169 @@ __global__ __launch_bounds__(NT) void k_rec_z(const typename Cx<T>::t *__restric
     }
 }
 
-// z pass of the scan.  Block -> (tile, configuration) with an XCD-aware
-// order: blocks land on the 8 XCDs round-robin, so block b is given the
-// logical index (b % 8) * (nb / 8) + b / 8 and each XCD sweeps a contiguous
-// range of tiles, all configurations of a tile back to back, keeping its
-// share of the receptor spectra in its own L2.
-template <typename T, int N, bool OCC>
+// Placed ligand atom as the fused energy transform uses it.
+template <typename T>
+struct DAtom {
+    int ax, ay, az;
+    T fx, fy, fz;
+    T g[3];
+};
+
+// z pass of the scan.  Block -> (tile of z-pencils, configuration) with an
+// XCD-aware order: blocks land on the 8 XCDs round-robin, so block b is
+// given the logical index (b % 8) * (nb / 8) + b / 8 and each XCD sweeps a
+// contiguous range of tiles, all configurations of a tile back to back,
+// keeping its share of the receptor spectra in its own L2.
+//
+// Energy channels: with EDIRECT the x and y transforms of each ligand plane
+// are evaluated here, per atom, as the DFT of its trilinear corners:
+//   sum_{dx,dy} w_dx w_dy w^(kx (ax+dx) + ky (ay+dy))
+//     = w^(kx ax) ((1-fx) + fx w^kx) * w^(ky ay) ((1-fy) + fy w^ky)
+// (w = exp(-2 pi i / N)), i.e. the xy FFT of the spread plane with its zero
+// inputs pruned; only the two planes floor(uz), floor(uz)+1 receive the
+// atom, with weights 1-fz and fz.  Without EDIRECT the xy-transformed planes
+// come from k_lig_fwd_xy through HBM.  The occupancy channel always comes
+// from k_lig_fwd_xy.  Then: forward FFT along z, product with the receptor
+// spectra summed over the energy channels (Eq. 9, R * conj(L)), inverse FFT
+// along z, store the valid z-translations only.
+template <typename T, int N, bool OCC, bool EDIRECT>
 __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, const int32_t *__restrict__ zcfg,
                                                int nz, int n_tiles, const typename Cx<T>::t *__restrict__ ws,
                                                const typename Cx<T>::t *__restrict__ rspec,
                                                const typename Cx<T>::t *__restrict__ twg,
-                                               typename Cx<T>::t *__restrict__ wsi) {
+                                               typename Cx<T>::t *__restrict__ wsi,
+                                               const int32_t *__restrict__ ulat, const T *__restrict__ gam) {
     using C2 = typename Cx<T>::t;
     using G = Geo<T, N>;
-    constexpr int R1 = G::R1, R2 = G::R2, M = G::M, P = G::U, NP = G::NP;
-    constexpr int NIN = OCC ? 4 : 3;
-    __shared__ C2 buf[N * P];
+    constexpr int R1 = G::R1, R2 = G::R2, M = G::M, P = G::U, NP = G::NP, H = G::H;
+    constexpr int AC = 64;  // atoms per XY table chunk
+    constexpr int PW = G::PW, PAD = G::PAD;
+    __shared__ C2 buf[4 * G::WREG];
     __shared__ C2 tw[N];
+    __shared__ DAtom<T> at[EDIRECT ? MAXA : 1];
+    __shared__ C2 xy[EDIRECT ? AC * P : 1];
     const int nb = gridDim.x, b = blockIdx.x;
     const int L = (nb % 8 == 0) ? (b % 8) * (nb / 8) + b / 8 : b;
     if (L >= n_tiles * nz) return;
     const int tile = L / nz, zi = L % nz;
     const CfgDev c = cfgs[zcfg[zi]];
     load_tw<T, N>(tw, twg);
-    const int n1 = threadIdx.x / P, p = threadIdx.x % P;
+    if (EDIRECT) {
+        for (int a = threadIdx.x; a < c.n_atoms; a += NT) {
+            const int32_t *U = ulat + 3 * (c.u_base + a);
+            DAtom<T> d;
+            d.ax = U[0] >> 16;
+            d.ay = U[1] >> 16;
+            d.az = U[2] >> 16;
+            d.fx = (T)(U[0] & 0xffff) * (T)(1.0 / 65536.0);
+            d.fy = (T)(U[1] & 0xffff) * (T)(1.0 / 65536.0);
+            d.fz = (T)(U[2] & 0xffff) * (T)(1.0 / 65536.0);
+            d.g[0] = gam[3 * (c.atom_base + a)];
+            d.g[1] = gam[3 * (c.atom_base + a) + 1];
+            d.g[2] = gam[3 * (c.atom_base + a) + 2];
+            at[a] = d;
+        }
+    }
+    __syncthreads();
+    const ZLane<N> zl;
+    const int n1 = zl.n1, p = zl.p;
+    C2 *wbuf = buf + zl.w * G::WREG;  // this wave's exchange region
+    C2 *ex = wbuf + zl.pl;
     const int pen = tile * P + p;
     const bool ok = pen < NP;
-    T er[R2], ei[R2], orr[R2], oi[R2];
+    const int nchunk = EDIRECT ? (c.n_atoms + AC - 1) / AC : 0;
+    // element e of this lane's pencil in the wave region
+    auto eaddr = [&](int e) { return e * PW + (e / R2) * PAD; };
+    T er[R2], ei[R2];
 #pragma unroll
-    for (int i = 0; i < R2; ++i) er[i] = ei[i] = orr[i] = oi[i] = (T)0;
-#pragma unroll
-    for (int ch = 0; ch < NIN; ++ch) {
-        const bool occ = ch == 3;
-        const int zs = occ ? c.zo0 : c.ze0, Lz = occ ? c.Lo : c.Le;
-        const C2 *src = ws + c.off_fwd + (int64_t)(occ ? 3 * c.Le : ch * c.Le) * NP + pen;
+    for (int i = 0; i < R2; ++i) er[i] = ei[i] = (T)0;
+#pragma unroll 1
+    for (int ch = 0; ch < 3; ++ch) {
         T re[R2], im[R2];
 #pragma unroll
-        for (int i = 0; i < R2; ++i) {
-            const int s = pmod(n1 + R1 * i - zs, N);
-            re[i] = im[i] = (T)0;
-            if (ok && s < Lz) {
-                const C2 v = src[(int64_t)s * NP];
-                re[i] = v.x;
-                im[i] = v.y;
+        for (int i = 0; i < R2; ++i) re[i] = im[i] = (T)0;
+        if (EDIRECT) {
+            // Lane (n1, p) owns the z-planes n1 + R1*i of pencil p in its wave region.
+            wave_sync();  // previous exchange reads of the region are done
+#pragma unroll
+            for (int i = 0; i < R2; ++i) ex[eaddr(n1 + R1 * i)] = C2{(T)0, (T)0};
+            for (int ck = 0; ck < nchunk; ++ck) {
+                const int a0 = ck * AC, na = min(AC, c.n_atoms - a0);
+                if (ch == 0 || nchunk > 1) {
+                    if (nchunk > 1) __syncthreads();
+                    // XY[a][p] = w^(kx ax)((1-fx) + fx w^kx) * w^(ky ay)((1-fy) + fy w^ky)
+                    for (int e = threadIdx.x; e < na * P; e += NT) {
+                        const int a = e / P, q = e - a * P;
+                        const int pq = tile * P + q;
+                        const int kyq = pq / H, kxq = pq - kyq * H;
+                        const DAtom<T> d = at[a0 + a];
+                        const C2 wx = tw[kxq & (N - 1)], wy = tw[kyq & (N - 1)];
+                        const C2 ex = tw[(kxq * d.ax) & (N - 1)], ey = tw[(kyq * d.ay) & (N - 1)];
+                        const T sxr = (T)1 - d.fx + d.fx * wx.x, sxi = d.fx * wx.y;
+                        const T syr = (T)1 - d.fy + d.fy * wy.x, syi = d.fy * wy.y;
+                        const T xr = ex.x * sxr - ex.y * sxi, xi = ex.x * sxi + ex.y * sxr;
+                        const T yr = ey.x * syr - ey.y * syi, yi = ey.x * syi + ey.y * syr;
+                        xy[a * P + q] = C2{xr * yr - xi * yi, xr * yi + xi * yr};
+                    }
+                    __syncthreads();
+                }
+                for (int a = 0; a < na; ++a) {
+                    const DAtom<T> d = at[a0 + a];
+                    const int za = d.az, zb = d.az + 1;
+                    const bool ha = (za & (R1 - 1)) == n1, hb = (zb & (R1 - 1)) == n1;
+                    if (!ha && !hb) continue;
+                    const C2 v = xy[a * P + p];
+                    const T g = d.g[ch];
+                    if (ha) {
+                        C2 &t = ex[eaddr(za & (N - 1))];
+                        const T w = g * ((T)1 - d.fz);
+                        t.x += w * v.x;
+                        t.y += w * v.y;
+                    }
+                    if (hb) {
+                        C2 &t = ex[eaddr(zb & (N - 1))];
+                        const T w = g * d.fz;
+                        t.x += w * v.x;
+                        t.y += w * v.y;
+                    }
+                }
+            }
+            if (ok) {
+#pragma unroll
+                for (int i = 0; i < R2; ++i) {
+                    const C2 v = ex[eaddr(n1 + R1 * i)];
+                    re[i] = v.x;
+                    im[i] = v.y;
+                }
+            }
+        } else {
+            // branch-free: every lane loads an in-bounds plane (clamped) and
+            // keeps it only inside the channel's plane window
+            const C2 *src = ws + c.off_fwd + (int64_t)ch * c.Le * NP + (ok ? pen : 0);
+#pragma unroll
+            for (int i = 0; i < R2; ++i) {
+                const int s = pmod(n1 + R1 * i - c.ze0, N);
+                const bool in = ok && s < c.Le;
+                const C2 v = src[(in ? s : 0) * NP];
+                re[i] = in ? v.x : (T)0;
+                im[i] = in ? v.y : (T)0;
             }
         }
-        fft_unit<T, N, false>(re, im, n1, buf + p, P, tw, true);
-        const C2 *R = rspec + (int64_t)ch * N * NP + pen;
+        fft_unit<T, N, false>(re, im, n1, ex, PW, tw, true, PAD);
+        const C2 *R = rspec + (int64_t)ch * N * NP + (ok ? pen : 0);
 #pragma unroll
         for (int i = 0; i < M; ++i)
 #pragma unroll
             for (int k1 = 0; k1 < R1; ++k1) {
                 const int k = spec_index<N>(n1, i, k1);
-                const C2 r = ok ? R[(int64_t)k * NP] : C2{(T)0, (T)0};
+                const C2 r = R[k * NP];
                 const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
-                // R * conj(L)
-                const T pr = r.x * lr + r.y * li;
-                const T pi = r.y * lr - r.x * li;
-                if (occ) {
-                    orr[i * R1 + k1] += pr;
-                    oi[i * R1 + k1] += pi;
-                } else {
-                    er[i * R1 + k1] += pr;
-                    ei[i * R1 + k1] += pi;
-                }
+                er[i * R1 + k1] += r.x * lr + r.y * li;  // R * conj(L)
+                ei[i * R1 + k1] += r.y * lr - r.x * li;
             }
     }
     const int Vz = c.V[2];
-    fft_unit_rev<T, N, true>(er, ei, n1, buf + p, P, tw, true);
+    fft_unit_rev<T, N, true>(er, ei, n1, ex, PW, tw, true, PAD);
     C2 *dst = wsi + c.off_inv + pen;
 #pragma unroll
     for (int i = 0; i < R2; ++i) {
@@ -484,12 +657,34 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
         if (ok && tz < Vz) dst[(int64_t)tz * NP] = C2{er[i], ei[i]};
     }
     if (OCC) {
-        fft_unit_rev<T, N, true>(orr, oi, n1, buf + p, P, tw, true);
+        T re[R2], im[R2];
+        const C2 *src = ws + c.off_fwd + (int64_t)c.occ_slot0 * NP + (ok ? pen : 0);
+#pragma unroll
+        for (int i = 0; i < R2; ++i) {
+            const int s = pmod(n1 + R1 * i - c.zo0, N);
+            const bool in = ok && s < c.Lo;
+            const C2 v = src[(in ? s : 0) * NP];
+            re[i] = in ? v.x : (T)0;
+            im[i] = in ? v.y : (T)0;
+        }
+        fft_unit<T, N, false>(re, im, n1, ex, PW, tw, true, PAD);
+        const C2 *R = rspec + (int64_t)3 * N * NP + (ok ? pen : 0);
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) {
+                const int k = spec_index<N>(n1, i, k1);
+                const C2 r = R[k * NP];
+                const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
+                re[i * R1 + k1] = r.x * lr + r.y * li;
+                im[i * R1 + k1] = r.y * lr - r.x * li;
+            }
+        fft_unit_rev<T, N, true>(re, im, n1, ex, PW, tw, true, PAD);
         dst += (int64_t)Vz * NP;
 #pragma unroll
         for (int i = 0; i < R2; ++i) {
             const int tz = n1 + R1 * i;
-            if (ok && tz < Vz) dst[(int64_t)tz * NP] = C2{orr[i], oi[i]};
+            if (ok && tz < Vz) dst[(int64_t)tz * NP] = C2{re[i], im[i]};
         }
     }
 }
@@ -536,15 +731,19 @@ struct LseAcc {
 };
 
 // Inverse xy + clash mask + Eq. 2 partials for one valid z-translation.
+// In a scan (no energy export) the energy channel of a plane whose every
+// translation clashes is not transformed: those energies are infinite by the
+// method and never enter Eq. 2.  e_count counts energy planes transformed.
 template <typename T, int N, bool OCC>
 __global__ __launch_bounds__(NT) void k_inv_xy_lse(const InvItem *__restrict__ items, const CfgDev *__restrict__ cfgs,
                                                     const typename Cx<T>::t *__restrict__ wsi, T beta, T inv_n3,
                                                     const typename Cx<T>::t *__restrict__ twg,
                                                     PlanePartial<T> *__restrict__ pp, T *__restrict__ psi_out,
-                                                    uint8_t *__restrict__ clash_out) {
+                                                    uint8_t *__restrict__ clash_out, unsigned int *__restrict__ e_count) {
     using C2 = typename Cx<T>::t;
     using G = Geo<T, N>;
     constexpr int R1 = G::R1, R2 = G::R2, M = G::M, S = G::S, U = G::U, NP = G::NP;
+    static_assert(N + (R1 - 1) * G::RPAD <= 2 * S, "row-pair exchange must fit in two rows");
     __shared__ C2 Pl[N * S];
     __shared__ C2 tw[N];
     __shared__ uint32_t cmask[(N * N + 31) / 32];
@@ -561,11 +760,15 @@ __global__ __launch_bounds__(NT) void k_inv_xy_lse(const InvItem *__restrict__ i
     for (int pass = 0; pass < NCH; ++pass) {
         const int och = OCC ? 1 - pass : 0;  // occupancy first
         const C2 *src = wsi + c.off_inv + ((int64_t)och * Vz + tz) * NP;
-        __syncthreads();
-        for (int e = threadIdx.x; e < NP; e += NT) {
-            const int ky = e / G::H, kx = e - ky * G::H;
-            Pl[ky * S + kx] = src[e];
+        if (OCC && och == 0 && !psi_out) {
+            // any clash-free translation on this plane?
+            int free_local = 0;
+            for (int e = threadIdx.x; e < Vy * Vx; e += NT) free_local |= !((cmask[e >> 5] >> (e & 31)) & 1u);
+            if (!__syncthreads_or(free_local)) break;
         }
+        if (och == 0 && threadIdx.x == 0 && e_count) atomicAdd(e_count, 1u);
+        __syncthreads();
+        plane_copy<T, N, true>(Pl, const_cast<C2 *>(src));
         __syncthreads();
         T re[R2], im[R2];
         // inverse y on columns (kx = 0 and N/2 packed into column 0), keep y < Vy
@@ -591,7 +794,7 @@ __global__ __launch_bounds__(NT) void k_inv_xy_lse(const InvItem *__restrict__ i
             }
             C2 *cp = Pl + (live ? col : 0);
             fft_unit<T, N, true>(re, im, n1, cp, S, tw, live);
-            __syncthreads();
+            wave_sync();  // column col (and N/2 for col = 0) is private to this unit
             if (live) {
 #pragma unroll
                 for (int i = 0; i < M; ++i)
@@ -640,7 +843,7 @@ __global__ __launch_bounds__(NT) void k_inv_xy_lse(const InvItem *__restrict__ i
                     im[i] = a.y + bq.x;
                 }
             }
-            fft_unit<T, N, true>(re, im, n1, row, 1, tw, live);
+            fft_unit<T, N, true>(re, im, n1, row, 1, tw, live, G::RPAD);
             if (live) {
 #pragma unroll
                 for (int i = 0; i < M; ++i)
@@ -908,30 +1111,36 @@ struct Launch {
                            thr, (const C2 *)tw, (C2 *)ws);
         return hipGetLastError();
     }
-    static hipError_t zprod(hipStream_t st, bool occ, const CfgDev *cfgs, const int32_t *zcfg, int nz,
-                            const void *ws, const void *rspec, const void *tw, void *wsi) {
+    static hipError_t zprod(hipStream_t st, bool occ, bool edirect, const CfgDev *cfgs, const int32_t *zcfg,
+                            int nz, const void *ws, const void *rspec, const void *tw, void *wsi,
+                            const int32_t *ulat, const void *gam) {
         if (nz <= 0) return hipSuccess;
         const int n_tiles = (G::NP + G::U - 1) / G::U;
         long long nb = (long long)n_tiles * nz;
         nb = (nb + 7) / 8 * 8;
-        if (occ)
-            hipLaunchKernelGGL((k_zprod<T, N, true>), dim3((unsigned)nb), dim3(NT), 0, st, cfgs, zcfg, nz, n_tiles,
-                               (const C2 *)ws, (const C2 *)rspec, (const C2 *)tw, (C2 *)wsi);
-        else
-            hipLaunchKernelGGL((k_zprod<T, N, false>), dim3((unsigned)nb), dim3(NT), 0, st, cfgs, zcfg, nz, n_tiles,
-                               (const C2 *)ws, (const C2 *)rspec, (const C2 *)tw, (C2 *)wsi);
+#define FFTDG_ZPROD(O, E)                                                                                 \
+    hipLaunchKernelGGL((k_zprod<T, N, O, E>), dim3((unsigned)nb), dim3(NT), 0, st, cfgs, zcfg, nz, n_tiles, \
+                       (const C2 *)ws, (const C2 *)rspec, (const C2 *)tw, (C2 *)wsi, ulat, (const T *)gam)
+        if (occ && edirect) FFTDG_ZPROD(true, true);
+        else if (occ) FFTDG_ZPROD(true, false);
+        else if (edirect) FFTDG_ZPROD(false, true);
+        else FFTDG_ZPROD(false, false);
+#undef FFTDG_ZPROD
         return hipGetLastError();
     }
     static hipError_t inv(hipStream_t st, bool occ, const InvItem *items, int n_items, const CfgDev *cfgs,
-                          const void *wsi, double beta, const void *tw, void *pp, void *psi_out, uint8_t *clash_out) {
+                          const void *wsi, double beta, const void *tw, void *pp, void *psi_out, uint8_t *clash_out,
+                          unsigned int *e_count) {
         if (n_items <= 0) return hipSuccess;
         const T b = (T)beta, s = (T)(1.0 / ((double)N * N * N));
         if (occ)
             hipLaunchKernelGGL((k_inv_xy_lse<T, N, true>), dim3(n_items), dim3(NT), 0, st, items, cfgs,
-                               (const C2 *)wsi, b, s, (const C2 *)tw, (PlanePartial<T> *)pp, (T *)psi_out, clash_out);
+                               (const C2 *)wsi, b, s, (const C2 *)tw, (PlanePartial<T> *)pp, (T *)psi_out, clash_out,
+                               e_count);
         else
             hipLaunchKernelGGL((k_inv_xy_lse<T, N, false>), dim3(n_items), dim3(NT), 0, st, items, cfgs,
-                               (const C2 *)wsi, b, s, (const C2 *)tw, (PlanePartial<T> *)pp, (T *)psi_out, clash_out);
+                               (const C2 *)wsi, b, s, (const C2 *)tw, (PlanePartial<T> *)pp, (T *)psi_out, clash_out,
+                               e_count);
         return hipGetLastError();
     }
     static hipError_t merge(hipStream_t st, const CfgDev *cfgs, int n_cfg, const void *pp, fftdg_partial *out) {

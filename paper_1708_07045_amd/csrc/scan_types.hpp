@@ -20,6 +20,8 @@ struct CfgDev {
     int32_t yo0, Lyo;    // occupancy channel: first row and count
     int32_t pp_base;     // first plane-partial slot (one per valid z translation)
     int32_t scanned;     // 1 if the configuration is scanned in this call
+    int32_t occ_slot0;   // forward-plane slot of the first occupancy plane
+    int32_t pad0;
     int64_t off_fwd;     // complex-element offset of its forward planes
     int64_t off_inv;     // complex-element offset of its inverse planes
 };

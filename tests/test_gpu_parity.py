@@ -27,10 +27,12 @@ def _ctx(w, precision=None):
     return fd.FFTDG.from_workload(w, precision=precision)
 
 
-def _gpu_setup(w, precision=None, snaps=None):
+def _gpu_setup(w, precision=None, snaps=None, **tuning):
     """Context with GPU-built receptor grids for all (or the chosen) snapshots."""
     import torch
     ctx = _ctx(w, precision)
+    if tuning:
+        ctx.set_tuning(**tuning)
     snaps = range(w.receptor.n_snap) if snaps is None else snaps
     gs, os_ = [], []
     for s in snaps:
@@ -91,8 +93,8 @@ def test_placement_bit_exact():
 
 
 # ------------------------------------------------------------------ energies
-def _energy_parity(w, cfgs, precision, tol, grids_o=None):
-    ctx, grids, occ = _gpu_setup(w, precision)
+def _energy_parity(w, cfgs, precision, tol, grids_o=None, **tuning):
+    ctx, grids, occ = _gpu_setup(w, precision, **tuning)
     b = _batch(w)
     go, oo = grids_o if grids_o is not None else oracle.receptor_grids(w)
     worst = 0.0
@@ -118,9 +120,10 @@ def test_energy_c1_fp64_cap():
     _energy_parity(w, [0, 1, 17, 42, 99], "f64", TOL_F64)
 
 
-def test_energy_c2_fp32_occ():
+@pytest.mark.parametrize("edirect", [1, 0])
+def test_energy_c2_fp32_occ(edirect):
     w = synth.config2(n_rot=12, n_conf=8)
-    _energy_parity(w, [0, 13, 27, 40, 66, 95], "f32", TOL_F32)
+    _energy_parity(w, [0, 13, 27, 40, 66, 95], "f32", TOL_F32, energy_xy_direct=edirect)
 
 
 def test_energy_c2_fp32_cap_and_fp64_n64():
@@ -129,7 +132,8 @@ def test_energy_c2_fp32_cap_and_fp64_n64():
     w.n_rec, w.n_fft = 60, 64
     w.origin = -0.5 * (60 - 1) * w.h * np.ones(3)
     for prec, tol in [("f32", TOL_F32), ("f64", TOL_F64)]:
-        _energy_parity(w, [0, 3, 5], prec, tol)
+        for ed in (1, 0):
+            _energy_parity(w, [0, 3, 5], prec, tol, energy_xy_direct=ed)
     w.clash_mode = "cap"
     _energy_parity(w, [1, 6], "f32", 2e-5)
 
@@ -157,9 +161,9 @@ def test_single_point_charge_gpu():
 
 
 # ------------------------------------------------------------------ partials, B, dG
-def _scan_parity(w, precision, tolB, ncheck=None):
+def _scan_parity(w, precision, tolB, **tuning):
     import torch
-    ctx, grids, occ = _gpu_setup(w, precision)
+    ctx, grids, occ = _gpu_setup(w, precision, **tuning)
     b = _batch(w)
     _announce(f"scan {w.name[:3]} {precision} n_cfg={b.n_cfg} n_snap={w.receptor.n_snap}")
     buf = ctx.scan(b, w.T)
@@ -191,13 +195,15 @@ def _scan_parity(w, precision, tolB, ncheck=None):
     return P, B, res
 
 
-def test_scan_c1_fp64():
-    _scan_parity(synth.config1(), "f64", 1e-8)
+@pytest.mark.parametrize("edirect", [1, 0])
+def test_scan_c1_fp64(edirect):
+    _scan_parity(synth.config1(), "f64", 1e-8, energy_xy_direct=edirect)
 
 
-def test_scan_c2_subset_fp32():
+@pytest.mark.parametrize("edirect,chunk", [(1, 256), (0, 256), (1, 7)])
+def test_scan_c2_subset_fp32(edirect, chunk):
     w = synth.subset(synth.config2(), 96, stride=83)
-    _scan_parity(w, "f32", 0.01)
+    _scan_parity(w, "f32", 0.01, energy_xy_direct=edirect, configs_per_chunk=chunk)
 
 
 def test_scan_batched_uneven_ligands_two_snapshots():
