@@ -226,7 +226,7 @@ int fftdg_profile_read(fftdg_ctx *ctx, int32_t kernel_id, double *ms_host, int64
  * the FP32 transforms):
  *   configs_per_chunk  configurations whose forward and inverse planes share
  *                      device workspace at one time (>= 1, default 256);
-^ *   energy_xy_direct   1: the x/y transforms of the three energy
+ *   energy_xy_direct   1: the x/y transforms of the three energy
  *                      channels are evaluated per atom inside the z-pencil
  *                      kernel (the xy FFT of the trilinearly spread plane
  *                      with its zero inputs pruned); 0: they go through the

@@ -17,15 +17,17 @@ struct KernelSet {
     // -> rspec [n_ch][N][np]; rxy is scratch [n_ch][n_rec][np]
     hipError_t (*rec_spectra)(hipStream_t, const void *grids, const uint8_t *occ, int n_rec, int n_ch,
                               const void *tw, void *rxy, void *rspec);
-    hipError_t (*fwd)(hipStream_t, const FwdItem *items, int n_items, const CfgDev *cfgs, const int32_t *ulat,
-                      const void *gam, const double *thr, const void *tw, void *ws);
+    // one block per forward plane; fwd_off[0..n_cfg] running plane counts
+    hipError_t (*fwd)(hipStream_t, const int32_t *fwd_off, int n_cfg, int n_items, const CfgDev *cfgs,
+                      const int32_t *ulat, const void *gam, const double *thr, const void *tw, void *ws);
     // edirect: energy-channel xy transforms evaluated per atom inside the
     // kernel (else read from forward planes written by fwd)
     hipError_t (*zprod)(hipStream_t, bool occ, bool edirect, const CfgDev *cfgs, const int32_t *zcfg, int nz,
                         const void *ws, const void *rspec, const void *tw, void *wsi, const int32_t *ulat,
                         const void *gam);
     // e_count (nullable): incremented once per energy plane transformed
-    hipError_t (*inv)(hipStream_t, bool occ, const InvItem *items, int n_items, const CfgDev *cfgs,
+    // one block per valid z translation; inv_off[0..n_cfg] running counts
+    hipError_t (*inv)(hipStream_t, bool occ, const int32_t *inv_off, int n_cfg, int n_items, const CfgDev *cfgs,
                       const void *wsi, double beta, const void *tw, void *pp, void *psi_out,
                       uint8_t *clash_out, unsigned int *e_count);
     hipError_t (*merge)(hipStream_t, const CfgDev *cfgs, int n_cfg, const void *pp, fftdg_partial *out);

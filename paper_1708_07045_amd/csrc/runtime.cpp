@@ -206,15 +206,14 @@ struct Plan {
     // chunks: contiguous configuration ranges
     struct Chunk {
         int c0, c1;               // configurations [c0, c1)
-        size_t fwd0, nfwd;        // fwd items
-        size_t inv0, ninv;        // inv items
+        size_t off0;              // start of this chunk's fwd_off / inv_off (c1-c0+1 entries each)
+        size_t nfwd, ninv;        // forward planes, valid z translations
         size_t z0, nz;            // scanned configurations (local indices)
         int64_t ws_fwd, ws_inv;   // complex elements used
         int pp;                   // plane partial slots used
     };
     std::vector<Chunk> chunks;
-    std::vector<FwdItem> fwd;
-    std::vector<InvItem> inv;
+    std::vector<int32_t> fwd_off, inv_off;
     std::vector<int32_t> zcfg;
     int64_t max_fwd = 0, max_inv = 0;
     int max_pp = 0;
@@ -395,9 +394,9 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
     while (c < ncfg) {
         Plan::Chunk ch{};
         ch.c0 = c;
-        ch.fwd0 = P.fwd.size();
-        ch.inv0 = P.inv.size();
+        ch.off0 = P.fwd_off.size();
         ch.z0 = P.zcfg.size();
+        int32_t nf = 0, ni = 0;
         int nscan = 0;
         int64_t wf = 0, wi = 0;
         int pp = 0;
@@ -413,12 +412,10 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
                 d.off_inv = wi;
                 d.pp_base = pp;
                 const int local = c - ch.c0;
-                if (!ctx->edirect)
-                    for (int k = 0; k < 3; ++k)
-                        for (int p = 0; p < d.Le; ++p) P.fwd.push_back(FwdItem{local, k, p, 0});
-                if (occ)
-                    for (int p = 0; p < d.Lo; ++p) P.fwd.push_back(FwdItem{local, 3, p, 0});
-                for (int tz = 0; tz < d.V[2]; ++tz) P.inv.push_back(InvItem{local, tz});
+                P.fwd_off.push_back(nf);
+                P.inv_off.push_back(ni);
+                nf += e_planes + (occ ? d.Lo : 0);
+                ni += d.V[2];
                 P.zcfg.push_back(local);
                 wf += f;
                 wi += iv;
@@ -426,13 +423,18 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
                 ++nscan;
             } else {
                 d.off_fwd = d.off_inv = 0;
-                d.pp_base = 0;
+                d.pp_base = pp;
+                d.occ_slot0 = 0;
+                P.fwd_off.push_back(nf);
+                P.inv_off.push_back(ni);
             }
             ++c;
         }
         ch.c1 = c;
-        ch.nfwd = P.fwd.size() - ch.fwd0;
-        ch.ninv = P.inv.size() - ch.inv0;
+        P.fwd_off.push_back(nf);
+        P.inv_off.push_back(ni);
+        ch.nfwd = nf;
+        ch.ninv = ni;
         ch.nz = P.zcfg.size() - ch.z0;
         ch.ws_fwd = wf;
         ch.ws_inv = wi;
@@ -471,8 +473,8 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     const size_t o_cfg = 0;
     const size_t o_u = align256(o_cfg + sizeof(CfgDev) * P.cfg.size());
     const size_t o_fwd = align256(o_u + sizeof(int32_t) * P.U.size());
-    const size_t o_inv = align256(o_fwd + sizeof(FwdItem) * P.fwd.size());
-    const size_t o_z = align256(o_inv + sizeof(InvItem) * P.inv.size());
+    const size_t o_inv = align256(o_fwd + sizeof(int32_t) * P.fwd_off.size());
+    const size_t o_z = align256(o_inv + sizeof(int32_t) * P.inv_off.size());
     const size_t o_gam = align256(o_z + sizeof(int32_t) * P.zcfg.size());
     const size_t o_thr = align256(o_gam + tsz * 3 * na);
     const size_t total = align256(o_thr + sizeof(double) * na);
@@ -482,8 +484,8 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     char *h = (char *)ctx->pinned;
     std::memcpy(h + o_cfg, P.cfg.data(), sizeof(CfgDev) * P.cfg.size());
     std::memcpy(h + o_u, P.U.data(), sizeof(int32_t) * P.U.size());
-    if (!P.fwd.empty()) std::memcpy(h + o_fwd, P.fwd.data(), sizeof(FwdItem) * P.fwd.size());
-    if (!P.inv.empty()) std::memcpy(h + o_inv, P.inv.data(), sizeof(InvItem) * P.inv.size());
+    std::memcpy(h + o_fwd, P.fwd_off.data(), sizeof(int32_t) * P.fwd_off.size());
+    std::memcpy(h + o_inv, P.inv_off.data(), sizeof(int32_t) * P.inv_off.size());
     if (!P.zcfg.empty()) std::memcpy(h + o_z, P.zcfg.data(), sizeof(int32_t) * P.zcfg.size());
     if (g.precision == FFTDG_F32)
         fill_gamma<float>(b, (float *)(h + o_gam));
@@ -501,8 +503,8 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     char *d = (char *)ctx->tables.p;
     const CfgDev *dcfg = (const CfgDev *)(d + o_cfg);
     const int32_t *du = (const int32_t *)(d + o_u);
-    const FwdItem *dfwd = (const FwdItem *)(d + o_fwd);
-    const InvItem *dinv = (const InvItem *)(d + o_inv);
+    const int32_t *dfwd = (const int32_t *)(d + o_fwd);
+    const int32_t *dinv = (const int32_t *)(d + o_inv);
     const int32_t *dz = (const int32_t *)(d + o_z);
     const void *dgam = (const void *)(d + o_gam);
     const double *dthr = (const double *)(d + o_thr);
@@ -519,8 +521,8 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
         const double b_fwd = (double)ch.ws_fwd * cb;
         const double b_inv = (double)ch.ws_inv * cb;
         HIPCHK(ctx, timed(ctx, FFTDG_K_FWD, b_fwd, [&] {
-                   return ks->fwd(ctx->stream, dfwd + ch.fwd0, (int)ch.nfwd, ccfg, du, dgam, dthr, ctx->tw.p,
-                                  ctx->ws_fwd.p);
+                   return ks->fwd(ctx->stream, dfwd + ch.off0, ch.c1 - ch.c0, (int)ch.nfwd, ccfg, du, dgam, dthr,
+                                  ctx->tw.p, ctx->ws_fwd.p);
                }));
         for (int s = 0; s < ctx->n_snap; ++s) {
             if (snap_only >= 0 && s != snap_only) continue;
@@ -533,7 +535,7 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
             // plane has a clash-free translation (counted on the device)
             const double b_inv_fixed = (occ ? 0.5 * b_inv : 0.0) + pb * ch.pp;
             HIPCHK(ctx, timed(ctx, FFTDG_K_INV, b_inv_fixed, [&] {
-                       return ks->inv(ctx->stream, occ, dinv + ch.inv0, (int)ch.ninv, ccfg, ctx->ws_inv.p, beta,
+                       return ks->inv(ctx->stream, occ, dinv + ch.off0, ch.c1 - ch.c0, (int)ch.ninv, ccfg, ctx->ws_inv.p, beta,
                                       ctx->tw.p, ctx->pp.p, psi_out, clash_out,
                                       ctx->prof ? (unsigned int *)ctx->prof_cnt.p : nullptr);
                    }));

@@ -89,9 +89,42 @@ __device__ __forceinline__ long long isqrt_lt(long long rem) {
     return s;
 }
 
+// Largest i in [0, n) with off[i] <= b, for a running count off[0..n]
+// (off[0] = 0 <= b < off[n]); configurations without work repeat a value.
+__device__ __forceinline__ int find_cfg(const int32_t *__restrict__ off, int n, int b) {
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
 template <typename T, int N>
 __device__ __forceinline__ void load_tw(typename Cx<T>::t *tw, const typename Cx<T>::t *g) {
     for (int i = threadIdx.x; i < N; i += NT) tw[i] = g[i];
+}
+
+// Raw buffer access (stride 0): the descriptor covers [base, base + bytes);
+// reads at offsets beyond it return 0 and writes there are dropped by the
+// hardware, which the z kernel uses to window planes without branches.
+// Every descriptor spans only memory owned by the configuration at hand.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void *base, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(base), (short)0, bytes, 0x00020000);
+}
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ float2 buf_load(__amdgpu_buffer_rsrc_t r, int off, float2 *) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, 0, 0));
+}
+__device__ __forceinline__ double2 buf_load(__amdgpu_buffer_rsrc_t r, int off, double2 *) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, float2 v) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
+}
+__device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, double2 v) {
+    __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u32x4, v), r, off, 0, 0);
 }
 
 // Copy one contiguous half-plane [N][H] between global memory and the LDS
@@ -158,6 +191,15 @@ template <typename T, int N>
 struct LigEnergyFill {
     const EAtom<T> *list;
     int n, y0;
+    // does any atom reach storage rows r or r+1?
+    __device__ bool any(int r) const {
+        const int ya = y0 + r;
+        for (int a = 0; a < n; ++a) {
+            const int ay = list[a].ay;
+            if (ay + 1 >= ya && ay <= ya + 1) return true;
+        }
+        return false;
+    }
     __device__ void rows(int r, int n1, T *re, T *im, bool live, bool has_b) const {
         constexpr int R1 = Shape<N>::R1, R2 = Shape<N>::R2;
 #pragma unroll
@@ -186,6 +228,7 @@ template <typename T, int N>
 struct LigOccFill {
     const OAtom *list;
     int n, y0;
+    __device__ bool any(int) const { return n > 0; }
     __device__ void rows(int r, int n1, T *re, T *im, bool live, bool has_b) const {
         constexpr int R1 = Shape<N>::R1, R2 = Shape<N>::R2;
 #pragma unroll
@@ -223,6 +266,7 @@ template <typename T, int N, typename Src>
 struct DenseFill {
     const Src *plane;  // [n_rec][n_rec] plane of the receptor grid
     int n_rec;
+    __device__ bool any(int) const { return true; }
     __device__ void rows(int r, int n1, T *re, T *im, bool live, bool has_b) const {
         constexpr int R1 = Shape<N>::R1, R2 = Shape<N>::R2;
 #pragma unroll
@@ -253,10 +297,20 @@ __device__ void xy_forward(const Fill &fill, int y0, int Ly, typename Cx<T>::t *
     const int rounds_a = (npairs + U - 1) / U;
     for (int rd = 0; rd < rounds_a; ++rd) {
         const int r = 2 * (unit + U * rd);
-        const bool live = r < Ly;
-        fill.rows(r, n1, re, im, live, r + 1 < Ly);
-        C2 *row = Pl + (live ? r * S : 0);
-        fft_unit<T, N, false>(re, im, n1, row, 1, tw, live, G::RPAD);
+        const bool inside = r < Ly;
+        // a pair of all-zero rows transforms to zeros: skip its FFT
+        const bool live = inside && fill.any(r);
+        C2 *row = Pl + (inside ? r * S : 0);
+        if (inside && !live) {
+            for (int k = n1; k <= N / 2; k += R1) {
+                row[k] = C2{(T)0, (T)0};
+                row[S + k] = C2{(T)0, (T)0};
+            }
+        }
+        if (live) {  // a wavefront whose units all hold zero pairs skips the transform
+            fill.rows(r, n1, re, im, live, r + 1 < Ly);
+            fft_unit<T, N, false>(re, im, n1, row, 1, tw, live, G::RPAD);
+        }
         wave_sync();  // rows r, r+1 are private to this unit during phase A
         if (live) {
 #pragma unroll
@@ -350,7 +404,7 @@ __device__ void xy_forward(const Fill &fill, int y0, int Ly, typename Cx<T>::t *
 
 // ------------------------------------------------------------------ kernels
 template <typename T, int N>
-__global__ __launch_bounds__(NT) void k_lig_fwd_xy(const FwdItem *__restrict__ items,
+__global__ __launch_bounds__(NT) void k_lig_fwd_xy(const int32_t *__restrict__ fwd_off, int n_cfg,
                                                     const CfgDev *__restrict__ cfgs,
                                                     const int32_t *__restrict__ ulat,
                                                     const T *__restrict__ gam,
@@ -366,10 +420,14 @@ __global__ __launch_bounds__(NT) void k_lig_fwd_xy(const FwdItem *__restrict__ i
         OAtom o[MAXA];
     } L;
     __shared__ int nl;
-    const FwdItem it = items[blockIdx.x];
-    const CfgDev c = cfgs[it.cfg];
+    const int ic = find_cfg(fwd_off, n_cfg, (int)blockIdx.x);
+    const CfgDev c = cfgs[ic];
+    const int slot = (int)blockIdx.x - fwd_off[ic];
+    const bool occ = slot >= c.occ_slot0;
+    struct {
+        int ch, p;
+    } it = {occ ? 3 : slot / c.Le, occ ? slot - c.occ_slot0 : slot % c.Le};
     load_tw<T, N>(tw, twg);
-    const bool occ = it.ch == 3;
     const int zt = (occ ? c.zo0 : c.ze0) + it.p;
     const int y0 = occ ? c.yo0 : c.ye0;
     const int Ly = occ ? c.Lyo : c.Lye;
@@ -412,8 +470,7 @@ __global__ __launch_bounds__(NT) void k_lig_fwd_xy(const FwdItem *__restrict__ i
         if (lane == 0) nl = base;
     }
     __syncthreads();
-    const int64_t slot = occ ? (int64_t)c.occ_slot0 + it.p : (int64_t)it.ch * c.Le + it.p;
-    C2 *out = ws + c.off_fwd + slot * G::NP;
+    C2 *out = ws + c.off_fwd + (int64_t)slot * G::NP;
     if (occ) {
         LigOccFill<T, N> f{L.o, nl, y0};
         xy_forward<T, N>(f, y0, Ly, Pl, tw, out);
@@ -623,69 +680,68 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
                 }
             }
         } else {
-            // branch-free: every lane loads an in-bounds plane (clamped) and
-            // keeps it only inside the channel's plane window
-            const C2 *src = ws + c.off_fwd + (int64_t)ch * c.Le * NP + (ok ? pen : 0);
+            // planes outside the channel's window lie beyond the descriptor
+            // and read as zero
+            const auto rs = make_rsrc(ws + c.off_fwd + (int64_t)ch * c.Le * NP, c.Le * NP * (int)sizeof(C2));
+            const int po = ok ? pen : NP * N;
 #pragma unroll
             for (int i = 0; i < R2; ++i) {
                 const int s = pmod(n1 + R1 * i - c.ze0, N);
-                const bool in = ok && s < c.Le;
-                const C2 v = src[(in ? s : 0) * NP];
-                re[i] = in ? v.x : (T)0;
-                im[i] = in ? v.y : (T)0;
+                const C2 v = buf_load(rs, (s * NP + po) * (int)sizeof(C2), (C2 *)nullptr);
+                re[i] = v.x;
+                im[i] = v.y;
             }
         }
         fft_unit<T, N, false>(re, im, n1, ex, PW, tw, true, PAD);
-        const C2 *R = rspec + (int64_t)ch * N * NP + (ok ? pen : 0);
+        const auto rr = make_rsrc(rspec + (int64_t)ch * N * NP, N * NP * (int)sizeof(C2));
 #pragma unroll
         for (int i = 0; i < M; ++i)
 #pragma unroll
             for (int k1 = 0; k1 < R1; ++k1) {
                 const int k = spec_index<N>(n1, i, k1);
-                const C2 r = R[k * NP];
+                const C2 r = buf_load(rr, (k * NP + (ok ? pen : 0)) * (int)sizeof(C2), (C2 *)nullptr);
                 const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
                 er[i * R1 + k1] += r.x * lr + r.y * li;  // R * conj(L)
                 ei[i * R1 + k1] += r.y * lr - r.x * li;
             }
     }
     const int Vz = c.V[2];
+    const int po = ok ? pen : NP * N;  // out of every descriptor's range
     fft_unit_rev<T, N, true>(er, ei, n1, ex, PW, tw, true, PAD);
-    C2 *dst = wsi + c.off_inv + pen;
+    {
+        // valid z-translations only: tz >= Vz lies beyond the descriptor
+        const auto rd = make_rsrc(wsi + c.off_inv, Vz * NP * (int)sizeof(C2));
 #pragma unroll
-    for (int i = 0; i < R2; ++i) {
-        const int tz = n1 + R1 * i;
-        if (ok && tz < Vz) dst[(int64_t)tz * NP] = C2{er[i], ei[i]};
+        for (int i = 0; i < R2; ++i)
+            buf_store(rd, ((n1 + R1 * i) * NP + po) * (int)sizeof(C2), C2{er[i], ei[i]});
     }
     if (OCC) {
         T re[R2], im[R2];
-        const C2 *src = ws + c.off_fwd + (int64_t)c.occ_slot0 * NP + (ok ? pen : 0);
+        const auto rs = make_rsrc(ws + c.off_fwd + (int64_t)c.occ_slot0 * NP, c.Lo * NP * (int)sizeof(C2));
 #pragma unroll
         for (int i = 0; i < R2; ++i) {
             const int s = pmod(n1 + R1 * i - c.zo0, N);
-            const bool in = ok && s < c.Lo;
-            const C2 v = src[(in ? s : 0) * NP];
-            re[i] = in ? v.x : (T)0;
-            im[i] = in ? v.y : (T)0;
+            const C2 v = buf_load(rs, (s * NP + po) * (int)sizeof(C2), (C2 *)nullptr);
+            re[i] = v.x;
+            im[i] = v.y;
         }
         fft_unit<T, N, false>(re, im, n1, ex, PW, tw, true, PAD);
-        const C2 *R = rspec + (int64_t)3 * N * NP + (ok ? pen : 0);
+        const auto rr = make_rsrc(rspec + (int64_t)3 * N * NP, N * NP * (int)sizeof(C2));
 #pragma unroll
         for (int i = 0; i < M; ++i)
 #pragma unroll
             for (int k1 = 0; k1 < R1; ++k1) {
                 const int k = spec_index<N>(n1, i, k1);
-                const C2 r = R[k * NP];
+                const C2 r = buf_load(rr, (k * NP + (ok ? pen : 0)) * (int)sizeof(C2), (C2 *)nullptr);
                 const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
                 re[i * R1 + k1] = r.x * lr + r.y * li;
                 im[i * R1 + k1] = r.y * lr - r.x * li;
             }
         fft_unit_rev<T, N, true>(re, im, n1, ex, PW, tw, true, PAD);
-        dst += (int64_t)Vz * NP;
+        const auto rd = make_rsrc(wsi + c.off_inv + (int64_t)Vz * NP, Vz * NP * (int)sizeof(C2));
 #pragma unroll
-        for (int i = 0; i < R2; ++i) {
-            const int tz = n1 + R1 * i;
-            if (ok && tz < Vz) dst[(int64_t)tz * NP] = C2{re[i], im[i]};
-        }
+        for (int i = 0; i < R2; ++i)
+            buf_store(rd, ((n1 + R1 * i) * NP + po) * (int)sizeof(C2), C2{re[i], im[i]});
     }
 }
 
@@ -735,7 +791,8 @@ struct LseAcc {
 // translation clashes is not transformed: those energies are infinite by the
 // method and never enter Eq. 2.  e_count counts energy planes transformed.
 template <typename T, int N, bool OCC>
-__global__ __launch_bounds__(NT) void k_inv_xy_lse(const InvItem *__restrict__ items, const CfgDev *__restrict__ cfgs,
+__global__ __launch_bounds__(NT) void k_inv_xy_lse(const int32_t *__restrict__ inv_off, int n_cfg,
+                                                    const CfgDev *__restrict__ cfgs,
                                                     const typename Cx<T>::t *__restrict__ wsi, T beta, T inv_n3,
                                                     const typename Cx<T>::t *__restrict__ twg,
                                                     PlanePartial<T> *__restrict__ pp, T *__restrict__ psi_out,
@@ -748,9 +805,9 @@ __global__ __launch_bounds__(NT) void k_inv_xy_lse(const InvItem *__restrict__ i
     __shared__ C2 tw[N];
     __shared__ uint32_t cmask[(N * N + 31) / 32];
     __shared__ LseAcc<T> red[NT];
-    const InvItem it = items[blockIdx.x];
-    const CfgDev c = cfgs[it.cfg];
-    const int Vx = c.V[0], Vy = c.V[1], Vz = c.V[2], tz = it.tz;
+    const int ic = find_cfg(inv_off, n_cfg, (int)blockIdx.x);
+    const CfgDev c = cfgs[ic];
+    const int Vx = c.V[0], Vy = c.V[1], Vz = c.V[2], tz = (int)blockIdx.x - inv_off[ic];
     load_tw<T, N>(tw, twg);
     for (int i = threadIdx.x; i < (N * N + 31) / 32; i += NT) cmask[i] = 0u;
     const int unit = threadIdx.x / R1, n1 = threadIdx.x % R1;
@@ -1104,11 +1161,11 @@ struct Launch {
                            (const C2 *)tw, (C2 *)rspec);
         return hipGetLastError();
     }
-    static hipError_t fwd(hipStream_t st, const FwdItem *items, int n_items, const CfgDev *cfgs, const int32_t *ulat,
-                          const void *gam, const double *thr, const void *tw, void *ws) {
+    static hipError_t fwd(hipStream_t st, const int32_t *fwd_off, int n_cfg, int n_items, const CfgDev *cfgs,
+                          const int32_t *ulat, const void *gam, const double *thr, const void *tw, void *ws) {
         if (n_items <= 0) return hipSuccess;
-        hipLaunchKernelGGL((k_lig_fwd_xy<T, N>), dim3(n_items), dim3(NT), 0, st, items, cfgs, ulat, (const T *)gam,
-                           thr, (const C2 *)tw, (C2 *)ws);
+        hipLaunchKernelGGL((k_lig_fwd_xy<T, N>), dim3(n_items), dim3(NT), 0, st, fwd_off, n_cfg, cfgs, ulat,
+                           (const T *)gam, thr, (const C2 *)tw, (C2 *)ws);
         return hipGetLastError();
     }
     static hipError_t zprod(hipStream_t st, bool occ, bool edirect, const CfgDev *cfgs, const int32_t *zcfg,
@@ -1128,17 +1185,17 @@ struct Launch {
 #undef FFTDG_ZPROD
         return hipGetLastError();
     }
-    static hipError_t inv(hipStream_t st, bool occ, const InvItem *items, int n_items, const CfgDev *cfgs,
-                          const void *wsi, double beta, const void *tw, void *pp, void *psi_out, uint8_t *clash_out,
-                          unsigned int *e_count) {
+    static hipError_t inv(hipStream_t st, bool occ, const int32_t *inv_off, int n_cfg, int n_items,
+                          const CfgDev *cfgs, const void *wsi, double beta, const void *tw, void *pp, void *psi_out,
+                          uint8_t *clash_out, unsigned int *e_count) {
         if (n_items <= 0) return hipSuccess;
         const T b = (T)beta, s = (T)(1.0 / ((double)N * N * N));
         if (occ)
-            hipLaunchKernelGGL((k_inv_xy_lse<T, N, true>), dim3(n_items), dim3(NT), 0, st, items, cfgs,
+            hipLaunchKernelGGL((k_inv_xy_lse<T, N, true>), dim3(n_items), dim3(NT), 0, st, inv_off, n_cfg, cfgs,
                                (const C2 *)wsi, b, s, (const C2 *)tw, (PlanePartial<T> *)pp, (T *)psi_out, clash_out,
                                e_count);
         else
-            hipLaunchKernelGGL((k_inv_xy_lse<T, N, false>), dim3(n_items), dim3(NT), 0, st, items, cfgs,
+            hipLaunchKernelGGL((k_inv_xy_lse<T, N, false>), dim3(n_items), dim3(NT), 0, st, inv_off, n_cfg, cfgs,
                                (const C2 *)wsi, b, s, (const C2 *)tw, (PlanePartial<T> *)pp, (T *)psi_out, clash_out,
                                e_count);
         return hipGetLastError();

@@ -26,15 +26,9 @@ struct CfgDev {
     int64_t off_inv;     // complex-element offset of its inverse planes
 };
 
-// Forward xy work item: plane p of channel ch (0..2 energy, 3 occupancy).
-struct FwdItem {
-    int32_t cfg, ch, p, pad;
-};
-
-// Inverse xy work item: valid z translation tz of configuration cfg.
-struct InvItem {
-    int32_t cfg, tz;
-};
+// Work items are not listed: a chunk carries, per configuration, the
+// running count of its forward planes (fwd_off) and of its valid z
+// translations (inv_off); a block finds its configuration by binary search.
 
 template <typename T>
 struct PlanePartial {
