@@ -231,13 +231,39 @@ int fftdg_profile_read(fftdg_ctx *ctx, int32_t kernel_id, double *ms_host, int64
  *                      kernel (the xy FFT of the trilinearly spread plane
  *                      with its zero inputs pruned); 0: they go through the
  *                      same LDS-staged xy FFT pass as the occupancy channel
- *                      and through HBM (default). */
+ *                      and through HBM (default);
+ *   snapshots_per_pass receptor snapshots handled by one z-pencil launch
+ *                      (>= 1, default 1): with more than one, a
+ *                      configuration's forward z spectra stay in registers
+ *                      while the products and inverse transforms of every
+ *                      snapshot of the pass are computed; the inverse planes
+ *                      of all of them share device workspace;
+ *   use_graph          1: the scan's launch sequence is captured once into a
+ *                      hipGraph (kernel nodes only) and replayed by later
+ *                      scans whose launch shapes, buffers and temperature
+ *                      are unchanged (the new placement tables are uploaded
+ *                      first); not used while profiling or exporting
+ *                      energies.  Default 0. */
 typedef struct {
     int32_t configs_per_chunk;
     int32_t energy_xy_direct;
+    int32_t snapshots_per_pass;
+    int32_t use_graph;
 } fftdg_tuning;
 int fftdg_get_tuning(const fftdg_ctx *ctx, fftdg_tuning *out);
 int fftdg_set_tuning(fftdg_ctx *ctx, const fftdg_tuning *t);
+
+/* Autotuner: times the candidate schedules (configurations per chunk in
+ * {64, 128, 256, 512}, energy_xy_direct in {0, 1}, snapshots_per_pass in
+ * {1, n_snap} when there are several snapshots, use_graph in {0, 1}) with
+ * HIP events on an evenly
+ * strided sample of at most max_cfgs configurations of the batch (all
+ * receptor snapshots), keeps the fastest in the context and writes it to
+ * out (may be NULL); ms_host (may be NULL) receives its time per sampled
+ * configuration and snapshot.  Synchronizes the stream.  Results of later
+ * scans do not depend on the choice beyond FP rounding order. */
+int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max_cfgs, fftdg_tuning *out,
+                   double *ms_host);
 
 #ifdef __cplusplus
 }

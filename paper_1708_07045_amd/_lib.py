@@ -38,7 +38,8 @@ class GridDesc(ctypes.Structure):
 
 
 class Tuning(ctypes.Structure):
-    _fields_ = [("configs_per_chunk", ctypes.c_int32), ("energy_xy_direct", ctypes.c_int32)]
+    _fields_ = [("configs_per_chunk", ctypes.c_int32), ("energy_xy_direct", ctypes.c_int32),
+                ("snapshots_per_pass", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
 
 
 class BatchC(ctypes.Structure):
@@ -51,7 +52,7 @@ class BatchC(ctypes.Structure):
 EXPORTS = ["fftdg_version", "fftdg_status_string", "fftdg_create", "fftdg_destroy", "fftdg_last_error",
            "fftdg_set_stream", "fftdg_receptor_grids", "fftdg_set_receptors", "fftdg_scan",
            "fftdg_energy_grid", "fftdg_place", "fftdg_reduce", "fftdg_profile", "fftdg_profile_read",
-           "fftdg_get_tuning", "fftdg_set_tuning"]
+           "fftdg_get_tuning", "fftdg_set_tuning", "fftdg_autotune"]
 
 KERNEL_NAMES = ["lig_fwd_xy", "zprod", "inv_xy_lse", "merge", "rec_spectra", "reduce"]
 
@@ -87,6 +88,7 @@ def load():
     L.fftdg_profile_read.argtypes = [p, i32, p, p, p]
     L.fftdg_get_tuning.argtypes = [p, ctypes.POINTER(Tuning)]
     L.fftdg_set_tuning.argtypes = [p, ctypes.POINTER(Tuning)]
+    L.fftdg_autotune.argtypes = [p, ctypes.POINTER(BatchC), d, i32, ctypes.POINTER(Tuning), p]
     for name in EXPORTS:
         if name not in ("fftdg_destroy", "fftdg_status_string", "fftdg_last_error"):
             getattr(L, name).restype = ctypes.c_int
@@ -186,16 +188,33 @@ class FFTDG:
     def get_tuning(self) -> dict:
         t = Tuning()
         self._check(self.L.fftdg_get_tuning(self.h_ctx, ctypes.byref(t)))
-        return {"configs_per_chunk": t.configs_per_chunk, "energy_xy_direct": t.energy_xy_direct}
+        return {"configs_per_chunk": t.configs_per_chunk, "energy_xy_direct": t.energy_xy_direct,
+                "snapshots_per_pass": t.snapshots_per_pass, "use_graph": t.use_graph}
 
-    def set_tuning(self, configs_per_chunk: Optional[int] = None, energy_xy_direct: Optional[int] = None):
+    def set_tuning(self, configs_per_chunk: Optional[int] = None, energy_xy_direct: Optional[int] = None,
+                   snapshots_per_pass: Optional[int] = None, use_graph: Optional[int] = None):
         cur = self.get_tuning()
         if configs_per_chunk is not None:
             cur["configs_per_chunk"] = int(configs_per_chunk)
         if energy_xy_direct is not None:
             cur["energy_xy_direct"] = int(energy_xy_direct)
-        t = Tuning(cur["configs_per_chunk"], cur["energy_xy_direct"])
+        if snapshots_per_pass is not None:
+            cur["snapshots_per_pass"] = int(snapshots_per_pass)
+        if use_graph is not None:
+            cur["use_graph"] = int(use_graph)
+        t = Tuning(cur["configs_per_chunk"], cur["energy_xy_direct"], cur["snapshots_per_pass"],
+                   cur["use_graph"])
         self._check(self.L.fftdg_set_tuning(self.h_ctx, ctypes.byref(t)))
+
+    def autotune(self, batch: "Batch", T: float, max_cfgs: int = 2048):
+        """Pick the fastest schedule on a sample of the batch; returns
+        (tuning dict, ms per sampled configuration and snapshot)."""
+        t = Tuning()
+        ms = ctypes.c_double()
+        self._check(self.L.fftdg_autotune(self.h_ctx, ctypes.byref(batch.c), float(T), int(max_cfgs),
+                                          ctypes.byref(t), ctypes.byref(ms)))
+        return ({"configs_per_chunk": t.configs_per_chunk, "energy_xy_direct": t.energy_xy_direct,
+                 "snapshots_per_pass": t.snapshots_per_pass, "use_graph": t.use_graph}, ms.value)
 
     def set_chunk(self, n: int):
         self.set_tuning(configs_per_chunk=n)

@@ -22,9 +22,11 @@ struct KernelSet {
                       const int32_t *ulat, const void *gam, const double *thr, const void *tw, void *ws);
     // edirect: energy-channel xy transforms evaluated per atom inside the
     // kernel (else read from forward planes written by fwd)
+    // n_snap snapshots per launch: spectra spec_stride and outputs inv_stride
+    // complex elements apart
     hipError_t (*zprod)(hipStream_t, bool occ, bool edirect, const CfgDev *cfgs, const int32_t *zcfg, int nz,
                         const void *ws, const void *rspec, const void *tw, void *wsi, const int32_t *ulat,
-                        const void *gam);
+                        const void *gam, int n_snap, int64_t spec_stride, int64_t inv_stride);
     // e_count (nullable): incremented once per energy plane transformed
     // one block per valid z translation; inv_off[0..n_cfg] running counts
     hipError_t (*inv)(hipStream_t, bool occ, const int32_t *inv_off, int n_cfg, int n_items, const CfgDev *cfgs,

@@ -46,6 +46,13 @@ struct fftdg_ctx {
     bool staging_used = false;
     int chunk_cfgs = 256;
     bool edirect = false;
+    int snap_group = 1;  // snapshots per z launch (limited by workspace)
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;   // capture only; graphs run on `stream`
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    std::vector<int64_t> graph_sig;
+    DevBuf tune_out;     // partials written while autotuning
     size_t ws_limit = (size_t)24 << 30;
     // profiling
     bool prof = false;
@@ -495,7 +502,15 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     for (int i = 0; i < na; ++i) thr[i] = occ ? occ_threshold(g, b->sigma[i]) : 0.0;
     const size_t cb = (size_t)ctx->ks->cbytes;
     if ((rc = reserve(ctx, ctx->ws_fwd, cb * (size_t)std::max<int64_t>(P.max_fwd, 1)))) return rc;
-    if ((rc = reserve(ctx, ctx->ws_inv, cb * (size_t)std::max<int64_t>(P.max_inv, 1)))) return rc;
+    // snapshots whose inverse planes share the workspace: the z kernel keeps
+    // a configuration's forward spectra in registers across the group
+    const int s_begin = snap_only >= 0 ? snap_only : 0;
+    const int s_end = snap_only >= 0 ? snap_only + 1 : ctx->n_snap;
+    const int64_t inv1 = std::max<int64_t>(P.max_inv, 1);
+    const int64_t room = (int64_t)(ctx->ws_limit / cb) - P.max_fwd;
+    const int grp = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)(s_end - s_begin), room / inv1,
+                                                                  (int64_t)ctx->snap_group}));
+    if ((rc = reserve(ctx, ctx->ws_inv, cb * (size_t)inv1 * grp))) return rc;
     if ((rc = reserve(ctx, ctx->pp, (size_t)ctx->ks->ppbytes * (size_t)std::max(P.max_pp, 1)))) return rc;
     HIPCHK(ctx, hipMemcpyAsync(ctx->tables.p, h, total, hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipEventRecord(ctx->staging_ev, ctx->stream));
@@ -512,6 +527,11 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     const size_t spec_per_snap = (size_t)ctx->n_ch * g.n_fft * ctx->ks->np * cb;
     const KernelSet *ks = ctx->ks;
     const double pb = (double)ctx->ks->ppbytes;
+    // Every launch of the scan, issued on stream `st`.  The kernels read all
+    // per-chunk data from the device tables, so a captured sequence stays
+    // valid for any later scan with the same signature (launch shapes,
+    // table layout, buffers, temperature).
+    auto launch_all = [&](hipStream_t st) -> int {
     for (const Plan::Chunk &ch : P.chunks) {
         const CfgDev *ccfg = dcfg + ch.c0;
         // algorithmic bytes: forward planes written once (fwd), read once and
@@ -521,30 +541,79 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
         const double b_fwd = (double)ch.ws_fwd * cb;
         const double b_inv = (double)ch.ws_inv * cb;
         HIPCHK(ctx, timed(ctx, FFTDG_K_FWD, b_fwd, [&] {
-                   return ks->fwd(ctx->stream, dfwd + ch.off0, ch.c1 - ch.c0, (int)ch.nfwd, ccfg, du, dgam, dthr,
+                   return ks->fwd(st, dfwd + ch.off0, ch.c1 - ch.c0, (int)ch.nfwd, ccfg, du, dgam, dthr,
                                   ctx->tw.p, ctx->ws_fwd.p);
                }));
-        for (int s = 0; s < ctx->n_snap; ++s) {
-            if (snap_only >= 0 && s != snap_only) continue;
-            const char *rs = (const char *)ctx->rspec.p + spec_per_snap * s;
-            HIPCHK(ctx, timed(ctx, FFTDG_K_ZPROD, b_fwd + b_inv + (double)spec_per_snap, [&] {
-                       return ks->zprod(ctx->stream, occ, ctx->edirect, ccfg, dz + ch.z0, (int)ch.nz, ctx->ws_fwd.p,
-                                        rs, ctx->tw.p, ctx->ws_inv.p, du, dgam);
-                   }));
+        for (int s0 = s_begin; s0 < s_end; s0 += grp) {
+          const int ng = std::min(grp, s_end - s0);
+          const char *rs = (const char *)ctx->rspec.p + spec_per_snap * s0;
+          HIPCHK(ctx, timed(ctx, FFTDG_K_ZPROD, b_fwd + ng * (b_inv + (double)spec_per_snap), [&] {
+                     return ks->zprod(st, occ, ctx->edirect, ccfg, dz + ch.z0, (int)ch.nz, ctx->ws_fwd.p, rs,
+                                      ctx->tw.p, ctx->ws_inv.p, du, dgam, ng, (int64_t)(spec_per_snap / cb),
+                                      (int64_t)ch.ws_inv);
+                 }));
+          for (int s = s0; s < s0 + ng; ++s) {
+            void *wsi_s = (char *)ctx->ws_inv.p + (size_t)(s - s0) * (size_t)ch.ws_inv * cb;
             // inverse xy: occupancy planes always, energy planes only where the
             // plane has a clash-free translation (counted on the device)
             const double b_inv_fixed = (occ ? 0.5 * b_inv : 0.0) + pb * ch.pp;
             HIPCHK(ctx, timed(ctx, FFTDG_K_INV, b_inv_fixed, [&] {
-                       return ks->inv(ctx->stream, occ, dinv + ch.off0, ch.c1 - ch.c0, (int)ch.ninv, ccfg, ctx->ws_inv.p, beta,
+                       return ks->inv(st, occ, dinv + ch.off0, ch.c1 - ch.c0, (int)ch.ninv, ccfg, wsi_s, beta,
                                       ctx->tw.p, ctx->pp.p, psi_out, clash_out,
                                       ctx->prof ? (unsigned int *)ctx->prof_cnt.p : nullptr);
                    }));
             if (out)
                 HIPCHK(ctx, timed(ctx, FFTDG_K_MERGE, pb * ch.pp + sizeof(fftdg_partial) * (double)(ch.c1 - ch.c0), [&] {
-                           return ks->merge(ctx->stream, ccfg, ch.c1 - ch.c0, ctx->pp.p, out + (size_t)s * ncfg);
+                           return ks->merge(st, ccfg, ch.c1 - ch.c0, ctx->pp.p, out + (size_t)s * ncfg);
                        }));
+          }
         }
     }
+    return FFTDG_OK;
+    };
+    const bool graph_ok = ctx->use_graph && !ctx->prof && !psi_out && !clash_out && out;
+    if (!graph_ok) return launch_all(ctx->stream);
+    std::vector<int64_t> sig = {(int64_t)(intptr_t)ks, occ, ctx->edirect, grp, s_begin, s_end,
+                                (int64_t)(intptr_t)out, (int64_t)(intptr_t)ctx->tables.p,
+                                (int64_t)(intptr_t)ctx->ws_fwd.p, (int64_t)(intptr_t)ctx->ws_inv.p,
+                                (int64_t)(intptr_t)ctx->pp.p, (int64_t)(intptr_t)ctx->rspec.p,
+                                (int64_t)o_u, (int64_t)o_fwd, (int64_t)o_inv, (int64_t)o_z, (int64_t)o_gam,
+                                (int64_t)o_thr, ncfg};
+    int64_t bbits;
+    std::memcpy(&bbits, &beta, sizeof(bbits));
+    sig.push_back(bbits);
+    for (const Plan::Chunk &ch : P.chunks)
+        for (int64_t v : {(int64_t)ch.c0, (int64_t)ch.c1, (int64_t)ch.off0, (int64_t)ch.nfwd, (int64_t)ch.ninv,
+                          (int64_t)ch.z0, (int64_t)ch.nz, ch.ws_fwd, ch.ws_inv, (int64_t)ch.pp})
+            sig.push_back(v);
+    if (!(ctx->graph_exec && sig == ctx->graph_sig)) {
+        if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+        if (ctx->graph) (void)hipGraphDestroy(ctx->graph);
+        ctx->graph_exec = nullptr;
+        ctx->graph = nullptr;
+        ctx->graph_sig.clear();
+        if (!ctx->cap_stream) HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+        HIPCHK(ctx, hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeThreadLocal));
+        const int lrc = launch_all(ctx->cap_stream);
+        hipGraph_t gph = nullptr;
+        const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &gph);
+        if (lrc) {
+            if (gph) (void)hipGraphDestroy(gph);
+            return lrc;
+        }
+        if (ec != hipSuccess || !gph)
+            return set_err(ctx, FFTDG_E_DEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ec));
+        hipGraphExec_t ex = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&ex, gph, nullptr, nullptr, 0);
+        if (ei != hipSuccess) {
+            (void)hipGraphDestroy(gph);
+            return set_err(ctx, FFTDG_E_DEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ei));
+        }
+        ctx->graph = gph;
+        ctx->graph_exec = ex;
+        ctx->graph_sig = sig;
+    }
+    HIPCHK(ctx, hipGraphLaunch(ctx->graph_exec, ctx->stream));
     return FFTDG_OK;
 }
 
@@ -642,7 +711,7 @@ void fftdg_destroy(fftdg_ctx *c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     DevBuf *bufs[] = {&c->tw, &c->rspec, &c->rxy, &c->ws_fwd, &c->ws_inv, &c->pp, &c->tables,
-                      &c->red_B, &c->red_res, &c->red_off, &c->red_W, &c->prof_cnt};
+                      &c->red_B, &c->red_res, &c->red_off, &c->red_W, &c->prof_cnt, &c->tune_out};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->pinned) (void)hipHostFree(c->pinned);
@@ -652,6 +721,9 @@ void fftdg_destroy(fftdg_ctx *c) {
         (void)hipEventDestroy(r.b);
     }
     for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+    if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
     delete c;
 }
 
@@ -869,6 +941,8 @@ int fftdg_get_tuning(const fftdg_ctx *ctx, fftdg_tuning *t) {
     if (!ctx || !t) return FFTDG_E_INVALID;
     t->configs_per_chunk = ctx->chunk_cfgs;
     t->energy_xy_direct = ctx->edirect ? 1 : 0;
+    t->snapshots_per_pass = ctx->snap_group;
+    t->use_graph = ctx->use_graph ? 1 : 0;
     return FFTDG_OK;
 }
 
@@ -878,8 +952,94 @@ int fftdg_set_tuning(fftdg_ctx *ctx, const fftdg_tuning *t) {
     if (t->configs_per_chunk < 1) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: configs_per_chunk must be >= 1");
     if (t->energy_xy_direct != 0 && t->energy_xy_direct != 1)
         return set_err(ctx, FFTDG_E_INVALID, "set_tuning: energy_xy_direct must be 0 or 1");
+    if (t->snapshots_per_pass < 1) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: snapshots_per_pass must be >= 1");
     ctx->chunk_cfgs = t->configs_per_chunk;
     ctx->edirect = t->energy_xy_direct != 0;
+    if (t->use_graph != 0 && t->use_graph != 1) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: use_graph must be 0 or 1");
+    ctx->snap_group = t->snapshots_per_pass;
+    ctx->use_graph = t->use_graph != 0;
+    return FFTDG_OK;
+}
+
+int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max_cfgs, fftdg_tuning *out,
+                   double *ms_host) {
+    if (!ctx) return FFTDG_E_INVALID;
+    if (ctx->n_snap <= 0) return set_err(ctx, FFTDG_E_STATE, "autotune before set_receptors");
+    if (max_cfgs < 1) return set_err(ctx, FFTDG_E_INVALID, "autotune: max_cfgs must be >= 1");
+    if (!(T_K > 0.0) || !is_fin(T_K)) return set_err(ctx, FFTDG_E_INVALID, "autotune: temperature must be > 0");
+    int rc = validate_batch(ctx, b);
+    if (rc) return rc;
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const int ncfg = b->cfg_off[b->n_lig];
+    // evenly strided sample, within the caller's selection
+    std::vector<uint8_t> sel(ncfg, 0);
+    const int stride = std::max(1, (ncfg + max_cfgs - 1) / max_cfgs);
+    int nsel = 0;
+    for (int c = 0; c < ncfg; c += stride)
+        if (!b->cfg_select || b->cfg_select[c]) {
+            sel[c] = 1;
+            ++nsel;
+        }
+    if (nsel == 0) return set_err(ctx, FFTDG_E_INVALID, "autotune: empty sample");
+    fftdg_batch bs = *b;
+    bs.cfg_select = sel.data();
+    if ((rc = reserve(ctx, ctx->tune_out, sizeof(fftdg_partial) * (size_t)ncfg * ctx->n_snap))) return rc;
+    const fftdg_tuning keep = {ctx->chunk_cfgs, ctx->edirect ? 1 : 0, ctx->snap_group, ctx->use_graph ? 1 : 0};
+    const bool prof = ctx->prof;
+    ctx->prof = false;
+    std::vector<fftdg_tuning> cand;
+    std::vector<int> passes = {1};
+    if (ctx->n_snap > 1) passes.push_back(ctx->n_snap);
+    for (int chunk : {64, 128, 256, 512})
+        for (int ed : {0, 1})
+            for (int sp : passes)
+                for (int gr : {0, 1}) cand.push_back(fftdg_tuning{chunk, ed, sp, gr});
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    HIPCHK(ctx, hipEventCreate(&e0));
+    HIPCHK(ctx, hipEventCreate(&e1));
+    double best = INFINITY;
+    fftdg_tuning bt = keep;
+    int err = FFTDG_OK;
+    for (const fftdg_tuning &t : cand) {
+        ctx->chunk_cfgs = t.configs_per_chunk;
+        ctx->edirect = t.energy_xy_direct != 0;
+        ctx->snap_group = t.snapshots_per_pass;
+        ctx->use_graph = t.use_graph != 0;
+        float tmin = INFINITY;
+        for (int rep = 0; rep < 3 && !err; ++rep) {
+            Plan P;
+            if ((err = build_plan(ctx, &bs, false, -1, P))) break;
+            if (hipEventRecord(e0, ctx->stream) != hipSuccess) err = FFTDG_E_DEVICE;
+            if (!err) err = run_plan(ctx, &bs, P, T_K, (fftdg_partial *)ctx->tune_out.p, -1, nullptr, nullptr);
+            if (!err && hipEventRecord(e1, ctx->stream) != hipSuccess) err = FFTDG_E_DEVICE;
+            if (!err && hipEventSynchronize(e1) != hipSuccess) err = FFTDG_E_DEVICE;
+            float ms = 0.f;
+            if (!err && hipEventElapsedTime(&ms, e0, e1) != hipSuccess) err = FFTDG_E_DEVICE;
+            if (!err && rep > 0) tmin = std::min(tmin, ms);  // first run warms the plan's buffers
+        }
+        if (err) break;
+        if (tmin < best) {
+            best = tmin;
+            bt = t;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->prof = prof;
+    if (err) {
+        ctx->chunk_cfgs = keep.configs_per_chunk;
+        ctx->edirect = keep.energy_xy_direct != 0;
+        ctx->snap_group = keep.snapshots_per_pass;
+        ctx->use_graph = keep.use_graph != 0;
+        if (err == FFTDG_E_DEVICE && ctx->err.empty()) ctx->err = "autotune: HIP event error";
+        return err;
+    }
+    ctx->chunk_cfgs = bt.configs_per_chunk;
+    ctx->edirect = bt.energy_xy_direct != 0;
+    ctx->snap_group = bt.snapshots_per_pass;
+    ctx->use_graph = bt.use_graph != 0;
+    if (out) *out = bt;
+    if (ms_host) *ms_host = best / ((double)nsel * ctx->n_snap);
     return FFTDG_OK;
 }
 

@@ -568,14 +568,18 @@ struct DAtom {
 // come from k_lig_fwd_xy through HBM.  The occupancy channel always comes
 // from k_lig_fwd_xy.  Then: forward FFT along z, product with the receptor
 // spectra summed over the energy channels (Eq. 9, R * conj(L)), inverse FFT
-// along z, store the valid z-translations only.
-template <typename T, int N, bool OCC, bool EDIRECT>
+// along z, store the valid z-translations only.  The ligand's forward
+// spectra stay in registers while the product and inverse run for each of
+// n_snap receptor snapshots (spectra spec_stride apart, outputs inv_stride
+// apart).
+template <typename T, int N, bool OCC, bool EDIRECT, bool MULTI>
 __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, const int32_t *__restrict__ zcfg,
                                                int nz, int n_tiles, const typename Cx<T>::t *__restrict__ ws,
                                                const typename Cx<T>::t *__restrict__ rspec,
                                                const typename Cx<T>::t *__restrict__ twg,
                                                typename Cx<T>::t *__restrict__ wsi,
-                                               const int32_t *__restrict__ ulat, const T *__restrict__ gam) {
+                                               const int32_t *__restrict__ ulat, const T *__restrict__ gam,
+                                               int n_snap, int64_t spec_stride, int64_t inv_stride) {
     using C2 = typename Cx<T>::t;
     using G = Geo<T, N>;
     constexpr int R1 = G::R1, R2 = G::R2, M = G::M, P = G::U, NP = G::NP, H = G::H;
@@ -617,6 +621,7 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
     const int nchunk = EDIRECT ? (c.n_atoms + AC - 1) / AC : 0;
     // element e of this lane's pencil in the wave region
     auto eaddr = [&](int e) { return e * PW + (e / R2) * PAD; };
+    if constexpr (!MULTI) {
     T er[R2], ei[R2];
 #pragma unroll
     for (int i = 0; i < R2; ++i) er[i] = ei[i] = (T)0;
@@ -742,6 +747,147 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
 #pragma unroll
         for (int i = 0; i < R2; ++i)
             buf_store(rd, ((n1 + R1 * i) * NP + po) * (int)sizeof(C2), C2{re[i], im[i]});
+    }
+    } else {
+    // forward z transforms of the three energy channels, kept in registers
+    // for every snapshot of the group
+    T lr[3][R2], li[3][R2];
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        T *re = lr[ch], *im = li[ch];
+#pragma unroll
+        for (int i = 0; i < R2; ++i) re[i] = im[i] = (T)0;
+        if (EDIRECT) {
+            // Lane (n1, p) owns the z-planes n1 + R1*i of pencil p in its wave region.
+            wave_sync();  // previous exchange reads of the region are done
+#pragma unroll
+            for (int i = 0; i < R2; ++i) ex[eaddr(n1 + R1 * i)] = C2{(T)0, (T)0};
+            for (int ck = 0; ck < nchunk; ++ck) {
+                const int a0 = ck * AC, na = min(AC, c.n_atoms - a0);
+                if (ch == 0 || nchunk > 1) {
+                    if (nchunk > 1) __syncthreads();
+                    // XY[a][p] = w^(kx ax)((1-fx) + fx w^kx) * w^(ky ay)((1-fy) + fy w^ky)
+                    for (int e = threadIdx.x; e < na * P; e += NT) {
+                        const int a = e / P, q = e - a * P;
+                        const int pq = tile * P + q;
+                        const int kyq = pq / H, kxq = pq - kyq * H;
+                        const DAtom<T> d = at[a0 + a];
+                        const C2 wx = tw[kxq & (N - 1)], wy = tw[kyq & (N - 1)];
+                        const C2 ex_ = tw[(kxq * d.ax) & (N - 1)], ey = tw[(kyq * d.ay) & (N - 1)];
+                        const T sxr = (T)1 - d.fx + d.fx * wx.x, sxi = d.fx * wx.y;
+                        const T syr = (T)1 - d.fy + d.fy * wy.x, syi = d.fy * wy.y;
+                        const T xr = ex_.x * sxr - ex_.y * sxi, xi = ex_.x * sxi + ex_.y * sxr;
+                        const T yr = ey.x * syr - ey.y * syi, yi = ey.x * syi + ey.y * syr;
+                        xy[a * P + q] = C2{xr * yr - xi * yi, xr * yi + xi * yr};
+                    }
+                    __syncthreads();
+                }
+                for (int a = 0; a < na; ++a) {
+                    const DAtom<T> d = at[a0 + a];
+                    const int za = d.az, zb = d.az + 1;
+                    const bool ha = (za & (R1 - 1)) == n1, hb = (zb & (R1 - 1)) == n1;
+                    if (!ha && !hb) continue;
+                    const C2 v = xy[a * P + p];
+                    const T g = d.g[ch];
+                    if (ha) {
+                        C2 &t = ex[eaddr(za & (N - 1))];
+                        const T w = g * ((T)1 - d.fz);
+                        t.x += w * v.x;
+                        t.y += w * v.y;
+                    }
+                    if (hb) {
+                        C2 &t = ex[eaddr(zb & (N - 1))];
+                        const T w = g * d.fz;
+                        t.x += w * v.x;
+                        t.y += w * v.y;
+                    }
+                }
+            }
+            if (ok) {
+#pragma unroll
+                for (int i = 0; i < R2; ++i) {
+                    const C2 v = ex[eaddr(n1 + R1 * i)];
+                    re[i] = v.x;
+                    im[i] = v.y;
+                }
+            }
+        } else {
+            // planes outside the channel's window lie beyond the descriptor
+            // and read as zero
+            const auto rs = make_rsrc(ws + c.off_fwd + (int64_t)ch * c.Le * NP, c.Le * NP * (int)sizeof(C2));
+            const int po = ok ? pen : NP * N;
+#pragma unroll
+            for (int i = 0; i < R2; ++i) {
+                const int s = pmod(n1 + R1 * i - c.ze0, N);
+                const C2 v = buf_load(rs, (s * NP + po) * (int)sizeof(C2), (C2 *)nullptr);
+                re[i] = v.x;
+                im[i] = v.y;
+            }
+        }
+        fft_unit<T, N, false>(re, im, n1, ex, PW, tw, true, PAD);
+    }
+    const int Vz = c.V[2];
+    const int po = ok ? pen : NP * N;  // out of every descriptor's range
+    const int pr = ok ? pen : 0;
+#pragma unroll 1
+    for (int sn = 0; sn < n_snap; ++sn) {
+        T er[R2], ei[R2];
+#pragma unroll
+        for (int i = 0; i < R2; ++i) er[i] = ei[i] = (T)0;
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const auto rr = make_rsrc(rspec + sn * spec_stride + (int64_t)ch * N * NP, N * NP * (int)sizeof(C2));
+#pragma unroll
+            for (int i = 0; i < M; ++i)
+#pragma unroll
+                for (int k1 = 0; k1 < R1; ++k1) {
+                    const int k = spec_index<N>(n1, i, k1);
+                    const C2 r = buf_load(rr, (k * NP + pr) * (int)sizeof(C2), (C2 *)nullptr);
+                    const T a = lr[ch][i * R1 + k1], bq = li[ch][i * R1 + k1];
+                    er[i * R1 + k1] += r.x * a + r.y * bq;  // R * conj(L)
+                    ei[i * R1 + k1] += r.y * a - r.x * bq;
+                }
+        }
+        fft_unit_rev<T, N, true>(er, ei, n1, ex, PW, tw, true, PAD);
+        // valid z-translations only: tz >= Vz lies beyond the descriptor
+        const auto rd = make_rsrc(wsi + sn * inv_stride + c.off_inv, Vz * NP * (int)sizeof(C2));
+#pragma unroll
+        for (int i = 0; i < R2; ++i)
+            buf_store(rd, ((n1 + R1 * i) * NP + po) * (int)sizeof(C2), C2{er[i], ei[i]});
+    }
+    if (OCC) {
+        T orr[R2], oi[R2];
+        const auto rs = make_rsrc(ws + c.off_fwd + (int64_t)c.occ_slot0 * NP, c.Lo * NP * (int)sizeof(C2));
+#pragma unroll
+        for (int i = 0; i < R2; ++i) {
+            const int s = pmod(n1 + R1 * i - c.zo0, N);
+            const C2 v = buf_load(rs, (s * NP + po) * (int)sizeof(C2), (C2 *)nullptr);
+            orr[i] = v.x;
+            oi[i] = v.y;
+        }
+        fft_unit<T, N, false>(orr, oi, n1, ex, PW, tw, true, PAD);
+#pragma unroll 1
+        for (int sn = 0; sn < n_snap; ++sn) {
+            T re[R2], im[R2];
+            const auto rr = make_rsrc(rspec + sn * spec_stride + (int64_t)3 * N * NP, N * NP * (int)sizeof(C2));
+#pragma unroll
+            for (int i = 0; i < M; ++i)
+#pragma unroll
+                for (int k1 = 0; k1 < R1; ++k1) {
+                    const int k = spec_index<N>(n1, i, k1);
+                    const C2 r = buf_load(rr, (k * NP + pr) * (int)sizeof(C2), (C2 *)nullptr);
+                    const T a = orr[i * R1 + k1], bq = oi[i * R1 + k1];
+                    re[i * R1 + k1] = r.x * a + r.y * bq;
+                    im[i * R1 + k1] = r.y * a - r.x * bq;
+                }
+            fft_unit_rev<T, N, true>(re, im, n1, ex, PW, tw, true, PAD);
+            const auto rd =
+                make_rsrc(wsi + sn * inv_stride + c.off_inv + (int64_t)Vz * NP, Vz * NP * (int)sizeof(C2));
+#pragma unroll
+            for (int i = 0; i < R2; ++i)
+                buf_store(rd, ((n1 + R1 * i) * NP + po) * (int)sizeof(C2), C2{re[i], im[i]});
+        }
+    }
     }
 }
 
@@ -1170,14 +1316,21 @@ struct Launch {
     }
     static hipError_t zprod(hipStream_t st, bool occ, bool edirect, const CfgDev *cfgs, const int32_t *zcfg,
                             int nz, const void *ws, const void *rspec, const void *tw, void *wsi,
-                            const int32_t *ulat, const void *gam) {
+                            const int32_t *ulat, const void *gam, int n_snap, int64_t spec_stride,
+                            int64_t inv_stride) {
         if (nz <= 0) return hipSuccess;
         const int n_tiles = (G::NP + G::U - 1) / G::U;
         long long nb = (long long)n_tiles * nz;
         nb = (nb + 7) / 8 * 8;
 #define FFTDG_ZPROD(O, E)                                                                                 \
-    hipLaunchKernelGGL((k_zprod<T, N, O, E>), dim3((unsigned)nb), dim3(NT), 0, st, cfgs, zcfg, nz, n_tiles, \
-                       (const C2 *)ws, (const C2 *)rspec, (const C2 *)tw, (C2 *)wsi, ulat, (const T *)gam)
+    if (n_snap > 1)                                                                                       \
+        hipLaunchKernelGGL((k_zprod<T, N, O, E, true>), dim3((unsigned)nb), dim3(NT), 0, st, cfgs, zcfg, nz,  \
+                           n_tiles, (const C2 *)ws, (const C2 *)rspec, (const C2 *)tw, (C2 *)wsi, ulat,        \
+                           (const T *)gam, n_snap, spec_stride, inv_stride);                                   \
+    else                                                                                                  \
+    hipLaunchKernelGGL((k_zprod<T, N, O, E, false>), dim3((unsigned)nb), dim3(NT), 0, st, cfgs, zcfg, nz, n_tiles, \
+                       (const C2 *)ws, (const C2 *)rspec, (const C2 *)tw, (C2 *)wsi, ulat, (const T *)gam, n_snap, \
+                       spec_stride, inv_stride)
         if (occ && edirect) FFTDG_ZPROD(true, true);
         else if (occ) FFTDG_ZPROD(true, false);
         else if (edirect) FFTDG_ZPROD(false, true);

@@ -206,12 +206,14 @@ def test_scan_c2_subset_fp32(edirect, chunk):
     _scan_parity(w, "f32", 0.01, energy_xy_direct=edirect, configs_per_chunk=chunk)
 
 
-def test_scan_batched_uneven_ligands_two_snapshots():
+@pytest.mark.parametrize("snap_pass,chunk", [(16, 256), (1, 256), (2, 5)])
+def test_scan_batched_uneven_ligands_three_snapshots(snap_pass, chunk):
     """Ragged batch: 5 ligands of 8..40 atoms with different configuration
-    counts against 2 jittered snapshots (small chunk to cross chunk edges)."""
-    w = synth.config3(n_ligands=5, n_snap=2, cfg_scale=0.02)
-    P, B, res = _scan_parity(w, "f32", 0.01)
-    assert P.shape[0] == 2
+    counts against 3 jittered snapshots; snapshots handled all in one z pass,
+    one per pass, or 2 + 1, and chunks that cross ligand boundaries."""
+    w = synth.config3(n_ligands=5, n_snap=3, cfg_scale=0.02)
+    P, B, res = _scan_parity(w, "f32", 0.01, snapshots_per_pass=snap_pass, configs_per_chunk=chunk)
+    assert P.shape[0] == 3
 
 
 def test_cfg_select_and_empty_configs():
@@ -283,3 +285,49 @@ def test_rescan_is_deterministic():
     a = ctx.scan(b, w.T).cpu().numpy()
     c = ctx.scan(b, w.T).cpu().numpy()
     np.testing.assert_array_equal(a, c)
+
+
+def test_graph_replays_match_eager():
+    """The captured scan graph, replayed several times with other eager work
+    and synchronizations in between, gives exactly the eager results; a new
+    batch shape re-captures."""
+    import torch
+    w = synth.subset(synth.config2(), 48, stride=150)
+    w2 = synth.subset(synth.config2(), 20, stride=333)
+    ctx, grids, occ = _gpu_setup(w)
+    b, b2 = _batch(w), _batch(w2)
+    ref = ctx.scan(b, w.T).cpu().numpy()
+    ref2 = ctx.scan(b2, w.T).cpu().numpy()
+    ctx.set_tuning(use_graph=1)
+    out = ctx.alloc_partials(b)
+    for rep in range(4):
+        ctx.scan(b, w.T, out)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), ref)
+        x = torch.randn(1 << 20, device="cuda")  # unrelated eager work between replays
+        (x * 2).sum().item()
+        if rep == 2:
+            np.testing.assert_array_equal(ctx.scan(b2, w.T).cpu().numpy(), ref2)
+    B, _ = ctx.reduce(b, out, w.T)
+    ctx.set_tuning(use_graph=0)
+    B0, _ = ctx.reduce(b, ctx.scan(b, w.T), w.T)
+    assert B[0, 0] == B0[0, 0]
+
+
+def test_autotune_picks_valid_schedule():
+    import torch
+    w = synth.subset(synth.config2(), 160, stride=50)
+    ctx, grids, occ = _gpu_setup(w)
+    b = _batch(w)
+    ref = ctx.partials_numpy(ctx.scan(b, w.T), 1, b.n_cfg)
+    tun, ms = ctx.autotune(b, w.T, max_cfgs=64)
+    assert tun["configs_per_chunk"] in (64, 128, 256, 512)
+    assert tun["energy_xy_direct"] in (0, 1) and tun["use_graph"] in (0, 1)
+    assert ms > 0 and ctx.get_tuning() == tun
+    got = ctx.partials_numpy(ctx.scan(b, w.T), 1, b.n_cfg)
+    np.testing.assert_array_equal(got["n_finite"], ref["n_finite"])
+    fin = ref["n_finite"] > 0
+    kt = est.kT(w.T)
+    lz_a = got["m"][fin] + np.log(got["s"][fin])
+    lz_b = ref["m"][fin] + np.log(ref["s"][fin])
+    assert np.max(np.abs(kt * (lz_a - lz_b))) < 1e-3
