@@ -265,6 +265,60 @@ int fftdg_set_tuning(fftdg_ctx *ctx, const fftdg_tuning *t);
 int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max_cfgs, fftdg_tuning *out,
                    double *ms_host);
 
+/* ------------------------------------------------------------------------
+ * Learned importance-sampling proposal over ligand configurations.
+ *
+ * Not part of the paper: Eq. 2 is estimated from a subset of configurations
+ * drawn from a proposal q built from a small network's prediction of each
+ * configuration's log Boltzmann weight, with exact 1/q reweighting through
+ * fftdg_reduce's cfg_weight; the exhaustive scan stays the fallback and the
+ * judge of its error.
+ * ------------------------------------------------------------------------ */
+
+/* Per-configuration input features (host; FFTDG_N_FEATURES floats each):
+ *   [0..3]   rotation quaternion, normalised, sign fixed to w >= 0 (q = -q)
+ *   [4..11]  one-hot of the conformer index modulo 8
+ *   [12]     n_atoms / 40,   [13] ln(n_atoms) / ln(40)
+ *   [14..16] placed extent along x, y, z in units of 10 A
+ *   [17]     radius of gyration of the conformer in units of 5 A
+ * feat_host [n_cfg_total][FFTDG_N_FEATURES]. */
+#define FFTDG_N_FEATURES 18
+int fftdg_config_features(fftdg_ctx *ctx, const fftdg_batch *b, float *feat_host);
+
+/* Network: n_in inputs -> 3 hidden layers of `width` SiLU units -> 1 linear
+ * output; BF16 MFMA products with FP32 accumulation, FP32 master parameters,
+ * Adam (beta 0.9/0.999, eps 1e-8).  Flat FP32 parameter layout (row-major):
+ *   W1 [width][n_in], b1 [width], W2 [width][width], b2 [width],
+ *   W3 [width][width], b3 [width], W4 [1][width], b4 [1].
+ * Loss of a batch: sum_i w_i (y_i - t_i)^2 / sum_i w_i.
+ * Requirements: 1 <= n_in <= 64, width a multiple of 64 (<= 1024),
+ * batches of at most max_batch rows.  Parameters start at zero: set them. */
+typedef struct fftdg_mlp fftdg_mlp;
+int fftdg_mlp_create(fftdg_mlp **out, int device, void *hip_stream, int32_t n_in, int32_t width,
+                     int32_t max_batch);
+void fftdg_mlp_destroy(fftdg_mlp *m);
+const char *fftdg_mlp_last_error(const fftdg_mlp *m);
+int64_t fftdg_mlp_num_params(const fftdg_mlp *m);
+/* host <-> device parameters (synchronizes; set also resets Adam) */
+int fftdg_mlp_set_params(fftdg_mlp *m, const float *params_host, int64_t n);
+int fftdg_mlp_get_params(fftdg_mlp *m, float *params_host, int64_t n);
+/* y_dev[i] = net(x_dev[i]) for i < n (device arrays, x [n][n_in]) */
+int fftdg_mlp_forward(fftdg_mlp *m, const float *x_dev, int32_t n, float *y_dev);
+/* gradient of the loss over the rows idx_dev[0..B-1] (NULL = rows 0..B-1)
+ * of x_all_dev [.][n_in], t_all_dev, w_all_dev into grad_dev (flat layout);
+ * loss_host may be NULL (else synchronizes) */
+int fftdg_mlp_grad(fftdg_mlp *m, const float *x_all_dev, const float *t_all_dev, const float *w_all_dev,
+                   const int32_t *idx_dev, int32_t B, float *grad_dev, float *loss_host);
+/* one Adam step on that gradient with learning rate lr */
+int fftdg_mlp_train_step(fftdg_mlp *m, const float *x_all_dev, const float *t_all_dev,
+                         const float *w_all_dev, const int32_t *idx_dev, int32_t B, float lr,
+                         float *loss_host);
+/* Defensive mixture q_c = (1 - alpha) softmax(yhat / tau)_c + alpha / P over
+ * P configurations (FP64, q_dev [P]) and K inverse-CDF draws idx_dev [K] from
+ * the given uniforms u_dev [K] in [0, 1) (the random numbers are inputs). */
+int fftdg_proposal_sample(fftdg_mlp *m, const float *yhat_dev, int32_t P, double alpha, double tau, int32_t K,
+                          const double *u_dev, int32_t *idx_dev, double *q_dev);
+
 #ifdef __cplusplus
 }
 #endif

@@ -52,7 +52,12 @@ class BatchC(ctypes.Structure):
 EXPORTS = ["fftdg_version", "fftdg_status_string", "fftdg_create", "fftdg_destroy", "fftdg_last_error",
            "fftdg_set_stream", "fftdg_receptor_grids", "fftdg_set_receptors", "fftdg_scan",
            "fftdg_energy_grid", "fftdg_place", "fftdg_reduce", "fftdg_profile", "fftdg_profile_read",
-           "fftdg_get_tuning", "fftdg_set_tuning", "fftdg_autotune"]
+           "fftdg_get_tuning", "fftdg_set_tuning", "fftdg_autotune", "fftdg_config_features",
+           "fftdg_mlp_create", "fftdg_mlp_destroy", "fftdg_mlp_last_error", "fftdg_mlp_num_params",
+           "fftdg_mlp_set_params", "fftdg_mlp_get_params", "fftdg_mlp_forward", "fftdg_mlp_grad",
+           "fftdg_mlp_train_step", "fftdg_proposal_sample"]
+
+N_FEATURES = 18
 
 KERNEL_NAMES = ["lig_fwd_xy", "zprod", "inv_xy_lse", "merge", "rec_spectra", "reduce"]
 
@@ -89,9 +94,24 @@ def load():
     L.fftdg_get_tuning.argtypes = [p, ctypes.POINTER(Tuning)]
     L.fftdg_set_tuning.argtypes = [p, ctypes.POINTER(Tuning)]
     L.fftdg_autotune.argtypes = [p, ctypes.POINTER(BatchC), d, i32, ctypes.POINTER(Tuning), p]
+    L.fftdg_config_features.argtypes = [p, ctypes.POINTER(BatchC), p]
+    L.fftdg_mlp_create.argtypes = [ctypes.POINTER(p), ctypes.c_int, p, i32, i32, i32]
+    L.fftdg_mlp_destroy.argtypes = [p]
+    L.fftdg_mlp_destroy.restype = None
+    L.fftdg_mlp_last_error.argtypes = [p]
+    L.fftdg_mlp_last_error.restype = ctypes.c_char_p
+    L.fftdg_mlp_num_params.argtypes = [p]
+    L.fftdg_mlp_set_params.argtypes = [p, p, ctypes.c_int64]
+    L.fftdg_mlp_get_params.argtypes = [p, p, ctypes.c_int64]
+    L.fftdg_mlp_forward.argtypes = [p, p, i32, p]
+    L.fftdg_mlp_grad.argtypes = [p, p, p, p, p, i32, p, p]
+    L.fftdg_mlp_train_step.argtypes = [p, p, p, p, p, i32, ctypes.c_float, p]
+    L.fftdg_proposal_sample.argtypes = [p, p, i32, d, d, i32, p, p, p]
     for name in EXPORTS:
-        if name not in ("fftdg_destroy", "fftdg_status_string", "fftdg_last_error"):
+        if name not in ("fftdg_destroy", "fftdg_status_string", "fftdg_last_error", "fftdg_mlp_destroy",
+                        "fftdg_mlp_last_error", "fftdg_mlp_num_params"):
             getattr(L, name).restype = ctypes.c_int
+    L.fftdg_mlp_num_params.restype = ctypes.c_int64
     _lib = L
     return L
 
@@ -287,6 +307,12 @@ class FFTDG:
                                                  _ptr(psi), _ptr(clash), _ptr(shape)))
         return psi, clash
 
+    def features(self, batch: Batch) -> np.ndarray:
+        """Per-configuration proposal features [n_cfg][N_FEATURES] (host)."""
+        f = np.zeros((batch.n_cfg, N_FEATURES), np.float32)
+        self._check(self.L.fftdg_config_features(self.h_ctx, ctypes.byref(batch.c), _ptr(f)))
+        return f
+
     def place(self, batch: Batch, cfg: int):
         l = int(np.searchsorted(batch.cfg_off, cfg, side="right") - 1)
         na = int(batch.atom_off[l + 1] - batch.atom_off[l])
@@ -304,3 +330,90 @@ class FFTDG:
         self._check(self.L.fftdg_reduce(self.h_ctx, ctypes.byref(batch.c), _ptr(partials), _ptr(w), float(T),
                                         _ptr(B), _ptr(res)))
         return B, res
+
+
+class Network:
+    """The proposal network of the library (fftdg_mlp)."""
+
+    def __init__(self, n_in: int = N_FEATURES, width: int = 256, max_batch: int = 4096, device: int = 0,
+                 stream=None):
+        import torch
+        self.torch = torch
+        self.L = load()
+        self.n_in, self.width, self.max_batch = n_in, width, max_batch
+        self.device = torch.device("cuda", device)
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+        h = ctypes.c_void_p()
+        rc = self.L.fftdg_mlp_create(ctypes.byref(h), device, ctypes.c_void_p(stream), n_in, width, max_batch)
+        if rc != OK:
+            raise FFTDGError(rc, "fftdg_mlp_create failed (" + self.L.fftdg_status_string(rc).decode() + ")")
+        self.h = h
+        self.n_params = int(self.L.fftdg_mlp_num_params(h))
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.fftdg_mlp_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, rc):
+        if rc != OK:
+            raise FFTDGError(rc, self.L.fftdg_mlp_last_error(self.h).decode())
+
+    def set_params(self, p: np.ndarray):
+        p = np.ascontiguousarray(p, np.float32)
+        self._check(self.L.fftdg_mlp_set_params(self.h, _ptr(p), p.size))
+
+    def get_params(self) -> np.ndarray:
+        p = np.zeros(self.n_params, np.float32)
+        self._check(self.L.fftdg_mlp_get_params(self.h, _ptr(p), p.size))
+        return p
+
+    def _dev(self, a, dtype):
+        t = self.torch
+        if isinstance(a, t.Tensor):
+            return a.to(self.device, dtype).contiguous()
+        return t.as_tensor(np.ascontiguousarray(a), device=self.device).to(dtype).contiguous()
+
+    def forward(self, X):
+        t = self.torch
+        x = self._dev(X, t.float32)
+        y = t.empty(x.shape[0], dtype=t.float32, device=self.device)
+        self._check(self.L.fftdg_mlp_forward(self.h, _ptr(x), int(x.shape[0]), _ptr(y)))
+        return y
+
+    def grad(self, X, T, W, idx=None):
+        t = self.torch
+        x, tt, ww = self._dev(X, t.float32), self._dev(T, t.float32), self._dev(W, t.float32)
+        ii = None if idx is None else self._dev(idx, t.int32)
+        B = int(x.shape[0] if ii is None else ii.shape[0])
+        g = t.zeros(self.n_params, dtype=t.float32, device=self.device)
+        loss = ctypes.c_float()
+        self._check(self.L.fftdg_mlp_grad(self.h, _ptr(x), _ptr(tt), _ptr(ww), _ptr(ii), B, _ptr(g),
+                                          ctypes.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, x, t_, w, idx, lr: float, want_loss: bool = False):
+        """x, t_, w, idx: device tensors (float32, float32, float32, int32)."""
+        loss = ctypes.c_float()
+        self._check(self.L.fftdg_mlp_train_step(self.h, _ptr(x), _ptr(t_), _ptr(w), _ptr(idx), int(idx.shape[0]),
+                                                float(lr), ctypes.byref(loss) if want_loss else None))
+        return loss.value if want_loss else None
+
+    def sample(self, yhat, alpha: float, tau: float, uniforms):
+        """Mixture proposal q [P] (float64) and len(uniforms) draws (int32)."""
+        t = self.torch
+        y = self._dev(yhat, t.float32)
+        u = self._dev(uniforms, t.float64)
+        P, K = int(y.shape[0]), int(u.shape[0])
+        idx = t.empty(K, dtype=t.int32, device=self.device)
+        q = t.empty(P, dtype=t.float64, device=self.device)
+        self._check(self.L.fftdg_proposal_sample(self.h, _ptr(y), P, float(alpha), float(tau), K, _ptr(u),
+                                                 _ptr(idx), _ptr(q)))
+        return q, idx

@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfftdg.so")
-SOURCES = ["scan_kernels.hip", "runtime.cpp"]
+SOURCES = ["scan_kernels.hip", "mlp.hip", "runtime.cpp"]
 HEADERS = ["fft_device.hpp", "scan_types.hpp", "kernels.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -961,6 +961,52 @@ int fftdg_set_tuning(fftdg_ctx *ctx, const fftdg_tuning *t) {
     return FFTDG_OK;
 }
 
+int fftdg_config_features(fftdg_ctx *ctx, const fftdg_batch *b, float *feat) {
+    if (!ctx) return FFTDG_E_INVALID;
+    int rc = validate_batch(ctx, b);
+    if (rc) return rc;
+    if (!feat) return set_err(ctx, FFTDG_E_INVALID, "config_features: NULL output");
+    size_t row = 0;
+    for (int l = 0; l < b->n_lig; ++l) {
+        const int na = b->atom_off[l + 1] - b->atom_off[l];
+        const int nc = b->conf_off[l + 1] - b->conf_off[l];
+        std::vector<double> rg(nc);
+        for (int k = 0; k < nc; ++k) {
+            const double *X = b->conf_xyz + 3 * (row + (size_t)k * na);
+            double cm[3] = {0, 0, 0}, s2 = 0.0;
+            for (int i = 0; i < na; ++i)
+                for (int d = 0; d < 3; ++d) cm[d] += X[3 * i + d] / na;
+            for (int i = 0; i < na; ++i)
+                for (int d = 0; d < 3; ++d) s2 += (X[3 * i + d] - cm[d]) * (X[3 * i + d] - cm[d]);
+            rg[k] = std::sqrt(s2 / na);
+        }
+        std::vector<int32_t> U(3 * (size_t)na);
+        for (int c = b->cfg_off[l]; c < b->cfg_off[l + 1]; ++c) {
+            float *f = feat + (size_t)c * FFTDG_N_FEATURES;
+            const double *q = b->cfg_quat + 4 * c;
+            const double nq = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+            if (!(nq > 0.0)) return set_err(ctx, FFTDG_E_INVALID, "config_features: zero quaternion");
+            const double sg = q[0] < 0.0 ? -1.0 : 1.0;
+            for (int d = 0; d < 4; ++d) f[d] = (float)(sg * q[d] / nq);
+            for (int d = 0; d < 8; ++d) f[4 + d] = (b->cfg_conf[c] % 8) == d ? 1.f : 0.f;
+            f[12] = (float)(na / 40.0);
+            f[13] = (float)(std::log((double)na) / std::log(40.0));
+            const int k = b->cfg_conf[c];
+            int box[3];
+            if (!place_one(b->conf_xyz + 3 * (row + (size_t)k * na), na, q, ctx->g.h, U.data(), box))
+                return set_err(ctx, FFTDG_E_INVALID, "config_features: placement failed");
+            for (int d = 0; d < 3; ++d) {
+                int32_t mx = U[d];
+                for (int i = 1; i < na; ++i) mx = std::max(mx, U[3 * i + d]);
+                f[14 + d] = (float)((mx / 65536.0 - 2.0) * ctx->g.h / 10.0);
+            }
+            f[17] = (float)(rg[k] / 5.0);
+        }
+        row += (size_t)nc * na;
+    }
+    return FFTDG_OK;
+}
+
 int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max_cfgs, fftdg_tuning *out,
                    double *ms_host) {
     if (!ctx) return FFTDG_E_INVALID;
