@@ -54,6 +54,139 @@ def cpu_baseline(w, budget_s: float):
                       f"+ exact clash test + partials, OpenMP over configurations, {dt:.1f} s"}
 
 
+def configs_needed(args):
+    """Configurations a BPMF estimate needs for +-0.1 kcal/mol in every
+    snapshot, plain uniform sampling vs the learned proposal, on the batched
+    141-ligand x 10-snapshot workload (seeded split: 101 training ligands,
+    40 held out).  Costs are fine-scan equivalents; a coarse pre-scan counts
+    at its measured cost ratio."""
+    import numpy as np
+    import torch
+    import paper_1708_07045_amd as fd
+    from paper_1708_07045_amd import proposal as prop
+    from workload import synth
+
+    w = synth.config3(cfg_scale=1.0)
+    T = w.T
+    kT = prop.KCAL_R * T
+    b = fd.Batch(w.ligands)
+    S = w.receptor.n_snap
+    log(f"configs needed: {len(w.ligands)} ligands, {b.n_cfg} configurations x {S} snapshots")
+    ctx_f = prop.make_context(w)
+    ctx_c = prop.make_context(w, prop.coarse_desc(w))
+    ctx_f.autotune(b, T, max_cfgs=2048)
+    ctx_c.autotune(b, T, max_cfgs=2048)
+
+    def timed_scan(ctx):
+        out = ctx.scan(b, T)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        ctx.scan(b, T, out)
+        torch.cuda.synchronize()
+        return out, time.perf_counter() - t0
+
+    part_f, t_f = timed_scan(ctx_f)
+    part_c, t_c = timed_scan(ctx_c)
+    rho = t_c / t_f
+    B_ex, res_ex = ctx_f.reduce(b, part_f, T)
+    log(f"exhaustive fine scan {t_f:.2f}s, coarse scan {t_c:.2f}s (cost ratio {rho:.3f})")
+    train_l, test_l = prop.split_ligands(len(w.ligands), 101)
+    rows = prop.rows_of(b.cfg_off, train_l)
+    X = prop.inputs(ctx_f, ctx_c, b, part_c, with_scan=True)
+    Xc = X[:, :fd.N_FEATURES].contiguous()
+    t, wt = prop.targets(ctx_f, b, part_f)
+    nets, t_train = {}, {}
+    for name, xin in (("net_scan", X), ("net_cfg", Xc)):
+        net = fd.Network(int(xin.shape[1]), 256, 512)
+        net.set_params(prop.init_params(int(xin.shape[1]), 256))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        hist = prop.train(net, xin, t, wt, rows, epochs=args.is_epochs)
+        torch.cuda.synchronize()
+        t_train[name] = time.perf_counter() - t0
+        log(f"{name}: trained {args.is_epochs} epochs on {rows.size} rows in {t_train[name]:.1f}s, "
+            f"last batch loss {hist[-1]:.4f}")
+        nets[name] = (net, xin)
+    pred = {"net_scan": nets["net_scan"][0].forward(X).cpu().numpy(),
+            "net_cfg": nets["net_cfg"][0].forward(Xc).cpu().numpy(),
+            "coarse": X[:, fd.N_FEATURES].cpu().numpy()}
+    P_f = ctx_f.partials_numpy(part_f, S, b.n_cfg)
+    alpha = 0.1
+    # temperature of the mixture, chosen on training ligands only
+    taus = (0.5, 1.0, 2.0)
+    tune_l = train_l[:: max(1, len(train_l) // args.is_tune_ligands)][: args.is_tune_ligands]
+    tau_of = {}
+    for name in pred:
+        best = None
+        for tau in taus:
+            ks = []
+            for l in tune_l:
+                Zs = prop.ligand_weights(P_f, b.cfg_off, l)
+                yl = pred[name][b.cfg_off[l]:b.cfg_off[l + 1]]
+                k, _ = prop.kstar_is(prop.sub_batch(w, l), Zs, yl, alpha, tau, kT, 1000 + int(l), reps=50)
+                ks.append(k / Zs.shape[1])
+            m = float(np.median(ks))
+            log(f"tau {tau} for {name}: median fraction {m:.3f} on {len(tune_l)} training ligands")
+            if best is None or m < best[0]:
+                best = (m, tau)
+        tau_of[name] = best[1]
+    log(f"mixture temperatures (nats) chosen on training ligands: {tau_of}")
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([170807045, 21])))
+    per = []
+    for l in test_l:
+        Zs = prop.ligand_weights(P_f, b.cfg_off, l)
+        Pl = Zs.shape[1]
+        row = {"ligand": int(l), "n_cfg": int(Pl), "plain": prop.kstar_plain(Zs, kT, rng, reps=args.is_reps)}
+        for name in pred:
+            yl = pred[name][b.cfg_off[l]:b.cfg_off[l + 1]]
+            k, bf = prop.kstar_is(prop.sub_batch(w, l), Zs, yl, alpha, tau_of[name], kT, 2000 + int(l),
+                                  reps=args.is_reps)
+            extra = rho * Pl if name in ("net_scan", "coarse") else 0.0
+            row[name] = min(float(Pl), k + extra)
+            row[name + "_budget"] = bf
+        per.append(row)
+        log(f"ligand {l}: P={Pl} plain {row['plain']:.0f}  net_scan {row['net_scan']:.0f}  "
+            f"coarse {row['coarse']:.0f}  net_cfg {row['net_cfg']:.0f}")
+    med = lambda key: float(np.median([r["plain"] / r[key] for r in per]))
+    # one real importance-sampled scan of the held-out ligands at 10 % of
+    # the configurations (5 % exact top + 5 % draws), against the exhaustive
+    bt = fd.Batch([w.ligands[l] for l in test_l])
+    yt = np.concatenate([pred["net_scan"][b.cfg_off[l]:b.cfg_off[l + 1]] for l in test_l])
+    u = synth.uniforms(31, bt.n_cfg)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    est = prop.is_estimate(ctx_f, bt, yt, 0.05, 0.05, alpha, tau_of["net_scan"], u, T)
+    torch.cuda.synchronize()
+    t_is = time.perf_counter() - t0
+    Bref = B_ex[test_l]
+    dref = res_ex["dG"][test_l]
+    dB = est["B"] - Bref
+    ddg = est["res"]["dG"] - dref
+    n_is = int(est["n_scanned"].sum())
+    return {
+        "workload": f"batched: {len(w.ligands)} ligands x {S} snapshots, {b.n_cfg} configurations, "
+                    f"101 training / {len(test_l)} held-out ligands (seeded split)",
+        "criterion": "RMS over replicates of (B_hat - B_exhaustive) <= 0.1 kcal/mol in every snapshot; "
+                     "cost = distinct fine-scanned configurations (+ coarse pre-scan at its cost ratio)",
+        "replicates": args.is_reps,
+        "coarse_cost_ratio": rho,
+        "mixture_alpha": alpha,
+        "mixture_tau_nats": tau_of,
+        "train_seconds": t_train,
+        "median_plain_over": {"net_scan": med("net_scan"), "net_cfg": med("net_cfg"), "coarse": med("coarse")},
+        "median_fraction_of_pool": {k: float(np.median([r[k] / r["n_cfg"] for r in per]))
+                                    for k in ("plain", "net_scan", "net_cfg", "coarse")},
+        "is_run_10pct": {"configs_scanned": n_is, "configs_total": int(bt.n_cfg),
+                         "fallback_ligands": int(est["fallback"].sum()),
+                         "rms_dB_kcal_mol": float(np.sqrt(np.mean(dB[np.isfinite(dB)] ** 2))),
+                         "max_abs_dB_kcal_mol": float(np.max(np.abs(dB[np.isfinite(dB)]))),
+                         "rms_ddG_kcal_mol": float(np.sqrt(np.mean(ddg ** 2))),
+                         "seconds_is_path_fine_only": t_is,
+                         "seconds_exhaustive_fine_same_ligands": t_f * bt.n_cfg / b.n_cfg},
+        "per_ligand": per,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -69,16 +202,31 @@ def main():
     ap.add_argument("--no-autotune", action="store_true", help="skip the schedule autotuner (setup, untimed)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-is", action="store_true", help="skip the configurations-needed measurement")
+    ap.add_argument("--is-only", action="store_true", help="only the configurations-needed measurement")
+    ap.add_argument("--is-reps", type=int, default=200, help="replicates per budget (configurations needed)")
+    ap.add_argument("--is-epochs", type=int, default=20)
+    ap.add_argument("--is-tune-ligands", type=int, default=12)
+    ap.add_argument("--is-detail", default="", help="write per-ligand configurations-needed results here (JSON)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the scan shards by ligand/snapshot/configuration chunk; see DESIGN.md)", file=sys.stderr)
+        print(f"bench.py: this implementation runs on one GPU; --gpus {args.gpus} is not supported "
+              "(the scan would shard by ligand, snapshot and configuration chunk)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
     import torch
     import paper_1708_07045_amd as fd
     from workload import synth
+
+    if args.is_only:
+        cn = configs_needed(args)
+        if args.is_detail:
+            with open(args.is_detail, "w") as f:
+                json.dump(cn, f, indent=1)
+        print(json.dumps({"metric": "configs needed for BPMF ±0.1 kcal/mol, MLP vs plain",
+                          "configs_needed": {k: v for k, v in cn.items() if k != "per_ligand"}}), flush=True)
+        return
 
     w = synth.config2() if args.workload == "c2" else synth.config3(cfg_scale=args.cfg_scale)
     n_snap = w.receptor.n_snap
@@ -193,6 +341,15 @@ def main():
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
     else:
         rec["cpu_baseline"] = None
+    if args.workload == "c2" and not args.no_is:
+        del ctx, out, grids, occ
+        torch.cuda.empty_cache()
+        cn = configs_needed(args)
+        rec["configs_needed"] = {k: v for k, v in cn.items() if k != "per_ligand"}
+        rec["configs_needed_median_plain_over_learned"] = cn["median_plain_over"]["net_scan"]
+        if args.is_detail:
+            with open(args.is_detail, "w") as f:
+                json.dump(cn, f, indent=1)
     print(json.dumps(rec), flush=True)
 
 

@@ -272,7 +272,7 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
  * drawn from a proposal q built from a small network's prediction of each
  * configuration's log Boltzmann weight, with exact 1/q reweighting through
  * fftdg_reduce's cfg_weight; the exhaustive scan stays the fallback and the
- * judge of its error.
+ * reference its error is measured against.
  * ------------------------------------------------------------------------ */
 
 /* Per-configuration input features (host; FFTDG_N_FEATURES floats each):
@@ -284,6 +284,48 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
  * feat_host [n_cfg_total][FFTDG_N_FEATURES]. */
 #define FFTDG_N_FEATURES 18
 int fftdg_config_features(fftdg_ctx *ctx, const fftdg_batch *b, float *feat_host);
+
+/* Per-configuration descriptors of a finished scan by this context (for
+ * instance a coarse-spacing context over the same batch, whose scan is a
+ * cheap predictor of the fine one), from partials p_dev [n_snap][n_cfg_total]
+ * and the context's snapshot weights W_s, in FP64:
+ *   x_c   = ln sum_s W_s Z_{c,s}   (Z as in fftdg_reduce, Eq. 2)
+ *   psi_c = min_s psi_min_{c,s},   f_c = sum_s n_finite / sum_s n_valid
+ * written as floats into columns col0 .. col0+2 of the row-major device
+ * matrix feat_dev [n_cfg_total][ld]:
+ *   (max(x_c - max_l x, -25) / 5,  min(psi_c - min_l psi, 50) / 10,  f_c)
+ * with max_l / min_l over the configurations of the same ligand; a
+ * configuration with nothing finite gets (-5, 5, 0).  Other columns are not
+ * touched.  Asynchronous on the context's stream. */
+#define FFTDG_N_SCAN_FEATURES 3
+int fftdg_scan_features(fftdg_ctx *ctx, const fftdg_batch *b, const fftdg_partial *p_dev, float *feat_dev,
+                        int32_t ld, int32_t col0);
+
+/* Stratified importance-sampling plan over each ligand's P configurations
+ * (host only).  From predicted log weights yhat_host [n_cfg_total]:
+ *   - the n_top = ceil(top_frac P) configurations of largest yhat (ties to
+ *     the lower index) are scanned exactly: select 1, weight 1;
+ *   - over the other R = P - n_top, taken in increasing index order, the
+ *     defensive mixture q_j = (1 - alpha) softmax(yhat / tau)_j + alpha / R
+ *     (FP64) is sampled K = ceil(draw_frac P) times (none if R = 0) by
+ *     inverse CDF: draw k takes the first j whose running sum of q exceeds
+ *     u_k times the total; a drawn configuration gets select 2 and weight
+ *     multiplicity / (K q_j);
+ *   - all others: select 0, weight 0.
+ * Uniforms u_host in [0, 1) are consumed in ligand order (ligand 0's K
+ * first); n_u must cover them all.  With these weights fftdg_reduce returns
+ *   Z_hat = sum_top Z_c + (1/K) sum_k Z_{c_k} / q_{c_k},
+ * an unbiased estimate of sum_c Z_c for any yhat (exact when top_frac = 1).
+ * select_host [n_cfg_total] (nonzero = scan; 1 exact stratum, 2 drawn) can
+ * be used as the batch's cfg_select and
+ * weight_host [n_cfg_total] (upload it) as fftdg_reduce's cfg_weight.
+ * n_scan_host (may be NULL) receives the number of selected configurations.
+ * Host only: needs no device, and ctx may be NULL (no error text is kept).
+ * E_INVALID: NULL pointer, fractions outside [0, 1], alpha outside [0, 1],
+ * tau <= 0, non-finite yhat, too few uniforms. */
+int fftdg_is_plan(fftdg_ctx *ctx, const fftdg_batch *b, const float *yhat_host, double top_frac,
+                  double draw_frac, double alpha, double tau, const double *u_host, int64_t n_u,
+                  uint8_t *select_host, double *weight_host, int64_t *n_scan_host);
 
 /* Network: n_in inputs -> 3 hidden layers of `width` SiLU units -> 1 linear
  * output; BF16 MFMA products with FP32 accumulation, FP32 master parameters,

@@ -9,7 +9,10 @@ Each function is the plain formula from the paper, in double precision:
     -kT ln(V_site C0) (Omega / 8 pi^2 = V_site);
   - importance-sampled and uniformly subsampled forms of Eq. 2 over
     configurations, and the bootstrap over configurations used for the
-    convergence figure of the results section.
+    convergence figure of the results section;
+  - not in the paper: the learned proposal's stratified sampling plan
+    (exact top stratum + defensive-mixture draws, weighted forms of Eq. 2)
+    and the per-configuration scan descriptors it takes as inputs.
 Partials are rows (m, s, n_valid, n_finite, psi_min, argmin) with
 x = -beta Psi, m = max x and s = sum exp(x - m) over one configuration.
 """
@@ -147,3 +150,87 @@ def inverse_cdf_sample(q: np.ndarray, uniforms: np.ndarray) -> np.ndarray:
     cdf = np.cumsum(np.asarray(q, dtype=np.float64))
     u = np.asarray(uniforms, dtype=np.float64) * cdf[-1]
     return np.minimum(np.searchsorted(cdf, u, side="right"), len(q) - 1)
+
+
+def bpmf_weighted(logz_cfg: np.ndarray, n_total: float, weight: np.ndarray, T: float) -> float:
+    """Eq. 2 with per-configuration weights w_c >= 0 on the numerator:
+    B = -kT [ ln sum_{w_c > 0} w_c Z_c - ln n_total ]; +inf if the sum is 0."""
+    lz = np.asarray(logz_cfg, dtype=np.float64)
+    w = np.asarray(weight, dtype=np.float64)
+    ok = (w > 0) & np.isfinite(lz)
+    val = lse(np.log(w[ok]) + lz[ok]) if np.any(ok) else -math.inf
+    if val == -math.inf or n_total <= 0:
+        return math.inf
+    return -kT(T) * (val - math.log(n_total))
+
+
+def stratified_plan(yhat: np.ndarray, cfg_off: np.ndarray, top_frac: float, draw_frac: float,
+                    alpha: float, tau: float, uniforms: np.ndarray):
+    """Stratified importance sampling over each ligand's configurations
+    (not in the paper; the proposal's sampling plan).  Per ligand of P
+    configurations: the ceil(top_frac P) largest yhat (ties to the lower
+    index) form an exact stratum (weight 1); the remaining R, in index order,
+    are sampled K = ceil(draw_frac P) times from the defensive mixture over
+    them (`proposal`, `inverse_cdf_sample`), each drawn one weighted
+    multiplicity / (K q).  Uniforms are consumed ligand by ligand.  Returns
+    (select uint8: 1 exact stratum, 2 drawn, 0 not scanned; weight float64)
+    over all configurations."""
+    y = np.asarray(yhat, dtype=np.float64)
+    u = np.asarray(uniforms, dtype=np.float64)
+    sel = np.zeros(y.size, np.uint8)
+    wt = np.zeros(y.size)
+    used = 0
+    for l in range(len(cfg_off) - 1):
+        a, b = int(cfg_off[l]), int(cfg_off[l + 1])
+        P = b - a
+        if P == 0:
+            continue
+        nt = min(P, math.ceil(top_frac * P))
+        order = sorted(range(P), key=lambda j: (-y[a + j], j))
+        top = np.zeros(P, bool)
+        top[order[:nt]] = True
+        sel[a:b][top] = 1
+        wt[a:b][top] = 1.0
+        rest = np.flatnonzero(~top)
+        K = math.ceil(draw_frac * P) if rest.size else 0
+        if K == 0:
+            continue
+        q = proposal(y[a + rest], alpha, tau)
+        draws = inverse_cdf_sample(q, u[used:used + K])
+        used += K
+        mult = np.bincount(draws, minlength=rest.size)
+        hit = mult > 0
+        sel[a + rest[hit]] = 2
+        wt[a + rest[hit]] = mult[hit] / (K * q[hit])
+    return sel, wt
+
+
+def scan_features(parts_by_snap, W: np.ndarray, cfg_off: np.ndarray) -> np.ndarray:
+    """Per-configuration scan descriptors (the proposal network's inputs
+    taken from a finished scan): x_c = ln sum_s W_s Z_{c,s} (W normalised),
+    psi_c = min_s psi_min, f_c = sum_s n_finite / sum_s n_valid; returned as
+    (max(x_c - max_l x, -25) / 5, min(psi_c - min_l psi, 50) / 10, f_c), max_l
+    and min_l over the ligand's configurations; (-5, 5, 0) when nothing is
+    finite.  parts_by_snap: [n_snap][n_cfg][6] partial rows."""
+    p = np.asarray(parts_by_snap, dtype=np.float64)
+    W = np.asarray(W, dtype=np.float64)
+    W = W / W.sum()
+    S, C = p.shape[0], p.shape[1]
+    x = np.full(C, -math.inf)
+    for c in range(C):
+        terms = [math.log(W[s]) + log_z(p[s, c:c + 1])[0] for s in range(S) if W[s] > 0]
+        x[c] = lse(np.array(terms)) if terms else -math.inf
+    psi = p[:, :, 4].min(axis=0)
+    nv = p[:, :, 2].sum(axis=0)
+    f = np.where(nv > 0, p[:, :, 3].sum(axis=0) / np.where(nv > 0, nv, 1), 0.0)
+    out = np.zeros((C, 3))
+    for l in range(len(cfg_off) - 1):
+        a, b = int(cfg_off[l]), int(cfg_off[l + 1])
+        if b == a:
+            continue
+        X, PM = np.max(x[a:b]), np.min(psi[a:b])
+        for c in range(a, b):
+            out[c, 0] = max(x[c] - X, -25.0) / 5.0 if np.isfinite(x[c]) else -5.0
+            out[c, 1] = min(psi[c] - PM, 50.0) / 10.0 if np.isfinite(psi[c]) else 5.0
+            out[c, 2] = f[c]
+    return out

@@ -55,9 +55,10 @@ EXPORTS = ["fftdg_version", "fftdg_status_string", "fftdg_create", "fftdg_destro
            "fftdg_get_tuning", "fftdg_set_tuning", "fftdg_autotune", "fftdg_config_features",
            "fftdg_mlp_create", "fftdg_mlp_destroy", "fftdg_mlp_last_error", "fftdg_mlp_num_params",
            "fftdg_mlp_set_params", "fftdg_mlp_get_params", "fftdg_mlp_forward", "fftdg_mlp_grad",
-           "fftdg_mlp_train_step", "fftdg_proposal_sample"]
+           "fftdg_mlp_train_step", "fftdg_proposal_sample", "fftdg_scan_features", "fftdg_is_plan"]
 
 N_FEATURES = 18
+N_SCAN_FEATURES = 3
 
 KERNEL_NAMES = ["lig_fwd_xy", "zprod", "inv_xy_lse", "merge", "rec_spectra", "reduce"]
 
@@ -107,6 +108,8 @@ def load():
     L.fftdg_mlp_grad.argtypes = [p, p, p, p, p, i32, p, p]
     L.fftdg_mlp_train_step.argtypes = [p, p, p, p, p, i32, ctypes.c_float, p]
     L.fftdg_proposal_sample.argtypes = [p, p, i32, d, d, i32, p, p, p]
+    L.fftdg_scan_features.argtypes = [p, ctypes.POINTER(BatchC), p, p, i32, i32]
+    L.fftdg_is_plan.argtypes = [p, ctypes.POINTER(BatchC), p, d, d, d, d, p, ctypes.c_int64, p, p, p]
     for name in EXPORTS:
         if name not in ("fftdg_destroy", "fftdg_status_string", "fftdg_last_error", "fftdg_mlp_destroy",
                         "fftdg_mlp_last_error", "fftdg_mlp_num_params"):
@@ -321,6 +324,21 @@ class FFTDG:
         self._check(self.L.fftdg_place(self.h_ctx, ctypes.byref(batch.c), cfg, _ptr(U), _ptr(box)))
         return U, box
 
+    def scan_features(self, batch: Batch, partials, feat, col0: int):
+        """Write the N_SCAN_FEATURES descriptors of this context's scan into
+        columns col0.. of the device float matrix feat [n_cfg][ld]."""
+        t = self.torch
+        assert feat.dtype == t.float32 and feat.dim() == 2 and feat.is_contiguous()
+        assert feat.shape[0] == batch.n_cfg
+        self._check(self.L.fftdg_scan_features(self.h_ctx, ctypes.byref(batch.c), _ptr(partials), _ptr(feat),
+                                               int(feat.shape[1]), int(col0)))
+        return feat
+
+    def is_plan(self, batch: Batch, yhat, top_frac: float, draw_frac: float, alpha: float, tau: float,
+                uniforms):
+        """Stratified importance-sampling plan (see is_plan)."""
+        return is_plan(batch, yhat, top_frac, draw_frac, alpha, tau, uniforms, self)
+
     def reduce(self, batch: Batch, partials, T: float, cfg_weight=None):
         B = np.zeros((batch.n_lig, self.n_snap), np.float64)
         res = np.zeros(batch.n_lig, RESULT_DTYPE)
@@ -330,6 +348,26 @@ class FFTDG:
         self._check(self.L.fftdg_reduce(self.h_ctx, ctypes.byref(batch.c), _ptr(partials), _ptr(w), float(T),
                                         _ptr(B), _ptr(res)))
         return B, res
+
+
+def is_plan(batch: Batch, yhat, top_frac: float, draw_frac: float, alpha: float, tau: float, uniforms,
+            ctx: Optional["FFTDG"] = None):
+    """fftdg_is_plan (host only): (select uint8 [n_cfg], weight float64
+    [n_cfg], number of configurations selected)."""
+    L = load()
+    y = yhat.detach().float().cpu().numpy() if hasattr(yhat, "detach") else np.asarray(yhat)
+    y = np.ascontiguousarray(y, np.float32)
+    u = np.ascontiguousarray(uniforms, np.float64)
+    sel = np.zeros(batch.n_cfg, np.uint8)
+    wt = np.zeros(batch.n_cfg, np.float64)
+    n = ctypes.c_int64()
+    h = ctx.h_ctx if ctx is not None else None
+    rc = L.fftdg_is_plan(h, ctypes.byref(batch.c), _ptr(y), float(top_frac), float(draw_frac), float(alpha),
+                         float(tau), _ptr(u), int(u.size), _ptr(sel), _ptr(wt), ctypes.byref(n))
+    if rc != OK:
+        msg = L.fftdg_last_error(h).decode() if h else L.fftdg_status_string(rc).decode()
+        raise FFTDGError(rc, "fftdg_is_plan: " + msg)
+    return sel, wt, int(n.value)
 
 
 class Network:

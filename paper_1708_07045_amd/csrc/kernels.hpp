@@ -41,6 +41,9 @@ hipError_t launch_reduce(hipStream_t st, const fftdg_partial *p, int64_t n_cfg_t
                          const int32_t *cfg_off, const double *cfg_w, const double *W, double kT, double h3,
                          double c0, double *B, LigRed *res);
 
+hipError_t launch_scan_features(hipStream_t st, const fftdg_partial *p, int64_t n_cfg_total, int n_snap, int n_lig,
+                                const int32_t *cfg_off, const double *W, float *feat, int ld, int col0);
+
 hipError_t launch_receptor_grids(hipStream_t st, int precision, int n_atoms, const double *xyz, const double *q,
                                  const double *sg, const double *ep, int n_rec, double h, const double *origin,
                                  int mode, double cap, double occ_f, void *grids, uint8_t *occ);

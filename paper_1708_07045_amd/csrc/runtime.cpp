@@ -1089,4 +1089,109 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
     return FFTDG_OK;
 }
 
+int fftdg_scan_features(fftdg_ctx *ctx, const fftdg_batch *b, const fftdg_partial *p, float *feat, int32_t ld,
+                        int32_t col0) {
+    if (!ctx) return FFTDG_E_INVALID;
+    if (ctx->n_snap <= 0) return set_err(ctx, FFTDG_E_STATE, "scan_features before set_receptors");
+    if (!b || b->n_lig <= 0 || !b->cfg_off) return set_err(ctx, FFTDG_E_INVALID, "scan_features: bad batch");
+    if (!p || !feat) return set_err(ctx, FFTDG_E_INVALID, "scan_features: NULL pointer");
+    if (col0 < 0 || ld < col0 + FFTDG_N_SCAN_FEATURES)
+        return set_err(ctx, FFTDG_E_INVALID, "scan_features: columns col0..col0+2 must lie within ld");
+    for (int l = 0; l < b->n_lig; ++l)
+        if (b->cfg_off[l + 1] < b->cfg_off[l]) return set_err(ctx, FFTDG_E_INVALID, "scan_features: bad cfg_off");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const int nl = b->n_lig, ns = ctx->n_snap;
+    int rc;
+    if ((rc = reserve(ctx, ctx->red_off, sizeof(int32_t) * (nl + 1)))) return rc;
+    if ((rc = reserve(ctx, ctx->red_W, sizeof(double) * ns))) return rc;
+    HIPCHK(ctx, hipMemcpyAsync(ctx->red_off.p, b->cfg_off, sizeof(int32_t) * (nl + 1), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(ctx->red_W.p, ctx->W.data(), sizeof(double) * ns, hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, launch_scan_features(ctx->stream, p, b->cfg_off[nl], ns, nl, (const int32_t *)ctx->red_off.p,
+                                     (const double *)ctx->red_W.p, feat, ld, col0));
+    return FFTDG_OK;
+}
+
+int fftdg_is_plan(fftdg_ctx *ctx, const fftdg_batch *b, const float *yhat, double top_frac, double draw_frac,
+                  double alpha, double tau, const double *u, int64_t n_u, uint8_t *sel, double *wt,
+                  int64_t *n_scan) {
+    // host only; ctx (may be NULL) just keeps the error message
+    if (!b || b->n_lig <= 0 || !b->cfg_off) return set_err(ctx, FFTDG_E_INVALID, "is_plan: bad batch");
+    if (!yhat || !sel || !wt || (!u && n_u > 0)) return set_err(ctx, FFTDG_E_INVALID, "is_plan: NULL pointer");
+    if (!(top_frac >= 0.0 && top_frac <= 1.0) || !(draw_frac >= 0.0 && draw_frac <= 1.0))
+        return set_err(ctx, FFTDG_E_INVALID, "is_plan: fractions must lie in [0, 1]");
+    if (!(alpha >= 0.0 && alpha <= 1.0)) return set_err(ctx, FFTDG_E_INVALID, "is_plan: alpha must lie in [0, 1]");
+    if (!(tau > 0.0) || !is_fin(tau)) return set_err(ctx, FFTDG_E_INVALID, "is_plan: tau must be > 0");
+    const int nl = b->n_lig;
+    // uniforms needed, checked before anything is written
+    int64_t need = 0;
+    for (int l = 0; l < nl; ++l) {
+        const int P = b->cfg_off[l + 1] - b->cfg_off[l];
+        if (P < 0) return set_err(ctx, FFTDG_E_INVALID, "is_plan: bad cfg_off");
+        const int nt = std::min<int64_t>(P, (int64_t)std::ceil(top_frac * P));
+        if (P - nt > 0) need += (int64_t)std::ceil(draw_frac * P);
+    }
+    if (need > n_u) return set_err(ctx, FFTDG_E_INVALID, "is_plan: fewer uniforms than draws");
+    for (int64_t c = 0; c < (int64_t)b->cfg_off[nl]; ++c)
+        if (!is_fin((double)yhat[c])) return set_err(ctx, FFTDG_E_INVALID, "is_plan: non-finite prediction");
+    for (int64_t k = 0; k < need; ++k)
+        if (!(u[k] >= 0.0 && u[k] < 1.0)) return set_err(ctx, FFTDG_E_INVALID, "is_plan: uniforms must lie in [0, 1)");
+    int64_t used = 0, n_sel = 0;
+    std::vector<int> order, rest;
+    std::vector<double> cdf;
+    for (int l = 0; l < nl; ++l) {
+        const int c0 = b->cfg_off[l], P = b->cfg_off[l + 1] - c0;
+        for (int j = 0; j < P; ++j) {
+            sel[c0 + j] = 0;
+            wt[c0 + j] = 0.0;
+        }
+        if (P == 0) continue;
+        const int nt = (int)std::min<int64_t>(P, (int64_t)std::ceil(top_frac * P));
+        order.resize(P);
+        for (int j = 0; j < P; ++j) order[j] = j;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](int a, int c) { return yhat[c0 + a] > yhat[c0 + c]; });
+        std::vector<uint8_t> top(P, 0);
+        for (int j = 0; j < nt; ++j) {
+            top[order[j]] = 1;
+            sel[c0 + order[j]] = 1;
+            wt[c0 + order[j]] = 1.0;
+        }
+        const int R = P - nt;
+        if (R == 0) continue;
+        const int K = (int)std::ceil(draw_frac * P);
+        if (K == 0) continue;
+        rest.clear();
+        for (int j = 0; j < P; ++j)
+            if (!top[j]) rest.push_back(j);
+        double ymax = -INFINITY;
+        for (int j : rest) ymax = std::max(ymax, (double)yhat[c0 + j] / tau);
+        double se = 0.0;
+        for (int j : rest) se += std::exp((double)yhat[c0 + j] / tau - ymax);
+        cdf.resize(R);
+        std::vector<double> q(R);
+        double run = 0.0;
+        for (int i = 0; i < R; ++i) {
+            q[i] = (1.0 - alpha) * std::exp((double)yhat[c0 + rest[i]] / tau - ymax) / se + alpha / R;
+            run += q[i];
+            cdf[i] = run;
+        }
+        std::vector<int> mult(R, 0);
+        for (int k = 0; k < K; ++k) {
+            const double x = u[used + k] * cdf[R - 1];
+            int i = (int)(std::upper_bound(cdf.begin(), cdf.end(), x) - cdf.begin());
+            if (i > R - 1) i = R - 1;
+            ++mult[i];
+        }
+        used += K;
+        for (int i = 0; i < R; ++i)
+            if (mult[i] > 0) {
+                sel[c0 + rest[i]] = 2;
+                wt[c0 + rest[i]] = (double)mult[i] / ((double)K * q[i]);
+            }
+    }
+    for (int64_t c = 0; c < (int64_t)b->cfg_off[nl]; ++c) n_sel += sel[c] != 0;
+    if (n_scan) *n_scan = n_sel;
+    return FFTDG_OK;
+}
+
 }  // extern "C"

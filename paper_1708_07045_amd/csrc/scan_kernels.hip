@@ -1234,6 +1234,78 @@ __global__ __launch_bounds__(NT) void k_reduce(const fftdg_partial *__restrict__
     }
 }
 
+// Per-configuration descriptors of a finished scan (inputs of the learned
+// proposal), one block per ligand, FP64:
+//   x_c   = ln sum_s W_s Z_{c,s}            (Eq. 2 numerator of one configuration)
+//   psi_c = min_s psi_min_{c,s}
+//   f_c   = sum_s n_finite / sum_s n_valid
+// written as floats  (max(x_c - max_c' x_c', -25) / 5,
+//                     min(psi_c - min_c' psi_c', 50) / 10,  f_c)
+// into columns col0..col0+2 of the row-major matrix feat[n_cfg][ld].
+// Configurations with nothing finite get (-5, 5, 0).
+__device__ __forceinline__ void cfg_stats(const fftdg_partial *__restrict__ p, int64_t n_cfg_total, int n_snap,
+                                          const double *__restrict__ W, int c, double &x, double &psi,
+                                          double &frac) {
+    double mx = -INFINITY;
+    psi = INFINITY;
+    long long nv = 0, nf = 0;
+    for (int s = 0; s < n_snap; ++s) {
+        const fftdg_partial q = p[(int64_t)s * n_cfg_total + c];
+        nv += q.n_valid;
+        nf += q.n_finite;
+        if (q.psi_min < psi) psi = q.psi_min;
+        if (q.n_finite > 0 && W[s] > 0.0) {
+            const double v = log(W[s]) + q.m + log(q.s);
+            if (v > mx) mx = v;
+        }
+    }
+    double sum = 0.0;
+    if (mx > -INFINITY)
+        for (int s = 0; s < n_snap; ++s) {
+            const fftdg_partial q = p[(int64_t)s * n_cfg_total + c];
+            if (q.n_finite > 0 && W[s] > 0.0) sum += exp(log(W[s]) + q.m + log(q.s) - mx);
+        }
+    x = mx > -INFINITY ? mx + log(sum) : -INFINITY;
+    frac = nv > 0 ? (double)nf / (double)nv : 0.0;
+}
+
+__global__ __launch_bounds__(NT) void k_scan_features(const fftdg_partial *__restrict__ p, int64_t n_cfg_total,
+                                                       int n_snap, const int32_t *__restrict__ cfg_off,
+                                                       const double *__restrict__ W, float *__restrict__ feat,
+                                                       int ld, int col0) {
+    __shared__ double sx[NT], sp[NT];
+    const int lig = blockIdx.x, t = threadIdx.x;
+    const int c0i = cfg_off[lig], c1i = cfg_off[lig + 1];
+    double xm = -INFINITY, pm = INFINITY;
+    for (int c = c0i + t; c < c1i; c += NT) {
+        double x, psi, f;
+        cfg_stats(p, n_cfg_total, n_snap, W, c, x, psi, f);
+        if (x > xm) xm = x;
+        if (psi < pm) pm = psi;
+    }
+    sx[t] = xm;
+    sp[t] = pm;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (t < w) {
+            sx[t] = sx[t] > sx[t + w] ? sx[t] : sx[t + w];
+            sp[t] = sp[t] < sp[t + w] ? sp[t] : sp[t + w];
+        }
+        __syncthreads();
+    }
+    const double X = sx[0], PM = sp[0];
+    for (int c = c0i + t; c < c1i; c += NT) {
+        double x, psi, f;
+        cfg_stats(p, n_cfg_total, n_snap, W, c, x, psi, f);
+        const double a = x > -INFINITY ? fmax(x - X, -25.0) / 5.0 : -5.0;
+        const double b = psi < INFINITY ? fmin(psi - PM, 50.0) / 10.0 : 5.0;
+        float *row = feat + (int64_t)c * ld + col0;
+        row[0] = (float)a;
+        row[1] = (float)b;
+        row[2] = (float)f;
+    }
+}
+
 // Eq. 7 receptor grids and Eq. 10 occupancy from atoms, FP64, one thread per
 // grid point, atoms staged through LDS in order.
 #pragma clang fp contract(off)
@@ -1394,6 +1466,13 @@ hipError_t launch_reduce(hipStream_t st, const fftdg_partial *p, int64_t n_cfg_t
                          double c0, double *B, LigRed *res) {
     hipLaunchKernelGGL(k_reduce, dim3(n_lig), dim3(NT), 0, st, p, n_cfg_total, n_snap, cfg_off, cfg_w, W, kT, h3,
                        c0, B, res);
+    return hipGetLastError();
+}
+
+hipError_t launch_scan_features(hipStream_t st, const fftdg_partial *p, int64_t n_cfg_total, int n_snap, int n_lig,
+                                const int32_t *cfg_off, const double *W, float *feat, int ld, int col0) {
+    hipLaunchKernelGGL(k_scan_features, dim3(n_lig), dim3(NT), 0, st, p, n_cfg_total, n_snap, cfg_off, W, feat, ld,
+                       col0);
     return hipGetLastError();
 }
 

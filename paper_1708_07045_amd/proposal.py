@@ -1,0 +1,253 @@
+"""Learned importance sampling over ligand configurations (driver).
+
+Not part of the paper.  Eq. 2 pools every configuration of a ligand; when a
+few configurations carry most of the Boltzmann weight, a subset chosen with a
+proposal close to those weights estimates the same sum with fewer scans.
+Z_{c,s} = sum_t exp(-Psi/kT) is configuration c's weight in snapshot s.
+
+Pipeline, each step a library call (this module only arranges them):
+  1. a coarse-spacing context (twice the spacing, half the grid edge) scans
+     every configuration: about 1/12 of the cost of the fine scan;
+  2. per-configuration inputs: fftdg_config_features (rotation, conformer,
+     size, extent) and fftdg_scan_features of the coarse scan;
+  3. the network (fftdg_mlp, BF16 MFMA) predicts each configuration's
+     relative log weight ln sum_s W_s Z_{c,s} - max (in units of 5 nats, the
+     scale of the scan descriptors); it is trained with the library's Adam
+     step on exhaustive fine scans of training ligands, the targets being
+     fftdg_scan_features of those scans;
+  4. fftdg_is_plan: the top fraction by prediction is scanned exactly, the
+     rest sampled from a defensive mixture with 1/q weights;
+  5. fftdg_scan with cfg_select, fftdg_reduce with cfg_weight: unbiased
+     B_s and dG;
+  6. fallback: when the sampled remainder carries more than `max_share` of
+     the estimate in any snapshot, the ligand is scanned exhaustively.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+
+from . import _lib as fd
+
+KCAL_R = 1.987204259e-3
+N_IN_FULL = fd.N_FEATURES + fd.N_SCAN_FEATURES
+
+
+def coarse_desc(w, factor: int = 2) -> dict:
+    """Grid of a coarse context covering the same box: spacing x factor,
+    edges / factor."""
+    n_rec = w.n_rec // factor
+    h = w.h * factor
+    centre = np.asarray(w.origin, np.float64) + 0.5 * (w.n_rec - 1) * w.h
+    return dict(n_rec=n_rec, n_fft=w.n_fft // factor, h=h, origin=centre - 0.5 * (n_rec - 1) * h)
+
+
+def make_context(w, grid: Optional[dict] = None, device: int = 0):
+    """Context with receptor grids of every snapshot built and set."""
+    import torch
+    g = dict(n_rec=w.n_rec, n_fft=w.n_fft, h=w.h, origin=w.origin)
+    if grid:
+        g.update(grid)
+    ctx = fd.FFTDG(g["n_rec"], g["n_fft"], g["h"], g["origin"], w.precision, w.clash_mode, w.ljr_cap, w.occ_f,
+                   device)
+    gl, ol = [], []
+    for s in range(w.receptor.n_snap):
+        gg, oo = ctx.receptor_grids(w.receptor.xyz[s], w.receptor.q, w.receptor.sigma, w.receptor.eps)
+        gl.append(gg)
+        ol.append(oo)
+    grids = torch.stack(gl).contiguous()
+    occ = torch.stack(ol).contiguous() if w.clash_mode == "occ" else None
+    ctx.set_receptors(grids, occ, w.receptor.weights)
+    ctx._grids = (grids, occ)
+    return ctx
+
+
+def inputs(ctx_fine, ctx_coarse, batch, part_coarse, with_scan: bool = True):
+    """Device float matrix [n_cfg][N_FEATURES (+ N_SCAN_FEATURES)]."""
+    import torch
+    F = ctx_fine.features(batch)
+    n_in = N_IN_FULL if with_scan else fd.N_FEATURES
+    X = torch.zeros((batch.n_cfg, n_in), dtype=torch.float32, device=ctx_fine.device)
+    X[:, :fd.N_FEATURES] = torch.as_tensor(F, device=ctx_fine.device)
+    if with_scan:
+        ctx_coarse.scan_features(batch, part_coarse, X, fd.N_FEATURES)
+    return X
+
+
+def targets(ctx_fine, batch, part_fine):
+    """(t [n_cfg] relative log weight / 5 on the device, loss weights): the
+    first scan descriptor of an exhaustive fine scan; configurations within
+    5 nats of their ligand's best weigh 10x."""
+    import torch
+    D = torch.zeros((batch.n_cfg, fd.N_SCAN_FEATURES), dtype=torch.float32, device=ctx_fine.device)
+    ctx_fine.scan_features(batch, part_fine, D, 0)
+    t = D[:, 0].contiguous()
+    w = np.where(t.cpu().numpy() > -1.0, 10.0, 1.0).astype(np.float32)
+    return t, torch.as_tensor(w, device=ctx_fine.device)
+
+
+def init_params(n_in: int, width: int, seed: int = 0) -> np.ndarray:
+    """Flat FP32 parameters (fftdg_mlp layout), each weight and bias
+    uniform in +-1/sqrt(fan_in)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([170807045, 5, seed])))
+    out = []
+    for rows, cols in ((width, n_in), (width, width), (width, width), (1, width)):
+        a = 1.0 / np.sqrt(cols)
+        out.append(rng.uniform(-a, a, rows * cols))
+        out.append(rng.uniform(-a, a, rows))
+    return np.concatenate(out).astype(np.float32)
+
+
+def train(net, X, t, w, rows: np.ndarray, epochs: int = 20, batch: int = 512, lr: float = 1e-3,
+          seed: int = 0, log=None):
+    """Adam with the library's kernels over the given rows (device tensors
+    X, t, w); the learning rate decays linearly to lr/10.  Returns the last
+    batch loss of each epoch."""
+    import torch
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([170807045, 7, seed])))
+    rows = np.asarray(rows, np.int32)
+    n_steps = epochs * max(1, rows.size // batch)
+    step, hist = 0, []
+    for ep in range(epochs):
+        idx = torch.as_tensor(rows[rng.permutation(rows.size)], device=X.device)
+        last = None
+        nb = max(1, rows.size // batch)
+        for k in range(nb):
+            f = 1.0 - 0.9 * step / max(1, n_steps - 1)
+            last = net.train_step(X, t, w, idx[k * batch:(k + 1) * batch], lr * f, want_loss=(k == nb - 1))
+            step += 1
+        hist.append(last)
+        if log:
+            log(f"epoch {ep + 1}/{epochs}: batch loss {last:.4f}")
+    return hist
+
+
+def predict(net, X):
+    """Network prediction (device float [n]), in units of 5 nats."""
+    return net.forward(X)
+
+
+def is_estimate(ctx, batch, yhat, top_frac: float, draw_frac: float, alpha: float, tau: float, uniforms,
+                T: float, max_share: float = 0.5):
+    """Importance-sampled B [n_lig][n_snap] and per-ligand results from one
+    plan, with the exhaustive fallback per ligand.
+
+    yhat is in units of 5 nats, so the mixture's temperature is tau / 5 in
+    those units (tau in nats).  Returns dict(B, res, n_scanned (per ligand),
+    fallback (per ligand, bool), share (per ligand: the largest fraction of
+    a snapshot's estimate that came from sampled configurations))."""
+    sel, wt, _ = ctx.is_plan(batch, yhat, top_frac, draw_frac, alpha, tau / 5.0, uniforms)
+    bsel = batch.with_select(sel)
+    part = ctx.scan(bsel, T)
+    B, res = ctx.reduce(bsel, part, T, cfg_weight=wt)
+    P = ctx.partials_numpy(part, ctx.n_snap, batch.n_cfg)
+    fin = P["n_finite"] > 0
+    lz = np.where(fin, P["m"] + np.log(np.where(fin, P["s"], 1.0)), -np.inf)
+    nl = batch.n_lig
+    share = np.zeros(nl)
+    n_scanned = np.zeros(nl, np.int64)
+    for l in range(nl):
+        a, b = batch.cfg_off[l], batch.cfg_off[l + 1]
+        n_scanned[l] = np.count_nonzero(sel[a:b])
+        z = lz[:, a:b] + np.log(np.where(wt[a:b] > 0, wt[a:b], 1.0))[None, :]
+        z = np.where((wt[a:b] > 0)[None, :], z, -np.inf)
+        m = np.max(z, axis=1, keepdims=True)
+        ok = np.isfinite(m[:, 0])
+        if not np.any(ok):
+            continue
+        e = np.exp(z[ok] - m[ok])
+        share[l] = np.max(e[:, sel[a:b] == 2].sum(axis=1) / e.sum(axis=1))
+    fallback = share > max_share
+    if np.any(fallback):
+        full = np.zeros(batch.n_cfg, np.uint8)
+        for l in np.flatnonzero(fallback):
+            full[batch.cfg_off[l]:batch.cfg_off[l + 1]] = 1
+        bf = batch.with_select(full)
+        pf = ctx.scan(bf, T)
+        Bf, rf = ctx.reduce(bf, pf, T)
+        for l in np.flatnonzero(fallback):
+            B[l] = Bf[l]
+            res[l] = rf[l]
+            n_scanned[l] = batch.cfg_off[l + 1] - batch.cfg_off[l]
+    return dict(B=B, res=res, n_scanned=n_scanned, fallback=fallback, share=share)
+
+
+# --------------------------------------------------------------------------
+# Measurement: configurations needed for +-0.1 kcal/mol (replicate protocol)
+# --------------------------------------------------------------------------
+
+BUDGETS = (0.01, 0.02, 0.03, 0.05, 0.07, 0.1, 0.15, 0.2, 0.3, 0.5)
+PLAIN_K = (25, 50, 100, 200, 400, 800, 1600, 3200)
+
+
+def _err_rms(Zs, Zw, kT):
+    """RMS over replicates of kT ln(Z_hat / Z) per snapshot: Zs [S][P]
+    (exhaustive, scaled), Zw [R][S] replicate estimates of sum_c Zs."""
+    with np.errstate(divide="ignore"):
+        e = -kT * (np.log(Zw) - np.log(Zs.sum(axis=1))[None, :])
+    e = np.where(np.isfinite(e), e, 1e3)
+    return np.sqrt(np.mean(e ** 2, axis=0))
+
+
+def kstar_plain(Zs, kT, rng, reps: int = 200, tol: float = 0.1):
+    """Distinct configurations a uniform with-replacement sample needs for
+    RMS <= tol in every snapshot (the exhaustive scan, P, if none does)."""
+    P = Zs.shape[1]
+    for K in PLAIN_K:
+        idx = rng.integers(0, P, (reps, K))
+        Zw = Zs[:, idx].mean(axis=2).T * P
+        if np.max(_err_rms(Zs, Zw, kT)) <= tol:
+            return min(float(P), float(np.mean([np.unique(r).size for r in idx])))
+    return float(P)
+
+
+def kstar_is(sub_batch, Zs, yhat, alpha, tau, kT, seed0, reps: int = 200, tol: float = 0.1):
+    """Same for the stratified plan (half the budget exact top, half draws)
+    over the budget fractions BUDGETS; returns (distinct configurations,
+    budget fraction) or (P, None)."""
+    P = Zs.shape[1]
+    for bf in BUDGETS:
+        half = bf / 2.0
+        K = int(np.ceil(half * P))
+        Wr = np.zeros((reps, P))
+        ns = np.zeros(reps)
+        for r in range(reps):
+            u = np.random.Generator(np.random.PCG64(np.random.SeedSequence([170807045, seed0, r]))).random(K + 1)
+            sel, wt, n = fd.is_plan(sub_batch, yhat, half, half, alpha, tau / 5.0, u)
+            Wr[r] = wt
+            ns[r] = n
+        Zw = Wr @ Zs.T
+        if np.max(_err_rms(Zs, Zw, kT)) <= tol:
+            return float(np.mean(ns)), bf
+    return float(P), None
+
+
+def ligand_weights(P_fine, cfg_off, l):
+    """Exhaustive Z_{c,s} of ligand l scaled by the per-snapshot maximum
+    (host FP64) from fine partials [S][n_cfg]."""
+    a, b = cfg_off[l], cfg_off[l + 1]
+    p = P_fine[:, a:b]
+    fin = p["n_finite"] > 0
+    lz = np.where(fin, p["m"] + np.log(np.where(fin, p["s"], 1.0)), -np.inf)
+    m = np.max(lz, axis=1, keepdims=True)
+    m = np.where(np.isfinite(m), m, 0.0)
+    return np.exp(lz - m)
+
+
+def sub_batch(w, l):
+    return fd.Batch([w.ligands[l]])
+
+
+def split_ligands(n: int, n_train: int, seed: int = 170807045):
+    perm = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 11]))).permutation(n)
+    return np.sort(perm[:n_train]), np.sort(perm[n_train:])
+
+
+def rows_of(cfg_off, ligs):
+    return np.concatenate([np.arange(cfg_off[l], cfg_off[l + 1]) for l in ligs]).astype(np.int32)
+
+
+__all__ = ["coarse_desc", "make_context", "inputs", "targets", "train", "predict", "is_estimate", "kstar_plain",
+           "kstar_is", "ligand_weights", "sub_batch", "split_ligands", "rows_of", "BUDGETS", "PLAIN_K",
+           "N_IN_FULL", "init_params"]

@@ -1,0 +1,135 @@
+"""Learned-proposal importance sampling on the GPU, through the C-ABI:
+scan descriptors against the oracle's definition, the stratified plan's
+weighted scan and reduce against the oracle's weighted Eq. 2 on oracle
+partials, the reductions to the plain scan, the exhaustive fallback and the
+training data path."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import estimators as est
+from workload import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def _rows(P):
+    """Library partials [S][C] -> oracle rows [S][C][6]."""
+    return np.stack([P["m"], P["s"], P["n_valid"], P["n_finite"], P["psi_min"], P["argmin"]], axis=-1).astype(np.float64)
+
+
+def _ctx(w):
+    from paper_1708_07045_amd import proposal as prop
+    return prop.make_context(w)
+
+
+def test_scan_features_match_oracle():
+    import torch
+    import paper_1708_07045_amd as fd
+    print("scan features: c3 4 ligands x 3 snapshots", flush=True)
+    w = synth.config3(n_ligands=4, n_snap=3, cfg_scale=0.03)
+    ctx = _ctx(w)
+    b = fd.Batch(w.ligands)
+    part = ctx.scan(b, w.T)
+    X = torch.full((b.n_cfg, 7), 9.0, dtype=torch.float32, device="cuda")
+    ctx.scan_features(b, part, X, 2)
+    X = X.cpu().numpy()
+    ref = est.scan_features(_rows(ctx.partials_numpy(part, 3, b.n_cfg)), w.receptor.weights, b.cfg_off)
+    np.testing.assert_allclose(X[:, 2:5], ref, rtol=0, atol=2e-6)
+    assert np.all(X[:, :2] == 9.0) and np.all(X[:, 5:] == 9.0)   # other columns untouched
+
+
+def test_is_scan_matches_oracle_weighted_bpmf():
+    import paper_1708_07045_amd as fd
+    print("IS scan vs oracle: c2 subset 120 cfgs", flush=True)
+    w = synth.subset(synth.config2(), 120, stride=61)
+    ctx = _ctx(w)
+    b = fd.Batch(w.ligands)
+    go, oo = oracle.receptor_grids(w)
+    parts, _ = oracle.scan(w, go, oo)
+    lz = est.log_z(parts)
+    y = (np.where(np.isfinite(lz), lz, -30.0) / 5.0 + np.random.default_rng(1).normal(0, 0.3, b.n_cfg))
+    y = y.astype(np.float32)
+    u = synth.uniforms(41, 64)
+    sel, wt, n = ctx.is_plan(b, y, 0.05, 0.1, 0.1, 0.2, u)
+    sel_o, wt_o = est.stratified_plan(y.astype(np.float64), b.cfg_off, 0.05, 0.1, 0.1, 0.2, u)
+    np.testing.assert_array_equal(sel, sel_o)
+    bs = b.with_select(sel)
+    part = ctx.scan(bs, w.T)
+    B, res = ctx.reduce(bs, part, w.T, cfg_weight=wt)
+    n_total = parts[:, 2].sum()
+    Bo = est.bpmf_weighted(lz, n_total, wt_o, w.T)
+    assert abs(B[0, 0] - Bo) < 0.01, (B[0, 0], Bo)
+    assert n == np.count_nonzero(sel) < b.n_cfg
+
+
+def test_top_fraction_one_equals_plain_scan():
+    import paper_1708_07045_amd as fd
+    print("IS top_frac=1 equals plain: c3 3 ligands x 2 snapshots", flush=True)
+    w = synth.config3(n_ligands=3, n_snap=2, cfg_scale=0.03)
+    ctx = _ctx(w)
+    b = fd.Batch(w.ligands)
+    B0, r0 = ctx.reduce(b, ctx.scan(b, w.T), w.T)
+    y = np.random.default_rng(2).normal(size=b.n_cfg).astype(np.float32)
+    sel, wt, n = ctx.is_plan(b, y, 1.0, 0.2, 0.1, 1.0, synth.uniforms(3, 10))
+    assert n == b.n_cfg and np.all(wt == 1.0)
+    bs = b.with_select(sel)
+    B1, r1 = ctx.reduce(bs, ctx.scan(bs, w.T), w.T, cfg_weight=wt)
+    np.testing.assert_array_equal(B0, B1)
+    np.testing.assert_array_equal(r0["dG"], r1["dG"])
+
+
+def test_is_estimate_fallback_is_the_exhaustive_scan():
+    import paper_1708_07045_amd as fd
+    from paper_1708_07045_amd import proposal as prop
+    print("IS fallback: c3 3 ligands x 2 snapshots", flush=True)
+    w = synth.config3(n_ligands=3, n_snap=2, cfg_scale=0.05)
+    ctx = _ctx(w)
+    b = fd.Batch(w.ligands)
+    B0, r0 = ctx.reduce(b, ctx.scan(b, w.T), w.T)
+    y = np.zeros(b.n_cfg, np.float32)
+    u = synth.uniforms(4, b.n_cfg)
+    out = prop.is_estimate(ctx, b, y, 0.0, 0.1, 0.1, 1.0, u, w.T, max_share=-1.0)
+    assert out["fallback"].all()
+    np.testing.assert_array_equal(out["B"], B0)
+    np.testing.assert_array_equal(out["res"]["dG"], r0["dG"])
+    # no fallback with a permissive threshold: estimates stay finite
+    out = prop.is_estimate(ctx, b, y, 0.02, 0.1, 0.1, 1.0, u, w.T, max_share=1.1)
+    assert not out["fallback"].any()
+    assert np.all(np.isfinite(out["B"]))
+
+
+def test_training_on_scan_targets():
+    """Targets from an exhaustive scan, inputs from a coarse-spacing scan;
+    the network's loss on the training rows falls."""
+    import torch
+    import paper_1708_07045_amd as fd
+    from paper_1708_07045_amd import proposal as prop
+    print("proposal training: c3 6 ligands x 2 snapshots (fine + coarse contexts)", flush=True)
+    w = synth.config3(n_ligands=6, n_snap=2, cfg_scale=0.1)
+    ctx_f = _ctx(w)
+    ctx_c = prop.make_context(w, prop.coarse_desc(w))
+    b = fd.Batch(w.ligands)
+    part_f = ctx_f.scan(b, w.T)
+    part_c = ctx_c.scan(b, w.T)
+    X = prop.inputs(ctx_f, ctx_c, b, part_c)
+    t, wt = prop.targets(ctx_f, b, part_f)
+    assert X.shape == (b.n_cfg, prop.N_IN_FULL)
+    tn = t.cpu().numpy()
+    assert np.all(tn <= 0.0) and np.all(tn >= -5.0)
+    for l in range(b.n_lig):
+        assert tn[b.cfg_off[l]:b.cfg_off[l + 1]].max() == 0.0
+    net = fd.Network(prop.N_IN_FULL, 256, 4096)
+    assert b.n_cfg <= 4096
+    net.set_params(prop.init_params(prop.N_IN_FULL, 256))
+    rows = np.arange(b.n_cfg, dtype=np.int32)
+    idx = torch.as_tensor(rows, device="cuda")
+    L0, _ = net.grad(X, t, wt, idx)
+    prop.train(net, X, t, wt, rows, epochs=8, batch=256)
+    L1, _ = net.grad(X, t, wt, idx)
+    assert math.isfinite(L1) and L1 < 0.5 * L0, (L0, L1)
+    # the coarse descriptor correlates with the fine target
+    c = np.corrcoef(X[:, fd.N_FEATURES].cpu().numpy(), tn)[0, 1]
+    assert c > 0.5, c

@@ -1,6 +1,9 @@
 """Parity of the HIP path (through the C-ABI) with the FP64 oracle.
 
-Tolerances (written here, derived in the design doc):
+Tolerances (the FP32 bound: a radix-2 FFT of length N adds about
+u sqrt(log2 N) relative error per transform, u = 2^-24, so three 128-point
+passes each way stay near 1e-6 normwise, with a margin of 10 for the
+spectral product and the sum over channels):
   FP64 path: raw energies normwise <= 1e-10, B and dG <= 1e-8 kcal/mol.
   FP32 path: raw energies ||dPsi||_2 / ||Psi||_2 <= 1e-5 and
              max|dPsi| <= 1e-5 * max|Psi| over the box-valid translations;

@@ -14,12 +14,21 @@ conformers randomly rotated about their centroid, receptor snapshots with
 normalised weights (Eq. 13).
 
 Recipe (all parameters per atom, receptor and ligand alike):
-    q ~ N(0, 0.4) e,  sigma ~ U(3, 4) A,  eps ~ U(0.05, 0.2) kcal/mol,
+    tiny case (config 1):  q ~ N(0, 0.4) e,  eps ~ U(0.05, 0.2) kcal/mol;
+    cavity cases (configs 2-5, an apolar T4L-L99A-like pocket and apolar
+    ligands):              q ~ N(0, 0.1) e,  eps ~ U(0.025, 0.1) kcal/mol;
+    sigma ~ U(3, 4) A everywhere;
 then charges are made locally neutral: receptor atoms are grouped with
 their nearest of n/4 random group centres and each group's mean charge is
 subtracted; a ligand's mean charge is subtracted.  (Independent charges
 give vacuum potentials of ~10^3 kcal/mol/e inside the cavity, far from
-any real receptor.)
+any real receptor.)  The cavity cases' scale was set against the spread the
+paper reports for BPMFs over ligand configurations (results section,
+convergence figure: bootstrap standard deviations of 0.04-0.3 kcal/mol at
+about 1000 configurations): with the config-1 parameters the cavity cases
+have a single configuration carrying > 99.9 % of the Boltzmann weight and
+bootstrap deviations of several kcal/mol, far outside that range; with the
+cavity parameters the median over the 141 ligands is ~0.25 kcal/mol.
 Ligand geometry: compact self-avoiding random tree (each new atom bonds,
 1.5 A away, to a random earlier atom with fewer than three bonds, chosen
 with weight exp(-d/1.5 A) by distance d from the centroid; non-bonded
@@ -102,10 +111,16 @@ class Workload:
         return int(sum(l.n_cfg for l in self.ligands))
 
 
-def atom_params(rng: np.random.Generator, n: int):
-    q = rng.normal(0.0, 0.4, n)
+# (charge sd in e, eps range in kcal/mol) of the two parameter sets
+TINY_PARAMS = (0.4, (0.05, 0.2))
+CAVITY_PARAMS = (0.1, (0.025, 0.1))
+
+
+def atom_params(rng: np.random.Generator, n: int, params=TINY_PARAMS):
+    q_sd, (e_lo, e_hi) = params
+    q = rng.normal(0.0, q_sd, n)
     sigma = rng.uniform(3.0, 4.0, n)
-    eps = rng.uniform(0.05, 0.2, n)
+    eps = rng.uniform(e_lo, e_hi, n)
     return q, sigma, eps
 
 
@@ -235,8 +250,9 @@ def pivot_conformers(rng, base: np.ndarray, parent: np.ndarray, n_conf: int,
     return np.stack(out)
 
 
-def make_ligand(rng_lig, rng_rot, n_atoms: int, n_conf: int, n_rot_per_conf: int) -> Ligand:
-    q, sigma, eps = atom_params(rng_lig, n_atoms)
+def make_ligand(rng_lig, rng_rot, n_atoms: int, n_conf: int, n_rot_per_conf: int,
+                params=TINY_PARAMS) -> Ligand:
+    q, sigma, eps = atom_params(rng_lig, n_atoms, params)
     q = q - q.mean()
     base, parent = random_tree(rng_lig, n_atoms)
     confs = pivot_conformers(rng_lig, base, parent, n_conf)
@@ -279,9 +295,9 @@ def config1(seed: int = ROOT_SEED) -> Workload:
                     300.0, "f64", rec, [lig])
 
 
-def cavity_receptor(rng, n_atoms=2600, r_in=10.0, r_out=19.3):
+def cavity_receptor(rng, n_atoms=2600, r_in=10.0, r_out=19.3, params=CAVITY_PARAMS):
     xyz = _shell_atoms(rng, n_atoms, r_in, r_out)
-    q, s, e = atom_params(rng, n_atoms)
+    q, s, e = atom_params(rng, n_atoms, params)
     q = neutralize_groups(rng, xyz, q)
     return xyz, q, s, e
 
@@ -294,7 +310,7 @@ def config2(seed: int = ROOT_SEED, n_rot: int = 1000, n_conf: int = 8) -> Worklo
     n_rec, h = 96, 0.25
     xyz, q, s, e = cavity_receptor(rs[_STREAM_RECEPTOR])
     rec = Receptor(xyz[None], q, s, e, np.ones(1))
-    lig = make_ligand(rs[_STREAM_LIGANDS], rs[_STREAM_ROTATIONS], 25, n_conf, n_rot)
+    lig = make_ligand(rs[_STREAM_LIGANDS], rs[_STREAM_ROTATIONS], 25, n_conf, n_rot, CAVITY_PARAMS)
     return Workload("c2: 2600-atom cavity, 96^3 @ 0.25 A -> 128^3 FFT, occ, 25-atom ligand x 8 conf x 1000 rot, f32",
                     n_rec, 128, h, _grid_origin(np.zeros(3), n_rec, h), "occ", 10.0, 0.5,
                     300.0, "f32", rec, [lig])
@@ -317,7 +333,7 @@ def config3(seed: int = ROOT_SEED, n_ligands: int = 141, n_snap: int = 10,
         na = int(rm.integers(8, 41))
         ncfg = int(rm.integers(200, 2001))
         ncfg = max(8, int(round(ncfg * cfg_scale / 8.0)) * 8)
-        ligs.append(make_ligand(rl, rr, na, 8, ncfg // 8))
+        ligs.append(make_ligand(rl, rr, na, 8, ncfg // 8, CAVITY_PARAMS))
     return Workload("c3: 141 ligands (8-40 atoms, 200-2000 cfgs) x 10 snapshots, 128^3 FFT, occ, f32",
                     n_rec, 128, h, _grid_origin(np.zeros(3), n_rec, h), "occ", 10.0, 0.5,
                     300.0, "f32", rec, ligs)
