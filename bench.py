@@ -29,6 +29,56 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "zprod_t4l_8000cfg_hbm_traffic.md")
+KERNEL_SOURCES = ["scan_kernels.hip", "fft_device.hpp", "scan_types.hpp", "kernels.hpp"]
+
+
+def kernel_source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_1708_07045_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(tuning: dict):
+    """HBM bytes per configuration of the z-pencil kernel measured by the
+    FETCH_SIZE / WRITE_SIZE counter runs recorded in the profile summary, if
+    those runs used these kernel sources and this schedule (else None)."""
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    rec = {}
+    for line in open(TRAFFIC_PROFILE):
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            rec[k.strip()] = v.strip().strip("`")
+    try:
+        if rec["kernel_source_sha256"] != kernel_source_digest():
+            return None
+        if int(rec["configs_per_chunk"]) != tuning["configs_per_chunk"] or \
+                int(rec["energy_xy_direct"]) != tuning["energy_xy_direct"]:
+            return None
+        return float(rec["hbm_bytes_per_cfg"])
+    except (KeyError, ValueError):
+        return None
+
+
+def copy_calibration():
+    """One 1 GiB device-to-device copy (a plain copy kernel of known size),
+    for scaling the FETCH_SIZE / WRITE_SIZE counters."""
+    import torch
+    n = 1 << 28
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    log(f"copy calibration: {4 * n} bytes read and written by one copy kernel")
+    del a, b
+    torch.cuda.empty_cache()
+
+
 def cpu_baseline(w, budget_s: float):
     """The FP64 oracle on the host cores over a bounded, evenly strided sample
     of the same configurations; returns configs/s and the sample."""
@@ -193,7 +243,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--chunk", type=int, default=0, help="configurations per chunk (0 = library default)")
-    ap.add_argument("--energy-direct", type=int, default=-1, help="1/0: energy xy transforms fused (default: library)")
+    ap.add_argument("--energy-direct", type=int, default=-1, help="energy xy transforms: 0 FFT pass, 1 in the z kernel, 2 direct in the forward pass (default: autotuned)")
     ap.add_argument("--snap-pass", type=int, default=0, help="snapshots per z pass (0 = library default)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3"],
                     help="c2: the 8000-configuration T4L-sized scan (the metric's workload); "
@@ -203,6 +253,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-is", action="store_true", help="skip the configurations-needed measurement")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device copy before timing (counter calibration)")
     ap.add_argument("--is-only", action="store_true", help="only the configurations-needed measurement")
     ap.add_argument("--is-reps", type=int, default=200, help="replicates per budget (configurations needed)")
     ap.add_argument("--is-epochs", type=int, default=20)
@@ -234,7 +286,7 @@ def main():
     ctx = fd.FFTDG.from_workload(w)
     if args.chunk:
         ctx.set_tuning(configs_per_chunk=args.chunk)
-    if args.energy_direct in (0, 1):
+    if args.energy_direct in (0, 1, 2):
         ctx.set_tuning(energy_xy_direct=args.energy_direct)
     if args.snap_pass:
         ctx.set_tuning(snapshots_per_pass=args.snap_pass)
@@ -250,12 +302,14 @@ def main():
     out = ctx.alloc_partials(batch)
     torch.cuda.synchronize()
     autotuned = None
-    if not args.no_autotune and not (args.chunk or args.energy_direct in (0, 1) or args.snap_pass):
+    if not args.no_autotune and not (args.chunk or args.energy_direct in (0, 1, 2) or args.snap_pass):
         t0 = time.perf_counter()
         tun, ms = ctx.autotune(batch, w.T, max_cfgs=2048)
         autotuned = {"choice": tun, "ms_per_cfg_snapshot": ms, "seconds": time.perf_counter() - t0}
         log(f"autotuned schedule {tun} ({ms * 1e3:.2f} us per configuration and snapshot on the sample)")
 
+    if args.copy_calibration:
+        copy_calibration()
     result = {}
 
     def step():
@@ -294,8 +348,13 @@ def main():
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
     kd = kernels[dom]
     achieved = kd["alg_GBps"]
+    traffic = None
+    if dom == "zprod" and args.workload == "c2":
+        per_cfg = recorded_traffic(ctx.get_tuning())
+        if per_cfg is not None:
+            traffic = per_cfg * n_cfg * args.steps / prof["zprod"][1]   # bytes per launch
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "avg_launch_us": kd["avg_launch_us"], "alg_bytes_per_launch": kd["alg_bytes_per_launch"]}
     # whole path: algorithmic bytes of all scan kernels per configuration
     path_bytes = sum(prof[k][2] for k in ("lig_fwd_xy", "zprod", "inv_xy_lse", "merge")) / args.steps

@@ -226,12 +226,14 @@ int fftdg_profile_read(fftdg_ctx *ctx, int32_t kernel_id, double *ms_host, int64
  * the FP32 transforms):
  *   configs_per_chunk  configurations whose forward and inverse planes share
  *                      device workspace at one time (>= 1, default 256);
- *   energy_xy_direct   1: the x/y transforms of the three energy
- *                      channels are evaluated per atom inside the z-pencil
- *                      kernel (the xy FFT of the trilinearly spread plane
- *                      with its zero inputs pruned); 0: they go through the
- *                      same LDS-staged xy FFT pass as the occupancy channel
- *                      and through HBM (default);
+ *   energy_xy_direct   how the x/y transforms of the three energy channels
+ *                      are done (each is the xy DFT of the trilinearly
+ *                      spread plane): 0: the same LDS-staged xy FFT pass as
+ *                      the occupancy channel, through HBM (default);
+ *                      1: evaluated per atom inside the z-pencil kernel, no
+ *                      HBM planes; 2: evaluated per atom in the forward
+ *                      pass (one block writes a z-plane of all three
+ *                      channels), through HBM;
  *   snapshots_per_pass receptor snapshots handled by one z-pencil launch
  *                      (>= 1, default 1): with more than one, a
  *                      configuration's forward z spectra stay in registers
@@ -254,7 +256,7 @@ int fftdg_get_tuning(const fftdg_ctx *ctx, fftdg_tuning *out);
 int fftdg_set_tuning(fftdg_ctx *ctx, const fftdg_tuning *t);
 
 /* Autotuner: times the candidate schedules (configurations per chunk in
- * {64, 128, 256, 512}, energy_xy_direct in {0, 1}, snapshots_per_pass in
+ * {64, 128, 256, 512}, energy_xy_direct in {0, 1, 2}, snapshots_per_pass in
  * {1, n_snap} when there are several snapshots, use_graph in {0, 1}) with
  * HIP events on an evenly
  * strided sample of at most max_cfgs configurations of the batch (all

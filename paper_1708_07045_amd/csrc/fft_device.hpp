@@ -82,11 +82,13 @@ __device__ __forceinline__ void tw16(int k, T br, T bi, T &tr, T &ti) {
 }
 
 // In-register R-point DFT (R in {2,4,8,16}), natural order in and out.
-template <int R, bool INV, typename T>
+// ZHI: inputs R/2..R-1 are zero (not read); the first radix-2 stage, which
+// pairs input n with n + R/2, then reduces to copies.
+template <int R, bool INV, typename T, bool ZHI = false>
 __device__ __forceinline__ void dft_reg(T *re, T *im) {
     T xr[R], xi[R];
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
+    for (int i = 0; i < (ZHI ? R / 2 : R); ++i) {
         xr[bitrev(i, R)] = re[i];
         xi[bitrev(i, R)] = im[i];
     }
@@ -94,6 +96,11 @@ __device__ __forceinline__ void dft_reg(T *re, T *im) {
     for (int len = 2; len <= R; len <<= 1) {
 #pragma unroll
         for (int i = 0; i < R; i += len) {
+            if (ZHI && len == 2) {  // bitrev(n + R/2) = bitrev(n) + 1
+                xr[i + 1] = xr[i];
+                xi[i + 1] = xi[i];
+                continue;
+            }
 #pragma unroll
             for (int j = 0; j < len / 2; ++j) {
                 T tr, ti;
@@ -141,12 +148,13 @@ __device__ __forceinline__ void wave_sync() {
 // lanes of a unit must belong to one wavefront: the exchange is ordered with
 // wave_sync(), not with a workgroup barrier.  `live` = false makes the unit
 // skip its LDS traffic.
-template <typename T, int N, bool INV>
+// ZHI: the inputs x[z], z >= N/2 (slots n2 >= R2/2) are zero and not read.
+template <typename T, int N, bool INV, bool ZHI = false>
 __device__ __forceinline__ void fft_unit(T *re, T *im, int n1, typename Cx<T>::t *ex, int es,
                                          const typename Cx<T>::t *tw, bool live, int pad = 0) {
     using C2 = typename Cx<T>::t;
     constexpr int R1 = Shape<N>::R1, R2 = Shape<N>::R2, M = R2 / R1;
-    dft_reg<R2, INV>(re, im);
+    dft_reg<R2, INV, T, ZHI>(re, im);
 #pragma unroll
     for (int k2 = 1; k2 < R2; ++k2) cmul_tw(re[k2], im[k2], tw[n1 * k2], INV);
     wave_sync();  // the exchange area may still be read by a previous step

@@ -17,14 +17,17 @@ struct KernelSet {
     // -> rspec [n_ch][N][np]; rxy is scratch [n_ch][n_rec][np]
     hipError_t (*rec_spectra)(hipStream_t, const void *grids, const uint8_t *occ, int n_rec, int n_ch,
                               const void *tw, void *rxy, void *rspec);
-    // one block per forward plane; fwd_off[0..n_cfg] running plane counts
-    hipError_t (*fwd)(hipStream_t, const int32_t *fwd_off, int n_cfg, int n_items, const CfgDev *cfgs,
+    // one block per forward plane (edf: one per energy z-plane for all three
+    // channels, evaluated directly, plus one per occupancy plane);
+    // fwd_off[0..n_cfg] running item counts
+    hipError_t (*fwd)(hipStream_t, bool edf, const int32_t *fwd_off, int n_cfg, int n_items, const CfgDev *cfgs,
                       const int32_t *ulat, const void *gam, const double *thr, const void *tw, void *ws);
     // edirect: energy-channel xy transforms evaluated per atom inside the
     // kernel (else read from forward planes written by fwd)
     // n_snap snapshots per launch: spectra spec_stride and outputs inv_stride
     // complex elements apart
-    hipError_t (*zprod)(hipStream_t, bool occ, bool edirect, const CfgDev *cfgs, const int32_t *zcfg, int nz,
+    // zhalf: every configuration's energy planes lie in [0, n_fft/2)
+    hipError_t (*zprod)(hipStream_t, bool occ, bool edirect, bool zhalf, const CfgDev *cfgs, const int32_t *zcfg, int nz,
                         const void *ws, const void *rspec, const void *tw, void *wsi, const int32_t *ulat,
                         const void *gam, int n_snap, int64_t spec_stride, int64_t inv_stride);
     // e_count (nullable): incremented once per energy plane transformed

@@ -45,7 +45,7 @@ struct fftdg_ctx {
     hipEvent_t staging_ev = nullptr;
     bool staging_used = false;
     int chunk_cfgs = 256;
-    bool edirect = false;
+    int edirect = 0;  // energy xy transforms: 0 FFT pass, 1 inside the z kernel, 2 direct in the forward pass
     int snap_group = 1;  // snapshots per z launch (limited by workspace)
     bool use_graph = false;
     hipStream_t cap_stream = nullptr;   // capture only; graphs run on `stream`
@@ -218,6 +218,7 @@ struct Plan {
         size_t z0, nz;            // scanned configurations (local indices)
         int64_t ws_fwd, ws_inv;   // complex elements used
         int pp;                   // plane partial slots used
+        bool zhalf;               // every scanned configuration's energy planes lie in [0, n_fft/2)
     };
     std::vector<Chunk> chunks;
     std::vector<int32_t> fwd_off, inv_off;
@@ -407,10 +408,12 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
         int nscan = 0;
         int64_t wf = 0, wi = 0;
         int pp = 0;
+        bool zhalf = true;
         while (c < ncfg) {
             CfgDev &d = P.cfg[c];
             if (d.scanned) {
-                const int e_planes = ctx->edirect ? 0 : 3 * d.Le;
+                const int e_planes = ctx->edirect == 1 ? 0 : 3 * d.Le;
+                const int e_items = ctx->edirect == 2 ? d.Le : e_planes;
                 d.occ_slot0 = e_planes;
                 const int64_t f = (int64_t)(e_planes + (occ ? d.Lo : 0)) * NP;
                 const int64_t iv = (int64_t)nout * d.V[2] * NP;
@@ -421,9 +424,10 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
                 const int local = c - ch.c0;
                 P.fwd_off.push_back(nf);
                 P.inv_off.push_back(ni);
-                nf += e_planes + (occ ? d.Lo : 0);
+                nf += e_items + (occ ? d.Lo : 0);
                 ni += d.V[2];
                 P.zcfg.push_back(local);
+                zhalf = zhalf && d.ze0 >= 0 && d.ze0 + d.Le <= ctx->g.n_fft / 2;
                 wf += f;
                 wi += iv;
                 pp += d.V[2];
@@ -446,6 +450,7 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
         ch.ws_fwd = wf;
         ch.ws_inv = wi;
         ch.pp = pp;
+        ch.zhalf = zhalf;
         P.max_fwd = std::max(P.max_fwd, wf);
         P.max_inv = std::max(P.max_inv, wi);
         P.max_pp = std::max(P.max_pp, pp);
@@ -541,14 +546,14 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
         const double b_fwd = (double)ch.ws_fwd * cb;
         const double b_inv = (double)ch.ws_inv * cb;
         HIPCHK(ctx, timed(ctx, FFTDG_K_FWD, b_fwd, [&] {
-                   return ks->fwd(st, dfwd + ch.off0, ch.c1 - ch.c0, (int)ch.nfwd, ccfg, du, dgam, dthr,
+                   return ks->fwd(st, ctx->edirect == 2, dfwd + ch.off0, ch.c1 - ch.c0, (int)ch.nfwd, ccfg, du, dgam, dthr,
                                   ctx->tw.p, ctx->ws_fwd.p);
                }));
         for (int s0 = s_begin; s0 < s_end; s0 += grp) {
           const int ng = std::min(grp, s_end - s0);
           const char *rs = (const char *)ctx->rspec.p + spec_per_snap * s0;
           HIPCHK(ctx, timed(ctx, FFTDG_K_ZPROD, b_fwd + ng * (b_inv + (double)spec_per_snap), [&] {
-                     return ks->zprod(st, occ, ctx->edirect, ccfg, dz + ch.z0, (int)ch.nz, ctx->ws_fwd.p, rs,
+                     return ks->zprod(st, occ, ctx->edirect == 1, ch.zhalf, ccfg, dz + ch.z0, (int)ch.nz, ctx->ws_fwd.p, rs,
                                       ctx->tw.p, ctx->ws_inv.p, du, dgam, ng, (int64_t)(spec_per_snap / cb),
                                       (int64_t)ch.ws_inv);
                  }));
@@ -584,7 +589,7 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     sig.push_back(bbits);
     for (const Plan::Chunk &ch : P.chunks)
         for (int64_t v : {(int64_t)ch.c0, (int64_t)ch.c1, (int64_t)ch.off0, (int64_t)ch.nfwd, (int64_t)ch.ninv,
-                          (int64_t)ch.z0, (int64_t)ch.nz, ch.ws_fwd, ch.ws_inv, (int64_t)ch.pp})
+                          (int64_t)ch.z0, (int64_t)ch.nz, ch.ws_fwd, ch.ws_inv, (int64_t)ch.pp, (int64_t)ch.zhalf})
             sig.push_back(v);
     if (!(ctx->graph_exec && sig == ctx->graph_sig)) {
         if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -940,7 +945,7 @@ int fftdg_profile_read(fftdg_ctx *ctx, int32_t k, double *ms, int64_t *n, double
 int fftdg_get_tuning(const fftdg_ctx *ctx, fftdg_tuning *t) {
     if (!ctx || !t) return FFTDG_E_INVALID;
     t->configs_per_chunk = ctx->chunk_cfgs;
-    t->energy_xy_direct = ctx->edirect ? 1 : 0;
+    t->energy_xy_direct = ctx->edirect;
     t->snapshots_per_pass = ctx->snap_group;
     t->use_graph = ctx->use_graph ? 1 : 0;
     return FFTDG_OK;
@@ -950,11 +955,11 @@ int fftdg_set_tuning(fftdg_ctx *ctx, const fftdg_tuning *t) {
     if (!ctx) return FFTDG_E_INVALID;
     if (!t) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: NULL");
     if (t->configs_per_chunk < 1) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: configs_per_chunk must be >= 1");
-    if (t->energy_xy_direct != 0 && t->energy_xy_direct != 1)
-        return set_err(ctx, FFTDG_E_INVALID, "set_tuning: energy_xy_direct must be 0 or 1");
+    if (t->energy_xy_direct < 0 || t->energy_xy_direct > 2)
+        return set_err(ctx, FFTDG_E_INVALID, "set_tuning: energy_xy_direct must be 0, 1 or 2");
     if (t->snapshots_per_pass < 1) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: snapshots_per_pass must be >= 1");
     ctx->chunk_cfgs = t->configs_per_chunk;
-    ctx->edirect = t->energy_xy_direct != 0;
+    ctx->edirect = t->energy_xy_direct;
     if (t->use_graph != 0 && t->use_graph != 1) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: use_graph must be 0 or 1");
     ctx->snap_group = t->snapshots_per_pass;
     ctx->use_graph = t->use_graph != 0;
@@ -1030,14 +1035,14 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
     fftdg_batch bs = *b;
     bs.cfg_select = sel.data();
     if ((rc = reserve(ctx, ctx->tune_out, sizeof(fftdg_partial) * (size_t)ncfg * ctx->n_snap))) return rc;
-    const fftdg_tuning keep = {ctx->chunk_cfgs, ctx->edirect ? 1 : 0, ctx->snap_group, ctx->use_graph ? 1 : 0};
+    const fftdg_tuning keep = {ctx->chunk_cfgs, ctx->edirect, ctx->snap_group, ctx->use_graph ? 1 : 0};
     const bool prof = ctx->prof;
     ctx->prof = false;
     std::vector<fftdg_tuning> cand;
     std::vector<int> passes = {1};
     if (ctx->n_snap > 1) passes.push_back(ctx->n_snap);
     for (int chunk : {64, 128, 256, 512})
-        for (int ed : {0, 1})
+        for (int ed : {0, 1, 2})
             for (int sp : passes)
                 for (int gr : {0, 1}) cand.push_back(fftdg_tuning{chunk, ed, sp, gr});
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1048,7 +1053,7 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
     int err = FFTDG_OK;
     for (const fftdg_tuning &t : cand) {
         ctx->chunk_cfgs = t.configs_per_chunk;
-        ctx->edirect = t.energy_xy_direct != 0;
+        ctx->edirect = t.energy_xy_direct;
         ctx->snap_group = t.snapshots_per_pass;
         ctx->use_graph = t.use_graph != 0;
         float tmin = INFINITY;
@@ -1074,14 +1079,14 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
     ctx->prof = prof;
     if (err) {
         ctx->chunk_cfgs = keep.configs_per_chunk;
-        ctx->edirect = keep.energy_xy_direct != 0;
+        ctx->edirect = keep.energy_xy_direct;
         ctx->snap_group = keep.snapshots_per_pass;
         ctx->use_graph = keep.use_graph != 0;
         if (err == FFTDG_E_DEVICE && ctx->err.empty()) ctx->err = "autotune: HIP event error";
         return err;
     }
     ctx->chunk_cfgs = bt.configs_per_chunk;
-    ctx->edirect = bt.energy_xy_direct != 0;
+    ctx->edirect = bt.energy_xy_direct;
     ctx->snap_group = bt.snapshots_per_pass;
     ctx->use_graph = bt.use_graph != 0;
     if (out) *out = bt;

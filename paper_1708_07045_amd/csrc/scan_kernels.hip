@@ -248,11 +248,11 @@ struct LigOccFill {
                 const long long xhi = floordiv(e.Ux + s, 65536LL);
                 const int span = (int)(xhi - xlo);
                 if (span < 0) continue;
-                const int xl = pmod((int)xlo, N);
+                const int xl = (int)xlo & (N - 1);
 #pragma unroll
                 for (int i = 0; i < R2; ++i) {
                     const int x = n1 + R1 * i;
-                    const int d = pmod(x - xl, N);
+                    const int d = (x - xl) & (N - 1);
                     if (d <= span) {
                         if (row == 0) re[i] = (T)1; else im[i] = (T)1;
                     }
@@ -351,7 +351,7 @@ __device__ void xy_forward(const Fill &fill, int y0, int Ly, typename Cx<T>::t *
         const bool live = c < N / 2;
 #pragma unroll
         for (int i = 0; i < R2; ++i) {
-            const int rr = pmod(n1 + R1 * i - y0, N);
+            const int rr = (n1 + R1 * i - y0) & (N - 1);
             re[i] = im[i] = (T)0;
             if (live && rr < Ly) {
                 if (c == 0) {
@@ -403,7 +403,108 @@ __device__ void xy_forward(const Fill &fill, int y0, int Ly, typename Cx<T>::t *
 }
 
 // ------------------------------------------------------------------ kernels
+// Energy planes by direct evaluation (forward mode 2): one block per
+// (configuration, energy plane z) writes the half spectra of all three
+// channels.  A trilinearly spread atom has 2 x 2 corners in the plane, so
+// its 2-D DFT factorises:
+//   F(ky, kx) = w^(kx ax) ((1-fx) + fx w^kx) * w^(ky ay) ((1-fy) + fy w^ky)
+// (w = exp(-2 pi i / N)), scaled by gamma_ch times its z weight; the plane's
+// spectrum is the sum over the few atoms that touch it.  Per-atom factors
+// are tabulated in LDS (DE_A atoms per pass); with more atoms the passes
+// accumulate in the output.  This is the xy FFT of the spread plane with
+// its zero inputs pruned, exact in exact arithmetic.
+constexpr int DE_A = 32;
+
 template <typename T, int N>
+__device__ void energy_plane_direct(const CfgDev &c, int p, const int32_t *__restrict__ ulat,
+                                    const T *__restrict__ gam, const typename Cx<T>::t *tw,
+                                    typename Cx<T>::t *tab, typename Cx<T>::t *__restrict__ ws) {
+    using C2 = typename Cx<T>::t;
+    constexpr int H = N / 2 + 1, NP = N * H;
+    __shared__ T wgt[DE_A][3];
+    __shared__ int2 axy[DE_A];
+    __shared__ T fxy[DE_A][2];
+    __shared__ int nsel;
+    __shared__ int list[MAXA];
+    const int zt = c.ze0 + p;
+    // atoms touching plane zt, in atom order
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        int base = 0;
+        for (int a0 = 0; a0 < c.n_atoms; a0 += 64) {
+            const int a = a0 + lane;
+            bool take = false;
+            if (a < c.n_atoms) {
+                const int az = ulat[3 * (c.u_base + a) + 2] >> 16;
+                take = (az == zt) || (az + 1 == zt);
+            }
+            const unsigned long long m = __ballot(take);
+            if (take) list[base + __popcll(m & ((1ULL << lane) - 1ULL))] = a;
+            base += __popcll(m);
+        }
+        if (lane == 0) nsel = base;
+    }
+    __syncthreads();
+    const int na = nsel;
+    C2 *X = tab, *Y = tab + DE_A * H;
+    C2 *out0 = ws + c.off_fwd + (int64_t)p * NP;
+    const int64_t chs = (int64_t)c.Le * NP;  // channel stride of the forward planes
+    for (int a0 = 0; a0 < na || a0 == 0; a0 += DE_A) {
+        const int nb = min(DE_A, na - a0);
+        if (threadIdx.x < nb) {
+            const int a = list[a0 + threadIdx.x];
+            const int32_t *U = ulat + 3 * (c.u_base + a);
+            const int az = U[2] >> 16;
+            const T fz = (T)(U[2] & 0xffff) * (T)(1.0 / 65536.0);
+            const T wz = (az == zt) ? (T)1 - fz : fz;
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) wgt[threadIdx.x][ch] = gam[3 * (c.atom_base + a) + ch] * wz;
+            axy[threadIdx.x] = int2{U[0] >> 16, U[1] >> 16};
+            fxy[threadIdx.x][0] = (T)(U[0] & 0xffff) * (T)(1.0 / 65536.0);
+            fxy[threadIdx.x][1] = (T)(U[1] & 0xffff) * (T)(1.0 / 65536.0);
+        }
+        __syncthreads();
+        for (int e = threadIdx.x; e < nb * (H + N); e += NT) {
+            const int a = e / (H + N), k = e - a * (H + N);
+            const bool isx = k < H;
+            const int kk = isx ? k : k - H;
+            const int ax = isx ? axy[a].x : axy[a].y;
+            const T f = isx ? fxy[a][0] : fxy[a][1];
+            const C2 e1 = tw[(kk * ax) & (N - 1)], wk = tw[kk & (N - 1)];
+            const T sr = (T)1 - f + f * wk.x, si = f * wk.y;
+            const C2 v = C2{e1.x * sr - e1.y * si, e1.x * si + e1.y * sr};
+            if (isx) X[a * H + kk] = v; else Y[a * N + kk] = v;
+        }
+        __syncthreads();
+        for (int o = threadIdx.x; o < NP; o += NT) {
+            const int ky = o / H, kx = o - ky * H;
+            T ar[3] = {(T)0, (T)0, (T)0}, ai[3] = {(T)0, (T)0, (T)0};
+            for (int a = 0; a < nb; ++a) {
+                const C2 x = X[a * H + kx], y = Y[a * N + ky];
+                const T vr = x.x * y.x - x.y * y.y, vi = x.x * y.y + x.y * y.x;
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) {
+                    ar[ch] += wgt[a][ch] * vr;
+                    ai[ch] += wgt[a][ch] * vi;
+                }
+            }
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                C2 *dst = out0 + ch * chs + o;
+                if (a0 > 0) {
+                    const C2 prev = *dst;
+                    ar[ch] += prev.x;
+                    ai[ch] += prev.y;
+                }
+                *dst = C2{ar[ch], ai[ch]};
+            }
+        }
+        __syncthreads();
+        if (na == 0) break;
+    }
+}
+
+template <typename T, int N, bool EDF>
 __global__ __launch_bounds__(NT) void k_lig_fwd_xy(const int32_t *__restrict__ fwd_off, int n_cfg,
                                                     const CfgDev *__restrict__ cfgs,
                                                     const int32_t *__restrict__ ulat,
@@ -422,12 +523,22 @@ __global__ __launch_bounds__(NT) void k_lig_fwd_xy(const int32_t *__restrict__ f
     __shared__ int nl;
     const int ic = find_cfg(fwd_off, n_cfg, (int)blockIdx.x);
     const CfgDev c = cfgs[ic];
-    const int slot = (int)blockIdx.x - fwd_off[ic];
+    const int item = (int)blockIdx.x - fwd_off[ic];
+    load_tw<T, N>(tw, twg);
+    if constexpr (EDF) {
+        if (item < c.Le) {  // block-uniform: the whole block takes this path
+            __syncthreads();
+            energy_plane_direct<T, N>(c, item, ulat, gam, tw, Pl, ws);
+            return;
+        }
+    }
+    // forward-plane slot in the workspace (energy planes ch * Le + p, then
+    // the occupancy planes from occ_slot0)
+    const int slot = EDF ? c.occ_slot0 + (item - c.Le) : item;
     const bool occ = slot >= c.occ_slot0;
     struct {
         int ch, p;
     } it = {occ ? 3 : slot / c.Le, occ ? slot - c.occ_slot0 : slot % c.Le};
-    load_tw<T, N>(tw, twg);
     const int zt = (occ ? c.zo0 : c.ze0) + it.p;
     const int y0 = occ ? c.yo0 : c.ye0;
     const int Ly = occ ? c.Lyo : c.Lye;
@@ -572,7 +683,7 @@ struct DAtom {
 // spectra stay in registers while the product and inverse run for each of
 // n_snap receptor snapshots (spectra spec_stride apart, outputs inv_stride
 // apart).
-template <typename T, int N, bool OCC, bool EDIRECT, bool MULTI>
+template <typename T, int N, bool OCC, bool EDIRECT, bool MULTI, bool ZH>
 __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, const int32_t *__restrict__ zcfg,
                                                int nz, int n_tiles, const typename Cx<T>::t *__restrict__ ws,
                                                const typename Cx<T>::t *__restrict__ rspec,
@@ -619,6 +730,10 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
     const int pen = tile * P + p;
     const bool ok = pen < NP;
     const int nchunk = EDIRECT ? (c.n_atoms + AC - 1) / AC : 0;
+    // ZH (launch-wide): every configuration's energy planes lie in [0, N/2),
+    // so the upper half of the z inputs is zero: not loaded, first FFT stage
+    // pruned
+    constexpr bool half = ZH && !EDIRECT;
     // element e of this lane's pencil in the wave region
     auto eaddr = [&](int e) { return e * PW + (e / R2) * PAD; };
     if constexpr (!MULTI) {
@@ -690,14 +805,14 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
             const auto rs = make_rsrc(ws + c.off_fwd + (int64_t)ch * c.Le * NP, c.Le * NP * (int)sizeof(C2));
             const int po = ok ? pen : NP * N;
 #pragma unroll
-            for (int i = 0; i < R2; ++i) {
-                const int s = pmod(n1 + R1 * i - c.ze0, N);
+            for (int i = 0; i < (half ? R2 / 2 : R2); ++i) {
+                const int s = (n1 + R1 * i - c.ze0) & (N - 1);
                 const C2 v = buf_load(rs, (s * NP + po) * (int)sizeof(C2), (C2 *)nullptr);
                 re[i] = v.x;
                 im[i] = v.y;
             }
         }
-        fft_unit<T, N, false>(re, im, n1, ex, PW, tw, true, PAD);
+        fft_unit<T, N, false, half>(re, im, n1, ex, PW, tw, true, PAD);
         const auto rr = make_rsrc(rspec + (int64_t)ch * N * NP, N * NP * (int)sizeof(C2));
 #pragma unroll
         for (int i = 0; i < M; ++i)
@@ -725,7 +840,7 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
         const auto rs = make_rsrc(ws + c.off_fwd + (int64_t)c.occ_slot0 * NP, c.Lo * NP * (int)sizeof(C2));
 #pragma unroll
         for (int i = 0; i < R2; ++i) {
-            const int s = pmod(n1 + R1 * i - c.zo0, N);
+            const int s = ((n1 + R1 * i - c.zo0) & (N - 1));
             const C2 v = buf_load(rs, (s * NP + po) * (int)sizeof(C2), (C2 *)nullptr);
             re[i] = v.x;
             im[i] = v.y;
@@ -817,14 +932,14 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
             const auto rs = make_rsrc(ws + c.off_fwd + (int64_t)ch * c.Le * NP, c.Le * NP * (int)sizeof(C2));
             const int po = ok ? pen : NP * N;
 #pragma unroll
-            for (int i = 0; i < R2; ++i) {
-                const int s = pmod(n1 + R1 * i - c.ze0, N);
+            for (int i = 0; i < (half ? R2 / 2 : R2); ++i) {
+                const int s = (n1 + R1 * i - c.ze0) & (N - 1);
                 const C2 v = buf_load(rs, (s * NP + po) * (int)sizeof(C2), (C2 *)nullptr);
                 re[i] = v.x;
                 im[i] = v.y;
             }
         }
-        fft_unit<T, N, false>(re, im, n1, ex, PW, tw, true, PAD);
+        fft_unit<T, N, false, half>(re, im, n1, ex, PW, tw, true, PAD);
     }
     const int Vz = c.V[2];
     const int po = ok ? pen : NP * N;  // out of every descriptor's range
@@ -860,7 +975,7 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
         const auto rs = make_rsrc(ws + c.off_fwd + (int64_t)c.occ_slot0 * NP, c.Lo * NP * (int)sizeof(C2));
 #pragma unroll
         for (int i = 0; i < R2; ++i) {
-            const int s = pmod(n1 + R1 * i - c.zo0, N);
+            const int s = ((n1 + R1 * i - c.zo0) & (N - 1));
             const C2 v = buf_load(rs, (s * NP + po) * (int)sizeof(C2), (C2 *)nullptr);
             orr[i] = v.x;
             oi[i] = v.y;
@@ -1379,14 +1494,19 @@ struct Launch {
                            (const C2 *)tw, (C2 *)rspec);
         return hipGetLastError();
     }
-    static hipError_t fwd(hipStream_t st, const int32_t *fwd_off, int n_cfg, int n_items, const CfgDev *cfgs,
-                          const int32_t *ulat, const void *gam, const double *thr, const void *tw, void *ws) {
+    static hipError_t fwd(hipStream_t st, bool edf, const int32_t *fwd_off, int n_cfg, int n_items,
+                          const CfgDev *cfgs, const int32_t *ulat, const void *gam, const double *thr,
+                          const void *tw, void *ws) {
         if (n_items <= 0) return hipSuccess;
-        hipLaunchKernelGGL((k_lig_fwd_xy<T, N>), dim3(n_items), dim3(NT), 0, st, fwd_off, n_cfg, cfgs, ulat,
-                           (const T *)gam, thr, (const C2 *)tw, (C2 *)ws);
+        if (edf)
+            hipLaunchKernelGGL((k_lig_fwd_xy<T, N, true>), dim3(n_items), dim3(NT), 0, st, fwd_off, n_cfg, cfgs,
+                               ulat, (const T *)gam, thr, (const C2 *)tw, (C2 *)ws);
+        else
+            hipLaunchKernelGGL((k_lig_fwd_xy<T, N, false>), dim3(n_items), dim3(NT), 0, st, fwd_off, n_cfg, cfgs,
+                               ulat, (const T *)gam, thr, (const C2 *)tw, (C2 *)ws);
         return hipGetLastError();
     }
-    static hipError_t zprod(hipStream_t st, bool occ, bool edirect, const CfgDev *cfgs, const int32_t *zcfg,
+    static hipError_t zprod(hipStream_t st, bool occ, bool edirect, bool zhalf, const CfgDev *cfgs, const int32_t *zcfg,
                             int nz, const void *ws, const void *rspec, const void *tw, void *wsi,
                             const int32_t *ulat, const void *gam, int n_snap, int64_t spec_stride,
                             int64_t inv_stride) {
@@ -1394,19 +1514,21 @@ struct Launch {
         const int n_tiles = (G::NP + G::U - 1) / G::U;
         long long nb = (long long)n_tiles * nz;
         nb = (nb + 7) / 8 * 8;
-#define FFTDG_ZPROD(O, E)                                                                                 \
+#define FFTDG_ZPROD(O, E, Z)                                                                              \
     if (n_snap > 1)                                                                                       \
-        hipLaunchKernelGGL((k_zprod<T, N, O, E, true>), dim3((unsigned)nb), dim3(NT), 0, st, cfgs, zcfg, nz,  \
-                           n_tiles, (const C2 *)ws, (const C2 *)rspec, (const C2 *)tw, (C2 *)wsi, ulat,        \
+        hipLaunchKernelGGL((k_zprod<T, N, O, E, true, Z>), dim3((unsigned)nb), dim3(NT), 0, st, cfgs, zcfg,  \
+                           nz, n_tiles, (const C2 *)ws, (const C2 *)rspec, (const C2 *)tw, (C2 *)wsi, ulat,    \
                            (const T *)gam, n_snap, spec_stride, inv_stride);                                   \
     else                                                                                                  \
-    hipLaunchKernelGGL((k_zprod<T, N, O, E, false>), dim3((unsigned)nb), dim3(NT), 0, st, cfgs, zcfg, nz, n_tiles, \
-                       (const C2 *)ws, (const C2 *)rspec, (const C2 *)tw, (C2 *)wsi, ulat, (const T *)gam, n_snap, \
-                       spec_stride, inv_stride)
-        if (occ && edirect) FFTDG_ZPROD(true, true);
-        else if (occ) FFTDG_ZPROD(true, false);
-        else if (edirect) FFTDG_ZPROD(false, true);
-        else FFTDG_ZPROD(false, false);
+        hipLaunchKernelGGL((k_zprod<T, N, O, E, false, Z>), dim3((unsigned)nb), dim3(NT), 0, st, cfgs, zcfg, \
+                           nz, n_tiles, (const C2 *)ws, (const C2 *)rspec, (const C2 *)tw, (C2 *)wsi, ulat,    \
+                           (const T *)gam, n_snap, spec_stride, inv_stride)
+        if (occ && edirect) FFTDG_ZPROD(true, true, false);
+        else if (occ && zhalf) FFTDG_ZPROD(true, false, true);
+        else if (occ) FFTDG_ZPROD(true, false, false);
+        else if (edirect) FFTDG_ZPROD(false, true, false);
+        else if (zhalf) FFTDG_ZPROD(false, false, true);
+        else FFTDG_ZPROD(false, false, false);
 #undef FFTDG_ZPROD
         return hipGetLastError();
     }

@@ -123,7 +123,7 @@ def test_energy_c1_fp64_cap():
     _energy_parity(w, [0, 1, 17, 42, 99], "f64", TOL_F64)
 
 
-@pytest.mark.parametrize("edirect", [1, 0])
+@pytest.mark.parametrize("edirect", [1, 0, 2])
 def test_energy_c2_fp32_occ(edirect):
     w = synth.config2(n_rot=12, n_conf=8)
     _energy_parity(w, [0, 13, 27, 40, 66, 95], "f32", TOL_F32, energy_xy_direct=edirect)
@@ -135,7 +135,7 @@ def test_energy_c2_fp32_cap_and_fp64_n64():
     w.n_rec, w.n_fft = 60, 64
     w.origin = -0.5 * (60 - 1) * w.h * np.ones(3)
     for prec, tol in [("f32", TOL_F32), ("f64", TOL_F64)]:
-        for ed in (1, 0):
+        for ed in (1, 0, 2):
             _energy_parity(w, [0, 3, 5], prec, tol, energy_xy_direct=ed)
     w.clash_mode = "cap"
     _energy_parity(w, [1, 6], "f32", 2e-5)
@@ -198,24 +198,25 @@ def _scan_parity(w, precision, tolB, **tuning):
     return P, B, res
 
 
-@pytest.mark.parametrize("edirect", [1, 0])
+@pytest.mark.parametrize("edirect", [1, 0, 2])
 def test_scan_c1_fp64(edirect):
     _scan_parity(synth.config1(), "f64", 1e-8, energy_xy_direct=edirect)
 
 
-@pytest.mark.parametrize("edirect,chunk", [(1, 256), (0, 256), (1, 7)])
+@pytest.mark.parametrize("edirect,chunk", [(1, 256), (0, 256), (1, 7), (2, 256), (2, 7)])
 def test_scan_c2_subset_fp32(edirect, chunk):
     w = synth.subset(synth.config2(), 96, stride=83)
     _scan_parity(w, "f32", 0.01, energy_xy_direct=edirect, configs_per_chunk=chunk)
 
 
-@pytest.mark.parametrize("snap_pass,chunk", [(16, 256), (1, 256), (2, 5)])
-def test_scan_batched_uneven_ligands_three_snapshots(snap_pass, chunk):
+@pytest.mark.parametrize("snap_pass,chunk,edirect", [(16, 256, 0), (1, 256, 0), (2, 5, 0), (1, 64, 2), (16, 9, 2)])
+def test_scan_batched_uneven_ligands_three_snapshots(snap_pass, chunk, edirect):
     """Ragged batch: 5 ligands of 8..40 atoms with different configuration
     counts against 3 jittered snapshots; snapshots handled all in one z pass,
     one per pass, or 2 + 1, and chunks that cross ligand boundaries."""
     w = synth.config3(n_ligands=5, n_snap=3, cfg_scale=0.02)
-    P, B, res = _scan_parity(w, "f32", 0.01, snapshots_per_pass=snap_pass, configs_per_chunk=chunk)
+    P, B, res = _scan_parity(w, "f32", 0.01, snapshots_per_pass=snap_pass, configs_per_chunk=chunk,
+                             energy_xy_direct=edirect)
     assert P.shape[0] == 3
 
 
@@ -325,7 +326,7 @@ def test_autotune_picks_valid_schedule():
     ref = ctx.partials_numpy(ctx.scan(b, w.T), 1, b.n_cfg)
     tun, ms = ctx.autotune(b, w.T, max_cfgs=64)
     assert tun["configs_per_chunk"] in (64, 128, 256, 512)
-    assert tun["energy_xy_direct"] in (0, 1) and tun["use_graph"] in (0, 1)
+    assert tun["energy_xy_direct"] in (0, 1, 2) and tun["use_graph"] in (0, 1)
     assert ms > 0 and ctx.get_tuning() == tun
     got = ctx.partials_numpy(ctx.scan(b, w.T), 1, b.n_cfg)
     np.testing.assert_array_equal(got["n_finite"], ref["n_finite"])
