@@ -64,6 +64,21 @@ def recorded_traffic(tuning: dict):
         return None
 
 
+ORACLE_GOLDEN = os.path.join(ROOT, "tests", "golden", "c2_oracle.json")
+
+
+def precision_vs_oracle(args, result):
+    """FP32 scan (FP64 accumulation) against the FP64 oracle's stored results
+    of the same T4L-sized workload (written by tests/golden/make_c2_oracle.py)."""
+    if args.workload != "c2" or not os.path.exists(ORACLE_GOLDEN):
+        return None
+    ref = json.load(open(ORACLE_GOLDEN))["occ"]
+    B, dG = float(result["B"][0, 0]), float(result["res"]["dG"][0])
+    return {"oracle": "FP64 direct trilinear sums, occupancy mode, all 8000 configurations",
+            "bpmf_abs_err_kcal_mol": abs(B - ref["B"]), "dG_abs_err_kcal_mol": abs(dG - ref["dG"]),
+            "oracle_bpmf_kcal_mol": ref["B"], "oracle_dG_kcal_mol": ref["dG"]}
+
+
 def copy_calibration():
     """One 1 GiB device-to-device copy (a plain copy kernel of known size),
     for scaling the FETCH_SIZE / WRITE_SIZE counters."""
@@ -387,6 +402,7 @@ def main():
         "path_alg_GBps": path_bytes / (ms_step / 1e3) / 1e9,
         "roofline": roof,
         "kernels": kernels,
+        "precision": precision_vs_oracle(args, result),
         "bpmf_kcal_mol": float(result["B"][0, 0]),
         "dG_kcal_mol": float(result["res"]["dG"][0]),
         "psi_min_kcal_mol": float(result["res"]["psi_min"][0]),
