@@ -79,6 +79,20 @@ def precision_vs_oracle(args, result):
             "oracle_bpmf_kcal_mol": ref["B"], "oracle_dG_kcal_mol": ref["dG"]}
 
 
+def pose_resampling(ctx, batch, partials, T, K: int = 100):
+    """Sampling importance resampling of K poses from the finished scan
+    (the solvation leg's input), timed."""
+    import torch
+    from workload import synth
+    u = synth.uniforms(77, 2 * K)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cfg, t, psi = ctx.sample_poses(batch, partials, 0, 0, T, u)
+    dt = time.perf_counter() - t0
+    return {"poses": K, "distinct_configurations": int(len(set(cfg.tolist()))), "seconds": dt,
+            "mean_psi_kcal_mol": float(psi.mean())}
+
+
 def copy_calibration():
     """One 1 GiB device-to-device copy (a plain copy kernel of known size),
     for scaling the FETCH_SIZE / WRITE_SIZE counters."""
@@ -403,6 +417,7 @@ def main():
         "roofline": roof,
         "kernels": kernels,
         "precision": precision_vs_oracle(args, result),
+        "pose_resampling": pose_resampling(ctx, batch, out, w.T) if args.workload == "c2" else None,
         "bpmf_kcal_mol": float(result["B"][0, 0]),
         "dG_kcal_mol": float(result["res"]["dG"][0]),
         "psi_min_kcal_mol": float(result["res"]["psi_min"][0]),

@@ -222,6 +222,29 @@ int fftdg_profile(fftdg_ctx *ctx, int enable);
 int fftdg_profile_read(fftdg_ctx *ctx, int32_t kernel_id, double *ms_host, int64_t *launches_host,
                        double *alg_bytes_host);
 
+/* Sampling importance resampling of poses (solvation section: poses for the
+ * single-step perturbation, Eq. 11, are drawn from the scanned bound state with
+ * weight exp(-Psi/kT)).  For ligand `lig` and snapshot `snap` of a finished
+ * scan of batch b (partials p_dev as written by fftdg_scan), draws K poses
+ * (configuration c, translation t), with replacement, with probability
+ * exp(-Psi_c(t)/kT) / Z over every clash-free box-valid translation of every
+ * scanned configuration of the ligand, in two inverse-CDF steps (the random
+ * numbers are inputs, u_host [2K] in [0, 1)):
+ *   configuration: the running sum over the ligand's configurations in index
+ *     order of Z_c = exp(m_c - max m) s_c (FP64, from the partials) is
+ *     searched for u_host[2k] times its total (first sum exceeding it);
+ *   translation: the configuration's energies are recomputed as
+ *     fftdg_energy_grid does and the running sum over its clash-free
+ *     translations in linear order (tz, ty, tx) of exp(-(Psi - min Psi)/kT)
+ *     (FP64) is searched for u_host[2k+1] times its total.
+ * Writes cfg_host [K] (configuration index in the batch), t_host [K][3]
+ * (tx, ty, tz, valid-translation indices as in fftdg_energy_grid) and
+ * psi_host [K] (the pose's Psi, kcal/mol).  E_NOVALID if the ligand has no
+ * clash-free translation in that snapshot.  Synchronizes the stream. */
+int fftdg_sample_poses(fftdg_ctx *ctx, const fftdg_batch *b, const fftdg_partial *p_dev, int32_t lig,
+                       int32_t snap, double T_K, int32_t K, const double *u_host, int32_t *cfg_host,
+                       int32_t *t_host, double *psi_host);
+
 /* Execution schedule (results do not depend on it beyond rounding order of
  * the FP32 transforms):
  *   configs_per_chunk  configurations whose forward and inverse planes share

@@ -234,3 +234,43 @@ def scan_features(parts_by_snap, W: np.ndarray, cfg_off: np.ndarray) -> np.ndarr
             out[c, 1] = min(psi[c] - PM, 50.0) / 10.0 if np.isfinite(psi[c]) else 5.0
             out[c, 2] = f[c]
     return out
+
+
+def sample_poses(partials: np.ndarray, energies, T: float, uniforms: np.ndarray):
+    """Sampling importance resampling of poses (solvation section: K poses
+    drawn from the scanned bound state with weight exp(-Psi/kT)), in two
+    inverse-CDF steps with the uniforms u[2k], u[2k+1]:
+      configuration: running sum over configurations in index order of
+        Z_c = exp(m_c - max m) s_c (configurations with nothing finite weigh 0);
+      translation: running sum over the configuration's clash-free
+        translations in linear (tz, ty, tx) order of exp(-(Psi - min Psi)/kT).
+    A draw takes the first running sum exceeding u times the total.
+    partials: rows of one ligand and snapshot; energies(c) -> (psi [Vz][Vy][Vx],
+    clash mask or None).  Returns (cfg [K], t [K][3] as (tx, ty, tz), psi [K])."""
+    p = np.asarray(partials, dtype=np.float64)
+    u = np.asarray(uniforms, dtype=np.float64)
+    K = u.size // 2
+    fin = p[:, 3] > 0
+    if not np.any(fin):
+        raise ValueError("no clash-free translation to draw")
+    M = np.max(p[fin, 0])
+    z = np.where(fin, np.exp(np.where(fin, p[:, 0], M) - M) * p[:, 1], 0.0)
+    cdf = np.cumsum(z)
+    cfg = np.minimum(np.searchsorted(cdf, u[0::2][:K] * cdf[-1], side="right"), len(z) - 1)
+    t = np.zeros((K, 3), np.int64)
+    psi_k = np.zeros(K)
+    beta = 1.0 / kT(T)
+    for c in np.unique(cfg):
+        psi, clash = energies(int(c))
+        Vz, Vy, Vx = psi.shape
+        f = psi.ravel()
+        ok = np.ones(f.size, bool) if clash is None else ~np.asarray(clash, bool).ravel()
+        w = np.where(ok, np.exp(-beta * (f - np.min(f[ok]))), 0.0)
+        cw = np.cumsum(w)
+        ks = np.flatnonzero(cfg == c)
+        lin = np.minimum(np.searchsorted(cw, u[2 * ks + 1] * cw[-1], side="right"), f.size - 1)
+        t[ks, 0] = lin % Vx
+        t[ks, 1] = (lin // Vx) % Vy
+        t[ks, 2] = lin // (Vx * Vy)
+        psi_k[ks] = f[lin]
+    return cfg, t, psi_k

@@ -55,7 +55,7 @@ EXPORTS = ["fftdg_version", "fftdg_status_string", "fftdg_create", "fftdg_destro
            "fftdg_get_tuning", "fftdg_set_tuning", "fftdg_autotune", "fftdg_config_features",
            "fftdg_mlp_create", "fftdg_mlp_destroy", "fftdg_mlp_last_error", "fftdg_mlp_num_params",
            "fftdg_mlp_set_params", "fftdg_mlp_get_params", "fftdg_mlp_forward", "fftdg_mlp_grad",
-           "fftdg_mlp_train_step", "fftdg_proposal_sample", "fftdg_scan_features", "fftdg_is_plan"]
+           "fftdg_mlp_train_step", "fftdg_proposal_sample", "fftdg_scan_features", "fftdg_is_plan", "fftdg_sample_poses"]
 
 N_FEATURES = 18
 N_SCAN_FEATURES = 3
@@ -110,6 +110,7 @@ def load():
     L.fftdg_proposal_sample.argtypes = [p, p, i32, d, d, i32, p, p, p]
     L.fftdg_scan_features.argtypes = [p, ctypes.POINTER(BatchC), p, p, i32, i32]
     L.fftdg_is_plan.argtypes = [p, ctypes.POINTER(BatchC), p, d, d, d, d, p, ctypes.c_int64, p, p, p]
+    L.fftdg_sample_poses.argtypes = [p, ctypes.POINTER(BatchC), p, i32, i32, d, i32, p, p, p, p]
     for name in EXPORTS:
         if name not in ("fftdg_destroy", "fftdg_status_string", "fftdg_last_error", "fftdg_mlp_destroy",
                         "fftdg_mlp_last_error", "fftdg_mlp_num_params"):
@@ -338,6 +339,18 @@ class FFTDG:
                 uniforms):
         """Stratified importance-sampling plan (see is_plan)."""
         return is_plan(batch, yhat, top_frac, draw_frac, alpha, tau, uniforms, self)
+
+    def sample_poses(self, batch: Batch, partials, lig: int, snap: int, T: float, uniforms):
+        """Sampling importance resampling of len(uniforms)//2 poses:
+        (configuration index [K], translation (tx, ty, tz) [K][3], Psi [K])."""
+        u = np.ascontiguousarray(uniforms, np.float64)
+        K = u.size // 2
+        cfg = np.zeros(K, np.int32)
+        t = np.zeros((K, 3), np.int32)
+        psi = np.zeros(K, np.float64)
+        self._check(self.L.fftdg_sample_poses(self.h_ctx, ctypes.byref(batch.c), _ptr(partials), int(lig), int(snap),
+                                              float(T), K, _ptr(u), _ptr(cfg), _ptr(t), _ptr(psi)))
+        return cfg, t, psi
 
     def reduce(self, batch: Batch, partials, T: float, cfg_weight=None):
         B = np.zeros((batch.n_lig, self.n_snap), np.float64)

@@ -44,6 +44,9 @@ hipError_t launch_reduce(hipStream_t st, const fftdg_partial *p, int64_t n_cfg_t
                          const int32_t *cfg_off, const double *cfg_w, const double *W, double kT, double h3,
                          double c0, double *B, LigRed *res);
 
+hipError_t launch_sample_translations(hipStream_t st, int precision, const void *psi, const uint8_t *clash, int n,
+                                     double beta, const double *u, int nu, int32_t *out_lin, double *out_psi);
+
 hipError_t launch_scan_features(hipStream_t st, const fftdg_partial *p, int64_t n_cfg_total, int n_snap, int n_lig,
                                 const int32_t *cfg_off, const double *W, float *feat, int ld, int col0);
 

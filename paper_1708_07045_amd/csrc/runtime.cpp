@@ -38,6 +38,7 @@ struct fftdg_ctx {
     const KernelSet *ks = nullptr;
     int n_ch = 3;  // receptor/ligand channels: 3 energy (+1 occupancy)
     DevBuf tw, rspec, rxy, ws_fwd, ws_inv, pp, tables, red_B, red_res, red_off, red_W;
+    DevBuf sir_psi, sir_clash, sir_u, sir_lin, sir_psi_out;  // pose resampling
     int n_snap = 0;
     std::vector<double> W;
     void *pinned = nullptr;
@@ -716,7 +717,8 @@ void fftdg_destroy(fftdg_ctx *c) {
     (void)hipSetDevice(c->device);
     (void)hipStreamSynchronize(c->stream);
     DevBuf *bufs[] = {&c->tw, &c->rspec, &c->rxy, &c->ws_fwd, &c->ws_inv, &c->pp, &c->tables,
-                      &c->red_B, &c->red_res, &c->red_off, &c->red_W, &c->prof_cnt, &c->tune_out};
+                      &c->red_B, &c->red_res, &c->red_off, &c->red_W, &c->prof_cnt, &c->tune_out,
+                      &c->sir_psi, &c->sir_clash, &c->sir_u, &c->sir_lin, &c->sir_psi_out};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->pinned) (void)hipHostFree(c->pinned);
@@ -1196,6 +1198,100 @@ int fftdg_is_plan(fftdg_ctx *ctx, const fftdg_batch *b, const float *yhat, doubl
     }
     for (int64_t c = 0; c < (int64_t)b->cfg_off[nl]; ++c) n_sel += sel[c] != 0;
     if (n_scan) *n_scan = n_sel;
+    return FFTDG_OK;
+}
+
+int fftdg_sample_poses(fftdg_ctx *ctx, const fftdg_batch *b, const fftdg_partial *p, int32_t lig, int32_t snap,
+                       double T_K, int32_t K, const double *u, int32_t *cfg_out, int32_t *t_out, double *psi_out) {
+    if (!ctx) return FFTDG_E_INVALID;
+    if (ctx->n_snap <= 0) return set_err(ctx, FFTDG_E_STATE, "sample_poses before set_receptors");
+    int rc = validate_batch(ctx, b);
+    if (rc) return rc;
+    if (lig < 0 || lig >= b->n_lig) return set_err(ctx, FFTDG_E_INVALID, "sample_poses: ligand out of range");
+    if (snap < 0 || snap >= ctx->n_snap) return set_err(ctx, FFTDG_E_INVALID, "sample_poses: snapshot out of range");
+    if (!(T_K > 0.0) || !is_fin(T_K)) return set_err(ctx, FFTDG_E_INVALID, "sample_poses: temperature must be > 0");
+    if (K < 0) return set_err(ctx, FFTDG_E_INVALID, "sample_poses: K must be >= 0");
+    if (K == 0) return FFTDG_OK;
+    if (!p || !u || !cfg_out || !t_out || !psi_out) return set_err(ctx, FFTDG_E_INVALID, "sample_poses: NULL pointer");
+    for (int k = 0; k < 2 * K; ++k)
+        if (!(u[k] >= 0.0 && u[k] < 1.0)) return set_err(ctx, FFTDG_E_INVALID, "sample_poses: uniforms must lie in [0, 1)");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    const int ncfg = b->cfg_off[b->n_lig];
+    const int c0 = b->cfg_off[lig], P = b->cfg_off[lig + 1] - c0;
+    std::vector<fftdg_partial> hp(P);
+    HIPCHK(ctx, hipMemcpyAsync(hp.data(), p + (int64_t)snap * ncfg + c0, sizeof(fftdg_partial) * P,
+                               hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    // configuration level: Z_c = exp(m_c - M) s_c in index order
+    double M = -INFINITY;
+    for (int j = 0; j < P; ++j)
+        if (hp[j].n_finite > 0) M = std::max(M, hp[j].m);
+    if (!(M > -INFINITY)) return set_err(ctx, FFTDG_E_NOVALID, "sample_poses: no clash-free translation to draw");
+    std::vector<double> cdf(P);
+    double run = 0.0;
+    for (int j = 0; j < P; ++j) {
+        if (hp[j].n_finite > 0) run += std::exp(hp[j].m - M) * hp[j].s;
+        cdf[j] = run;
+    }
+    std::vector<int> pick(K);
+    for (int k = 0; k < K; ++k) {
+        const double x = u[2 * k] * cdf[P - 1];
+        int j = (int)(std::upper_bound(cdf.begin(), cdf.end(), x) - cdf.begin());
+        if (j > P - 1) j = P - 1;
+        while (j > 0 && hp[j].n_finite == 0) --j;  // only at x == total (rounding)
+        pick[k] = j;
+    }
+    // translation level, one drawn configuration at a time
+    const double beta = 1.0 / (kR * T_K);
+    const size_t tsz = ctx->g.precision == FFTDG_F32 ? sizeof(float) : sizeof(double);
+    std::vector<int> order(K);
+    for (int k = 0; k < K; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int c) { return pick[a] < pick[c]; });
+    std::vector<double> uu;
+    std::vector<int32_t> lin;
+    std::vector<double> ps;
+    for (size_t q = 0; q < order.size();) {
+        const int j = pick[order[q]];
+        size_t r = q;
+        uu.clear();
+        while (r < order.size() && pick[order[r]] == j) uu.push_back(u[2 * order[r++] + 1]);
+        const int cfg = c0 + j;
+        Plan PL;
+        if ((rc = build_plan(ctx, b, true, cfg, PL))) return rc;
+        const CfgDev &d = PL.cfg[cfg];
+        const int n = d.n_valid;
+        if (n <= 0) return set_err(ctx, FFTDG_E_INVALID, "sample_poses: drawn configuration has no valid translation");
+        if ((rc = reserve(ctx, ctx->sir_psi, tsz * (size_t)n))) return rc;
+        if ((rc = reserve(ctx, ctx->sir_clash, (size_t)n))) return rc;
+        if ((rc = reserve(ctx, ctx->sir_u, sizeof(double) * uu.size()))) return rc;
+        if ((rc = reserve(ctx, ctx->sir_lin, sizeof(int32_t) * uu.size()))) return rc;
+        if ((rc = reserve(ctx, ctx->sir_psi_out, sizeof(double) * uu.size()))) return rc;
+        if ((rc = run_plan(ctx, b, PL, T_K, nullptr, snap, ctx->sir_psi.p, (uint8_t *)ctx->sir_clash.p))) return rc;
+        HIPCHK(ctx, hipMemcpyAsync(ctx->sir_u.p, uu.data(), sizeof(double) * uu.size(), hipMemcpyHostToDevice,
+                                   ctx->stream));
+        HIPCHK(ctx, launch_sample_translations(ctx->stream, ctx->g.precision, ctx->sir_psi.p,
+                                               (const uint8_t *)ctx->sir_clash.p, n, beta,
+                                               (const double *)ctx->sir_u.p, (int)uu.size(),
+                                               (int32_t *)ctx->sir_lin.p, (double *)ctx->sir_psi_out.p));
+        lin.resize(uu.size());
+        ps.resize(uu.size());
+        HIPCHK(ctx, hipMemcpyAsync(lin.data(), ctx->sir_lin.p, sizeof(int32_t) * uu.size(), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        HIPCHK(ctx, hipMemcpyAsync(ps.data(), ctx->sir_psi_out.p, sizeof(double) * uu.size(), hipMemcpyDeviceToHost,
+                                   ctx->stream));
+        HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+        const int Vx = d.V[0], Vy = d.V[1];
+        for (size_t i = 0; i < uu.size(); ++i) {
+            const int k = order[q + i];
+            const int l = lin[i];
+            cfg_out[k] = cfg;
+            t_out[3 * k + 0] = l % Vx;
+            t_out[3 * k + 1] = (l / Vx) % Vy;
+            t_out[3 * k + 2] = l / (Vx * Vy);
+            psi_out[k] = ps[i];
+        }
+        q = r;
+    }
     return FFTDG_OK;
 }
 

@@ -1421,6 +1421,69 @@ __global__ __launch_bounds__(NT) void k_scan_features(const fftdg_partial *__res
     }
 }
 
+// Translation draws of sampling importance resampling for one
+// configuration (one block): weights w_i = exp(-beta (Psi_i - Psi_min)) over
+// the clash-free translations i of the exported grid (linear order
+// (tz, ty, tx)), FP64; draw j takes the first i whose running sum of w
+// exceeds u_j times the total.  Each thread owns a contiguous segment; a
+// draw finds its segment from the segments' running sums, then scans it.
+template <typename T>
+__global__ __launch_bounds__(NT) void k_sample_translations(const T *__restrict__ psi,
+                                                            const uint8_t *__restrict__ clash, int n, double beta,
+                                                            const double *__restrict__ u, int nu,
+                                                            int32_t *__restrict__ out_lin, double *__restrict__ out_psi) {
+    __shared__ double seg[NT + 1];
+    __shared__ double red[NT];
+    const int t = threadIdx.x;
+    const int L = (n + NT - 1) / NT;
+    const int a = min(n, t * L), e = min(n, a + L);
+    double pm = INFINITY;
+    for (int i = a; i < e; ++i)
+        if (!clash[i] && (double)psi[i] < pm) pm = (double)psi[i];
+    red[t] = pm;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (t < w) red[t] = red[t] < red[t + w] ? red[t] : red[t + w];
+        __syncthreads();
+    }
+    const double P0 = red[0];
+    double sum = 0.0;
+    for (int i = a; i < e; ++i)
+        if (!clash[i]) sum += exp(-beta * ((double)psi[i] - P0));
+    seg[t + 1] = sum;
+    __syncthreads();
+    if (t == 0) {
+        seg[0] = 0.0;
+        for (int k = 1; k <= NT; ++k) seg[k] += seg[k - 1];
+    }
+    __syncthreads();
+    const double total = seg[NT];
+    for (int j = t; j < nu; j += NT) {
+        const double x = u[j] * total;
+        // segment k: seg[k] <= x < seg[k + 1]
+        int lo = 0, hi = NT;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (seg[mid] <= x) lo = mid; else hi = mid;
+        }
+        const int sa = min(n, lo * L), se = min(n, sa + L);
+        double run = seg[lo];
+        int pick = -1;
+        for (int i = sa; i < se; ++i) {
+            if (clash[i]) continue;
+            run += exp(-beta * ((double)psi[i] - P0));
+            pick = i;
+            if (run > x) break;
+        }
+        if (pick < 0) {  // x at the very top: the last clash-free translation
+            for (int i = n - 1; i >= 0; --i)
+                if (!clash[i]) { pick = i; break; }
+        }
+        out_lin[j] = pick;
+        out_psi[j] = (double)psi[pick];
+    }
+}
+
 // Eq. 7 receptor grids and Eq. 10 occupancy from atoms, FP64, one thread per
 // grid point, atoms staged through LDS in order.
 #pragma clang fp contract(off)
@@ -1588,6 +1651,17 @@ hipError_t launch_reduce(hipStream_t st, const fftdg_partial *p, int64_t n_cfg_t
                          double c0, double *B, LigRed *res) {
     hipLaunchKernelGGL(k_reduce, dim3(n_lig), dim3(NT), 0, st, p, n_cfg_total, n_snap, cfg_off, cfg_w, W, kT, h3,
                        c0, B, res);
+    return hipGetLastError();
+}
+
+hipError_t launch_sample_translations(hipStream_t st, int precision, const void *psi, const uint8_t *clash, int n,
+                                     double beta, const double *u, int nu, int32_t *out_lin, double *out_psi) {
+    if (precision == FFTDG_F64)
+        hipLaunchKernelGGL((k_sample_translations<double>), dim3(1), dim3(NT), 0, st, (const double *)psi, clash, n,
+                           beta, u, nu, out_lin, out_psi);
+    else
+        hipLaunchKernelGGL((k_sample_translations<float>), dim3(1), dim3(NT), 0, st, (const float *)psi, clash, n,
+                           beta, u, nu, out_lin, out_psi);
     return hipGetLastError();
 }
 
