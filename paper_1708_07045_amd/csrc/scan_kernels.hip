@@ -410,10 +410,15 @@ __device__ void xy_forward(const Fill &fill, int y0, int Ly, typename Cx<T>::t *
 //   F(ky, kx) = w^(kx ax) ((1-fx) + fx w^kx) * w^(ky ay) ((1-fy) + fy w^ky)
 // (w = exp(-2 pi i / N)), scaled by gamma_ch times its z weight; the plane's
 // spectrum is the sum over the few atoms that touch it.  Per-atom factors
-// are tabulated in LDS (DE_A atoms per pass); with more atoms the passes
-// accumulate in the output.  This is the xy FFT of the spread plane with
-// its zero inputs pruned, exact in exact arithmetic.
-constexpr int DE_A = 32;
+// are tabulated in LDS (de_atoms<N>() atoms per pass, as many as fit in the
+// plane buffer the FFT path uses); with more atoms the passes accumulate in
+// the output.  This is the xy FFT of the spread plane with its zero inputs
+// pruned, exact in exact arithmetic.
+template <int N>
+__host__ __device__ constexpr int de_atoms() {
+    // X [a][N/2+1] and Y [a][N] tables must fit in the N x S plane buffer
+    return (N * Geo<float, N>::S) / (N / 2 + 1 + N) < 32 ? (N * Geo<float, N>::S) / (N / 2 + 1 + N) : 32;
+}
 
 template <typename T, int N>
 __device__ void energy_plane_direct(const CfgDev &c, int p, const int32_t *__restrict__ ulat,
@@ -421,6 +426,8 @@ __device__ void energy_plane_direct(const CfgDev &c, int p, const int32_t *__res
                                     typename Cx<T>::t *tab, typename Cx<T>::t *__restrict__ ws) {
     using C2 = typename Cx<T>::t;
     constexpr int H = N / 2 + 1, NP = N * H;
+    constexpr int DE_A = de_atoms<N>();
+    static_assert(DE_A >= 1 && DE_A * (H + N) <= N * Geo<T, N>::S, "per-atom tables must fit the plane buffer");
     __shared__ T wgt[DE_A][3];
     __shared__ int2 axy[DE_A];
     __shared__ T fxy[DE_A][2];

@@ -141,6 +141,24 @@ def test_energy_c2_fp32_cap_and_fp64_n64():
     _energy_parity(w, [1, 6], "f32", 2e-5)
 
 
+@pytest.mark.parametrize("n_fft,h,prec", [(32, 0.8, "f32"), (64, 0.4, "f32"), (32, 0.8, "f64")])
+def test_direct_energy_many_atoms_per_plane(n_fft, h, prec):
+    """A flat 40-atom ligand with identity rotations puts every atom in two
+    z-planes, more than one pass of the per-atom tables of the direct energy
+    transform (energy mode 2) at these FFT sizes; modes 0 and 2 both match
+    the oracle."""
+    n_rec = n_fft - 2
+    w = synth.tiny(seed=11, n_rec=n_rec, n_fft=n_fft, h=h, n_rec_atoms=250, n_lig_atoms=40, n_cfg=3,
+                   clash_mode="occ", precision=prec, r_ball=0.45 * n_rec * h)
+    L = w.ligands[0]
+    L.conformers[..., 2] *= 0.02
+    L.cfg_quat[:] = [1.0, 0.0, 0.0, 0.0]
+    u, box = oracle.place_cfg(w, 0, 0)
+    assert len(set(np.floor(u[:, 2]).astype(int).tolist())) <= 2
+    for ed in (0, 2):
+        _energy_parity(w, [0, 1, 2], prec, TOL_F32 if prec == "f32" else TOL_F64, energy_xy_direct=ed)
+
+
 def test_single_point_charge_gpu():
     """One ligand atom of charge 1 (no LJ) at an integer lattice position
     reproduces the shifted receptor ELE grid."""
