@@ -93,6 +93,18 @@ def pose_resampling(ctx, batch, partials, T, K: int = 100):
             "mean_psi_kcal_mol": float(psi.mean())}
 
 
+def spacing_study(w, ctx, batch, partials):
+    """Grid energies at 0.125 / 0.25 / 0.5 / 0.8 A against direct pair sums
+    over 200 resampled poses (the paper's spacing comparison), timed."""
+    import torch
+    from paper_1708_07045_amd import spacing
+    t0 = time.perf_counter()
+    res = spacing.study(w, ctx, batch, partials, n_poses=200)
+    torch.cuda.synchronize()
+    res["seconds"] = time.perf_counter() - t0
+    return res
+
+
 def copy_calibration():
     """One 1 GiB device-to-device copy (a plain copy kernel of known size),
     for scaling the FETCH_SIZE / WRITE_SIZE counters."""
@@ -418,6 +430,7 @@ def main():
         "kernels": kernels,
         "precision": precision_vs_oracle(args, result),
         "pose_resampling": pose_resampling(ctx, batch, out, w.T) if args.workload == "c2" else None,
+        "spacing_study": spacing_study(w, ctx, batch, out) if args.workload == "c2" else None,
         "bpmf_kcal_mol": float(result["B"][0, 0]),
         "dG_kcal_mol": float(result["res"]["dG"][0]),
         "psi_min_kcal_mol": float(result["res"]["psi_min"][0]),

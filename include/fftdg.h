@@ -245,6 +245,44 @@ int fftdg_sample_poses(fftdg_ctx *ctx, const fftdg_batch *b, const fftdg_partial
                        int32_t snap, double T_K, int32_t K, const double *u_host, int32_t *cfg_host,
                        int32_t *t_host, double *psi_host);
 
+/* ------------------------------------------------------------------------
+ * Grid tools without an FFT context, for the accuracy of grid-based energies
+ * against direct atom-pair sums as the spacing varies (section on the
+ * accuracy of FFT-based interaction energies).  Each call launches on
+ * hip_stream of `device`, is asynchronous and returns E_INVALID for bad
+ * sizes or NULL pointers, E_DEVICE for HIP errors (no error text: there is
+ * no context).  n_fft of the grid description is ignored; any edge
+ * 2 <= n_rec <= 1024 is allowed.  All arrays are device arrays.
+ * ------------------------------------------------------------------------ */
+
+/* Eq. 7 grids [3][n_rec^3] (context precision of g) and Eq. 10 occupancy
+ * [n_rec^3] (OCC mode; NULL in CAP mode), exactly as fftdg_receptor_grids. */
+int fftdg_grids_build(int device, void *hip_stream, const fftdg_grid_desc *g, int32_t n_atoms,
+                      const double *xyz_dev, const double *q_dev, const double *sigma_dev,
+                      const double *eps_dev, void *grids_dev, uint8_t *occ_dev);
+
+/* Interaction energies of n_poses ligand poses (atom coordinates
+ * pose_xyz_dev [n_poses][n_atoms][3], Angstrom) from grids of g by trilinear
+ * interpolation at each atom (Eqs. 3 and 8 at one position; corners outside
+ * the grid read as zero), with the ligand weights of Eqs. 4-6 from the atom
+ * parameters q, sigma, eps [n_atoms]; FP64.  out_dev [n_poses][3] =
+ * (ELE, LJr, LJa) in kcal/mol.  n_atoms <= 256. */
+int fftdg_grid_energies(int device, void *hip_stream, const fftdg_grid_desc *g, const void *grids_dev,
+                        int32_t n_poses, int32_t n_atoms, const double *q_dev, const double *sigma_dev,
+                        const double *eps_dev, const double *pose_xyz_dev, double *out_dev);
+
+/* Direct atom-pair interaction energies of the same poses with receptor
+ * atoms rxyz_dev [n_rec_atoms][3] (Eqs. 4-6 without grids), FP64:
+ *   ELE 332.05 q_i q_j / r,  LJr sqrt(eps_i eps_j) (sigma_i sigma_j)^6 / r^12,
+ *   LJa -2 sqrt(eps_i eps_j) (sigma_i sigma_j)^3 / r^6;
+ * exclusion = 1 drops every term of a pair closer than 2^(-1/6) sigma_j (the
+ * receptor atom's, as in the occupancy-mode grids); 0 keeps all pairs.
+ * out_dev [n_poses][3].  n_atoms <= 256. */
+int fftdg_pair_energies(int device, void *hip_stream, int32_t n_rec_atoms, const double *rxyz_dev,
+                        const double *rq_dev, const double *rsigma_dev, const double *reps_dev, int32_t n_poses,
+                        int32_t n_atoms, const double *q_dev, const double *sigma_dev, const double *eps_dev,
+                        const double *pose_xyz_dev, int32_t exclusion, double *out_dev);
+
 /* Execution schedule (results do not depend on it beyond rounding order of
  * the FP32 transforms):
  *   configs_per_chunk  configurations whose forward and inverse planes share

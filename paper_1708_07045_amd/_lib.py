@@ -55,7 +55,8 @@ EXPORTS = ["fftdg_version", "fftdg_status_string", "fftdg_create", "fftdg_destro
            "fftdg_get_tuning", "fftdg_set_tuning", "fftdg_autotune", "fftdg_config_features",
            "fftdg_mlp_create", "fftdg_mlp_destroy", "fftdg_mlp_last_error", "fftdg_mlp_num_params",
            "fftdg_mlp_set_params", "fftdg_mlp_get_params", "fftdg_mlp_forward", "fftdg_mlp_grad",
-           "fftdg_mlp_train_step", "fftdg_proposal_sample", "fftdg_scan_features", "fftdg_is_plan", "fftdg_sample_poses"]
+           "fftdg_mlp_train_step", "fftdg_proposal_sample", "fftdg_scan_features", "fftdg_is_plan", "fftdg_sample_poses",
+           "fftdg_grids_build", "fftdg_grid_energies", "fftdg_pair_energies"]
 
 N_FEATURES = 18
 N_SCAN_FEATURES = 3
@@ -111,6 +112,9 @@ def load():
     L.fftdg_scan_features.argtypes = [p, ctypes.POINTER(BatchC), p, p, i32, i32]
     L.fftdg_is_plan.argtypes = [p, ctypes.POINTER(BatchC), p, d, d, d, d, p, ctypes.c_int64, p, p, p]
     L.fftdg_sample_poses.argtypes = [p, ctypes.POINTER(BatchC), p, i32, i32, d, i32, p, p, p, p]
+    L.fftdg_grids_build.argtypes = [ctypes.c_int, p, ctypes.POINTER(GridDesc), i32, p, p, p, p, p, p]
+    L.fftdg_grid_energies.argtypes = [ctypes.c_int, p, ctypes.POINTER(GridDesc), p, i32, i32, p, p, p, p, p]
+    L.fftdg_pair_energies.argtypes = [ctypes.c_int, p, i32, p, p, p, p, i32, i32, p, p, p, p, i32, p]
     for name in EXPORTS:
         if name not in ("fftdg_destroy", "fftdg_status_string", "fftdg_last_error", "fftdg_mlp_destroy",
                         "fftdg_mlp_last_error", "fftdg_mlp_num_params"):
@@ -361,6 +365,65 @@ class FFTDG:
         self._check(self.L.fftdg_reduce(self.h_ctx, ctypes.byref(batch.c), _ptr(partials), _ptr(w), float(T),
                                         _ptr(B), _ptr(res)))
         return B, res
+
+
+class GridTools:
+    """Grids and pose energies without an FFT context (fftdg_grids_build,
+    fftdg_grid_energies, fftdg_pair_energies) on one device and stream."""
+
+    def __init__(self, n_rec: int, h: float, origin, precision: str = "f64", clash_mode: str = "occ",
+                 ljr_cap: float = 10.0, occ_f: float = 0.5, device: int = 0, stream=None):
+        import torch
+        self.torch = torch
+        self.L = load()
+        self.device = torch.device("cuda", device)
+        self.dev_index = device
+        self.n_rec, self.h = n_rec, h
+        self.precision, self.clash_mode = precision, clash_mode
+        self.g = GridDesc(n_rec, 0, h, (ctypes.c_double * 3)(*[float(x) for x in origin]),
+                          F32 if precision == "f32" else F64, OCC if clash_mode == "occ" else CAP, ljr_cap, occ_f)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device).cuda_stream
+
+    def _d(self, a):
+        return self.torch.as_tensor(np.ascontiguousarray(a, np.float64), device=self.device)
+
+    @staticmethod
+    def _rc(rc, what):
+        if rc != OK:
+            raise FFTDGError(rc, what + " failed (" + load().fftdg_status_string(rc).decode() + ")")
+
+    def build(self, xyz, q, sigma, eps):
+        t = self.torch
+        n = self.n_rec
+        grids = t.empty((3, n, n, n), dtype=t.float32 if self.precision == "f32" else t.float64, device=self.device)
+        occ = t.empty((n, n, n), dtype=t.uint8, device=self.device) if self.clash_mode == "occ" else None
+        X, Q, S, E = self._d(xyz), self._d(q), self._d(sigma), self._d(eps)
+        self._rc(self.L.fftdg_grids_build(self.dev_index, ctypes.c_void_p(self.stream), ctypes.byref(self.g),
+                                          int(X.shape[0]), _ptr(X), _ptr(Q), _ptr(S), _ptr(E), _ptr(grids),
+                                          _ptr(occ)), "fftdg_grids_build")
+        t.cuda.synchronize(self.device)
+        return grids, occ
+
+    def grid_energies(self, grids, poses, q, sigma, eps):
+        """poses [n_poses][n_atoms][3] (Angstrom) -> [n_poses][3] (ELE, LJr, LJa)."""
+        P = self._d(poses)
+        Q, S, E = self._d(q), self._d(sigma), self._d(eps)
+        out = self.torch.empty((P.shape[0], 3), dtype=self.torch.float64, device=self.device)
+        self._rc(self.L.fftdg_grid_energies(self.dev_index, ctypes.c_void_p(self.stream), ctypes.byref(self.g),
+                                            _ptr(grids), int(P.shape[0]), int(P.shape[1]), _ptr(Q), _ptr(S), _ptr(E),
+                                            _ptr(P), _ptr(out)), "fftdg_grid_energies")
+        return out.cpu().numpy()
+
+    def pair_energies(self, rxyz, rq, rsigma, reps, poses, q, sigma, eps, exclusion: bool = True):
+        R, RQ, RS, RE = self._d(rxyz), self._d(rq), self._d(rsigma), self._d(reps)
+        P = self._d(poses)
+        Q, S, E = self._d(q), self._d(sigma), self._d(eps)
+        out = self.torch.empty((P.shape[0], 3), dtype=self.torch.float64, device=self.device)
+        self._rc(self.L.fftdg_pair_energies(self.dev_index, ctypes.c_void_p(self.stream), int(R.shape[0]), _ptr(R),
+                                            _ptr(RQ), _ptr(RS), _ptr(RE), int(P.shape[0]), int(P.shape[1]), _ptr(Q),
+                                            _ptr(S), _ptr(E), _ptr(P), 1 if exclusion else 0, _ptr(out)),
+                 "fftdg_pair_energies")
+        return out.cpu().numpy()
 
 
 def is_plan(batch: Batch, yhat, top_frac: float, draw_frac: float, alpha: float, tau: float, uniforms,

@@ -44,6 +44,14 @@ hipError_t launch_reduce(hipStream_t st, const fftdg_partial *p, int64_t n_cfg_t
                          const int32_t *cfg_off, const double *cfg_w, const double *W, double kT, double h3,
                          double c0, double *B, LigRed *res);
 
+hipError_t launch_grid_energies(hipStream_t st, int precision, const void *grids, int n_rec, double h,
+                                const double *origin, int n_atoms, const double *lq, const double *ls,
+                                const double *le, int n_poses, const double *pose, double *out);
+hipError_t launch_pair_energies(hipStream_t st, int n_rec_atoms, const double *rxyz, const double *rq,
+                                const double *rs, const double *re, int n_atoms, const double *lq,
+                                const double *ls, const double *le, int n_poses, const double *pose, int excl,
+                                double *out);
+
 hipError_t launch_sample_translations(hipStream_t st, int precision, const void *psi, const uint8_t *clash, int n,
                                      double beta, const double *u, int nu, int32_t *out_lin, double *out_psi);
 

@@ -1295,4 +1295,50 @@ int fftdg_sample_poses(fftdg_ctx *ctx, const fftdg_batch *b, const fftdg_partial
     return FFTDG_OK;
 }
 
+static int grid_desc_ok(const fftdg_grid_desc *g) {
+    return g && g->n_rec >= 2 && g->n_rec <= 1024 && g->h > 0.0 && is_fin(g->h) && is_fin(g->origin[0]) &&
+           is_fin(g->origin[1]) && is_fin(g->origin[2]) && (g->precision == FFTDG_F32 || g->precision == FFTDG_F64) &&
+           (g->clash_mode == FFTDG_OCC || g->clash_mode == FFTDG_CAP) && g->occ_f > 0.0 && is_fin(g->ljr_cap);
+}
+
+int fftdg_grids_build(int device, void *stream, const fftdg_grid_desc *g, int32_t n_atoms, const double *xyz,
+                      const double *q, const double *sg, const double *ep, void *grids, uint8_t *occ) {
+    if (!grid_desc_ok(g) || n_atoms <= 0 || !xyz || !q || !sg || !ep || !grids) return FFTDG_E_INVALID;
+    if (g->clash_mode == FFTDG_OCC && !occ) return FFTDG_E_INVALID;
+    if (hipSetDevice(device) != hipSuccess) return FFTDG_E_DEVICE;
+    if (launch_receptor_grids((hipStream_t)stream, g->precision, n_atoms, xyz, q, sg, ep, g->n_rec, g->h, g->origin,
+                              g->clash_mode == FFTDG_CAP ? 1 : 0, g->ljr_cap, g->occ_f, grids,
+                              g->clash_mode == FFTDG_OCC ? occ : nullptr) != hipSuccess)
+        return FFTDG_E_DEVICE;
+    return FFTDG_OK;
+}
+
+int fftdg_grid_energies(int device, void *stream, const fftdg_grid_desc *g, const void *grids, int32_t n_poses,
+                        int32_t n_atoms, const double *q, const double *sg, const double *ep, const double *pose_xyz,
+                        double *out) {
+    if (!grid_desc_ok(g) || n_poses < 0 || n_atoms <= 0 || n_atoms > 256 || !grids || !q || !sg || !ep ||
+        (n_poses > 0 && (!pose_xyz || !out)))
+        return FFTDG_E_INVALID;
+    if (n_poses == 0) return FFTDG_OK;
+    if (hipSetDevice(device) != hipSuccess) return FFTDG_E_DEVICE;
+    if (launch_grid_energies((hipStream_t)stream, g->precision, grids, g->n_rec, g->h, g->origin, n_atoms, q, sg, ep,
+                             n_poses, pose_xyz, out) != hipSuccess)
+        return FFTDG_E_DEVICE;
+    return FFTDG_OK;
+}
+
+int fftdg_pair_energies(int device, void *stream, int32_t n_rec_atoms, const double *rxyz, const double *rq,
+                        const double *rs, const double *re, int32_t n_poses, int32_t n_atoms, const double *q,
+                        const double *sg, const double *ep, const double *pose_xyz, int32_t exclusion, double *out) {
+    if (n_rec_atoms <= 0 || !rxyz || !rq || !rs || !re || n_poses < 0 || n_atoms <= 0 || n_atoms > 256 || !q ||
+        !sg || !ep || (n_poses > 0 && (!pose_xyz || !out)) || (exclusion != 0 && exclusion != 1))
+        return FFTDG_E_INVALID;
+    if (n_poses == 0) return FFTDG_OK;
+    if (hipSetDevice(device) != hipSuccess) return FFTDG_E_DEVICE;
+    if (launch_pair_energies((hipStream_t)stream, n_rec_atoms, rxyz, rq, rs, re, n_atoms, q, sg, ep, n_poses,
+                             pose_xyz, exclusion, out) != hipSuccess)
+        return FFTDG_E_DEVICE;
+    return FFTDG_OK;
+}
+
 }  // extern "C"

@@ -1491,6 +1491,108 @@ __global__ __launch_bounds__(NT) void k_sample_translations(const T *__restrict_
     }
 }
 
+// Interaction energy of ligand poses from the receptor grids by trilinear
+// interpolation at each atom's position (what the FFT correlation gives at
+// one translation, Eq. 8), FP64 accumulation; one block per pose.  Corners
+// outside [0, n_rec) read as zero (the zero padding the FFT sees).
+template <typename T>
+__global__ __launch_bounds__(NT) void k_grid_energies(const T *__restrict__ grids, int n_rec, double h, double ox,
+                                                      double oy, double oz, int n_atoms,
+                                                      const double *__restrict__ lq, const double *__restrict__ ls,
+                                                      const double *__restrict__ le,
+                                                      const double *__restrict__ pose, double *__restrict__ out) {
+    __shared__ double red[3][NT];
+    const int p = blockIdx.x, t = threadIdx.x;
+    const long long n2 = (long long)n_rec * n_rec, n3 = n2 * n_rec;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int i = t; i < n_atoms; i += NT) {
+        const double *x = pose + 3 * ((long long)p * n_atoms + i);
+        const double u[3] = {(x[0] - ox) / h, (x[1] - oy) / h, (x[2] - oz) / h};
+        int i0[3];
+        double f[3];
+        for (int d = 0; d < 3; ++d) {
+            const double fl = floor(u[d]);
+            i0[d] = (int)fl;
+            f[d] = u[d] - fl;
+        }
+        const double s3 = ls[i] * ls[i] * ls[i];
+        const double se = sqrt(le[i]);
+        const double gam[3] = {lq[i], se * s3 * s3, -2.0 * se * s3};
+        double v[3] = {0.0, 0.0, 0.0};
+        for (int c = 0; c < 8; ++c) {
+            const int cx = i0[0] + (c & 1), cy = i0[1] + ((c >> 1) & 1), cz = i0[2] + (c >> 2);
+            if (cx < 0 || cy < 0 || cz < 0 || cx >= n_rec || cy >= n_rec || cz >= n_rec) continue;
+            const double w = ((c & 1) ? f[0] : 1.0 - f[0]) * (((c >> 1) & 1) ? f[1] : 1.0 - f[1]) *
+                             ((c >> 2) ? f[2] : 1.0 - f[2]);
+            const long long g = (long long)cz * n2 + (long long)cy * n_rec + cx;
+            for (int ch = 0; ch < 3; ++ch) v[ch] += w * (double)grids[ch * n3 + g];
+        }
+        for (int ch = 0; ch < 3; ++ch) acc[ch] += gam[ch] * v[ch];
+    }
+    for (int ch = 0; ch < 3; ++ch) red[ch][t] = acc[ch];
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (t < w)
+            for (int ch = 0; ch < 3; ++ch) red[ch][t] += red[ch][t + w];
+        __syncthreads();
+    }
+    if (t < 3) out[3 * p + t] = red[t][0];
+}
+
+// Direct atom-pair interaction energies of ligand poses (Eqs. 4-6), FP64,
+// no grid: ELE 332.05 q_i q_j / r, LJr sqrt(eps_i eps_j) (sigma_i sigma_j)^6 / r^12,
+// LJa -2 sqrt(eps_i eps_j) (sigma_i sigma_j)^3 / r^6; with `excl` every term
+// of a pair closer than 2^(-1/6) sigma_j (the receptor atom's) is zero, as
+// in the occupancy-mode grids.  One block per pose.
+__global__ __launch_bounds__(NT) void k_pair_energies(int n_rec_atoms, const double *__restrict__ rxyz,
+                                                      const double *__restrict__ rq, const double *__restrict__ rs,
+                                                      const double *__restrict__ re, int n_atoms,
+                                                      const double *__restrict__ lq, const double *__restrict__ ls,
+                                                      const double *__restrict__ le,
+                                                      const double *__restrict__ pose, int excl,
+                                                      double *__restrict__ out) {
+    __shared__ double lx[MAXA], ly[MAXA], lz[MAXA], lg[3][MAXA];
+    __shared__ double red[3][NT];
+    const int p = blockIdx.x, t = threadIdx.x;
+    for (int i = t; i < n_atoms; i += NT) {
+        const double *x = pose + 3 * ((long long)p * n_atoms + i);
+        lx[i] = x[0];
+        ly[i] = x[1];
+        lz[i] = x[2];
+        const double s3 = ls[i] * ls[i] * ls[i];
+        const double se = sqrt(le[i]);
+        lg[0][i] = lq[i];
+        lg[1][i] = se * s3 * s3;
+        lg[2][i] = -2.0 * se * s3;
+    }
+    __syncthreads();
+    const double k6 = pow(2.0, -1.0 / 6.0);
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int j = t; j < n_rec_atoms; j += NT) {
+        const double X = rxyz[3 * j], Y = rxyz[3 * j + 1], Z = rxyz[3 * j + 2];
+        const double s3 = rs[j] * rs[j] * rs[j];
+        const double se = sqrt(re[j]);
+        const double rex = k6 * rs[j];
+        for (int i = 0; i < n_atoms; ++i) {
+            const double dx = lx[i] - X, dy = ly[i] - Y, dz = lz[i] - Z;
+            const double r = sqrt(dx * dx + dy * dy + dz * dz);
+            if (excl && r < rex) continue;
+            const double r6 = r * r * r * r * r * r;
+            acc[0] += lg[0][i] * 332.05 * rq[j] / r;
+            acc[1] += lg[1][i] * se * s3 * s3 / (r6 * r6);
+            acc[2] += lg[2][i] * se * s3 / r6;
+        }
+    }
+    for (int ch = 0; ch < 3; ++ch) red[ch][t] = acc[ch];
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (t < w)
+            for (int ch = 0; ch < 3; ++ch) red[ch][t] += red[ch][t + w];
+        __syncthreads();
+    }
+    if (t < 3) out[3 * p + t] = red[t][0];
+}
+
 // Eq. 7 receptor grids and Eq. 10 occupancy from atoms, FP64, one thread per
 // grid point, atoms staged through LDS in order.
 #pragma clang fp contract(off)
@@ -1658,6 +1760,27 @@ hipError_t launch_reduce(hipStream_t st, const fftdg_partial *p, int64_t n_cfg_t
                          double c0, double *B, LigRed *res) {
     hipLaunchKernelGGL(k_reduce, dim3(n_lig), dim3(NT), 0, st, p, n_cfg_total, n_snap, cfg_off, cfg_w, W, kT, h3,
                        c0, B, res);
+    return hipGetLastError();
+}
+
+hipError_t launch_grid_energies(hipStream_t st, int precision, const void *grids, int n_rec, double h,
+                                const double *origin, int n_atoms, const double *lq, const double *ls,
+                                const double *le, int n_poses, const double *pose, double *out) {
+    if (precision == FFTDG_F64)
+        hipLaunchKernelGGL((k_grid_energies<double>), dim3(n_poses), dim3(NT), 0, st, (const double *)grids, n_rec, h,
+                           origin[0], origin[1], origin[2], n_atoms, lq, ls, le, pose, out);
+    else
+        hipLaunchKernelGGL((k_grid_energies<float>), dim3(n_poses), dim3(NT), 0, st, (const float *)grids, n_rec, h,
+                           origin[0], origin[1], origin[2], n_atoms, lq, ls, le, pose, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_pair_energies(hipStream_t st, int n_rec_atoms, const double *rxyz, const double *rq,
+                                const double *rs, const double *re, int n_atoms, const double *lq,
+                                const double *ls, const double *le, int n_poses, const double *pose, int excl,
+                                double *out) {
+    hipLaunchKernelGGL(k_pair_energies, dim3(n_poses), dim3(NT), 0, st, n_rec_atoms, rxyz, rq, rs, re, n_atoms, lq,
+                       ls, le, pose, excl, out);
     return hipGetLastError();
 }
 
