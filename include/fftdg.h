@@ -60,7 +60,10 @@ typedef struct fftdg_ctx fftdg_ctx;
 /* Grid description (FFT-based BPMF estimation section).
  *   n_rec  receptor grid edge in points (the ligand box must fit inside)
  *   n_fft  FFT edge, n_fft >= n_rec; receptor grids are zero-padded to it.
- *          Supported: 32, 64, 128 (FFTDG_F32); 32, 64 (FFTDG_F64).
+ *          Supported: 32, 64, 128, 256 (FFTDG_F32); 32, 64 (FFTDG_F64).
+ *          At 256 (a 62 A grid at 0.25 A) the xy transforms run as
+ *          separate row and column passes over planes in device memory,
+ *          and energy_xy_direct = 1 is not available.
  *          In FFTDG_OCC mode choose n_fft >= n_rec + occupancy radius so
  *          that the periodic wrap only meets padding.
  *   h      grid spacing (A), origin position of point (0,0,0) (A)

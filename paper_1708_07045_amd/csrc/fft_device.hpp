@@ -25,6 +25,7 @@ template <int N> struct Shape;
 template <> struct Shape<32> { static constexpr int R1 = 4, R2 = 8; };
 template <> struct Shape<64> { static constexpr int R1 = 8, R2 = 8; };
 template <> struct Shape<128> { static constexpr int R1 = 8, R2 = 16; };
+template <> struct Shape<256> { static constexpr int R1 = 16, R2 = 16; };
 
 // cos(2 pi k / 16)
 __host__ __device__ constexpr double cos16(int k) {

@@ -655,7 +655,7 @@ int fftdg_create(fftdg_ctx **out, const fftdg_grid_desc *g, int device, void *hi
     if (g->precision != FFTDG_F32 && g->precision != FFTDG_F64) return fail(FFTDG_E_INVALID, "precision must be FFTDG_F32 or FFTDG_F64");
     if (g->clash_mode != FFTDG_OCC && g->clash_mode != FFTDG_CAP) return fail(FFTDG_E_INVALID, "clash_mode must be FFTDG_OCC or FFTDG_CAP");
     const KernelSet *ks = kernel_set(g->precision, g->n_fft);
-    if (!ks) return fail(FFTDG_E_INVALID, "unsupported n_fft for this precision (F32: 32/64/128, F64: 32/64)");
+    if (!ks) return fail(FFTDG_E_INVALID, "unsupported n_fft for this precision (F32: 32/64/128/256, F64: 32/64)");
     if (g->n_rec < 4 || g->n_rec > g->n_fft) return fail(FFTDG_E_INVALID, "need 4 <= n_rec <= n_fft");
     if (!(g->h > 0.0) || !is_fin(g->h)) return fail(FFTDG_E_INVALID, "h must be finite and > 0");
     for (int d = 0; d < 3; ++d)
@@ -959,6 +959,8 @@ int fftdg_set_tuning(fftdg_ctx *ctx, const fftdg_tuning *t) {
     if (t->configs_per_chunk < 1) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: configs_per_chunk must be >= 1");
     if (t->energy_xy_direct < 0 || t->energy_xy_direct > 2)
         return set_err(ctx, FFTDG_E_INVALID, "set_tuning: energy_xy_direct must be 0, 1 or 2");
+    if (t->energy_xy_direct == 1 && ctx->g.n_fft > 128)
+        return set_err(ctx, FFTDG_E_INVALID, "set_tuning: energy_xy_direct = 1 needs n_fft <= 128");
     if (t->snapshots_per_pass < 1) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: snapshots_per_pass must be >= 1");
     ctx->chunk_cfgs = t->configs_per_chunk;
     ctx->edirect = t->energy_xy_direct;
@@ -1046,7 +1048,8 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
     for (int chunk : {64, 128, 256, 512})
         for (int ed : {0, 1, 2})
             for (int sp : passes)
-                for (int gr : {0, 1}) cand.push_back(fftdg_tuning{chunk, ed, sp, gr});
+                for (int gr : {0, 1})
+                    if (ed != 1 || ctx->g.n_fft <= 128) cand.push_back(fftdg_tuning{chunk, ed, sp, gr});
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(ctx, hipEventCreate(&e0));
     HIPCHK(ctx, hipEventCreate(&e1));

@@ -43,7 +43,7 @@ struct Geo {
     // consecutive columns; 2*S = 8 (mod 64) words staggers successive rows
     // by 8 banks so every bank is hit exactly twice by a wavefront's 512 B
     // (two cycles, the minimum).
-    static constexpr int S = N == 128 ? 68 : (N == 64 ? 36 : 24);
+    static constexpr int S = N == 256 ? 132 : (N == 128 ? 68 : (N == 64 ? 36 : 24));
     // pad (complex elements per block of R2) of the row-pair exchanges,
     // moving the lanes of a unit onto distinct bank pairs; the exchange of
     // rows r, r+1 then spans N + (R1-1)*RPAD <= 2*S elements
@@ -420,14 +420,14 @@ __host__ __device__ constexpr int de_atoms() {
     return (N * Geo<float, N>::S) / (N / 2 + 1 + N) < 32 ? (N * Geo<float, N>::S) / (N / 2 + 1 + N) : 32;
 }
 
-template <typename T, int N>
+// tab holds DE_A * (N/2 + 1 + N) complex values.
+template <typename T, int N, int DE_A>
 __device__ void energy_plane_direct(const CfgDev &c, int p, const int32_t *__restrict__ ulat,
                                     const T *__restrict__ gam, const typename Cx<T>::t *tw,
                                     typename Cx<T>::t *tab, typename Cx<T>::t *__restrict__ ws) {
     using C2 = typename Cx<T>::t;
     constexpr int H = N / 2 + 1, NP = N * H;
-    constexpr int DE_A = de_atoms<N>();
-    static_assert(DE_A >= 1 && DE_A * (H + N) <= N * Geo<T, N>::S, "per-atom tables must fit the plane buffer");
+    static_assert(DE_A >= 1, "at least one atom per pass");
     __shared__ T wgt[DE_A][3];
     __shared__ int2 axy[DE_A];
     __shared__ T fxy[DE_A][2];
@@ -511,6 +511,54 @@ __device__ void energy_plane_direct(const CfgDev &c, int p, const int32_t *__res
     }
 }
 
+// Atoms of one configuration that touch plane zt of a channel, compacted in
+// atom order by the first wavefront: energy channel ch -> (ax, ay, fx, fy,
+// gamma_ch * z weight); occupancy -> lattice x, y and the squared radius left
+// after the z offset.  nl receives the count.
+template <typename T>
+__device__ void gather_plane_atoms(const CfgDev &c, bool occ, int zt, int ch, const int32_t *__restrict__ ulat,
+                                   const T *__restrict__ gam, const double *__restrict__ thr, EAtom<T> *Le,
+                                   OAtom *Lo, int &nl) {
+    if (threadIdx.x < 64) {
+        const int lane = threadIdx.x;
+        int base = 0;
+        for (int a0 = 0; a0 < c.n_atoms; a0 += 64) {
+            const int a = a0 + lane;
+            bool take = false;
+            EAtom<T> ea{};
+            OAtom oa{};
+            if (a < c.n_atoms) {
+                const int32_t *U = ulat + 3 * (c.u_base + a);
+                if (!occ) {
+                    const int az = U[2] >> 16;
+                    const T fz = (T)(U[2] & 0xffff) * (T)(1.0 / 65536.0);
+                    take = (az == zt) || (az + 1 == zt);
+                    const T wz = (az == zt) ? (T)1 - fz : fz;
+                    ea.ax = U[0] >> 16;
+                    ea.ay = U[1] >> 16;
+                    ea.fx = (T)(U[0] & 0xffff) * (T)(1.0 / 65536.0);
+                    ea.fy = (T)(U[1] & 0xffff) * (T)(1.0 / 65536.0);
+                    ea.w = gam[3 * (c.atom_base + a) + ch] * wz;
+                } else {
+                    const long long dz = (long long)zt * 65536LL - U[2];
+                    const long long remz = (long long)thr[c.atom_base + a] - dz * dz;
+                    take = remz > 0;
+                    oa.Ux = U[0];
+                    oa.Uy = U[1];
+                    oa.remz = remz;
+                }
+            }
+            const unsigned long long m = __ballot(take);
+            const int pos = base + __popcll(m & ((1ULL << lane) - 1ULL));
+            if (take) {
+                if (!occ) Le[pos] = ea; else Lo[pos] = oa;
+            }
+            base += __popcll(m);
+        }
+        if (lane == 0) nl = base;
+    }
+}
+
 template <typename T, int N, bool EDF>
 __global__ __launch_bounds__(NT) void k_lig_fwd_xy(const int32_t *__restrict__ fwd_off, int n_cfg,
                                                     const CfgDev *__restrict__ cfgs,
@@ -535,7 +583,9 @@ __global__ __launch_bounds__(NT) void k_lig_fwd_xy(const int32_t *__restrict__ f
     if constexpr (EDF) {
         if (item < c.Le) {  // block-uniform: the whole block takes this path
             __syncthreads();
-            energy_plane_direct<T, N>(c, item, ulat, gam, tw, Pl, ws);
+            constexpr int DEA = de_atoms<N>();
+            static_assert(DEA * (N / 2 + 1 + N) <= N * G::S, "per-atom tables must fit the plane buffer");
+            energy_plane_direct<T, N, DEA>(c, item, ulat, gam, tw, Pl, ws);
             return;
         }
     }
@@ -549,44 +599,7 @@ __global__ __launch_bounds__(NT) void k_lig_fwd_xy(const int32_t *__restrict__ f
     const int zt = (occ ? c.zo0 : c.ze0) + it.p;
     const int y0 = occ ? c.yo0 : c.ye0;
     const int Ly = occ ? c.Lyo : c.Lye;
-    if (threadIdx.x < 64) {
-        const int lane = threadIdx.x;
-        int base = 0;
-        for (int a0 = 0; a0 < c.n_atoms; a0 += 64) {
-            const int a = a0 + lane;
-            bool take = false;
-            EAtom<T> ea{};
-            OAtom oa{};
-            if (a < c.n_atoms) {
-                const int32_t *U = ulat + 3 * (c.u_base + a);
-                if (!occ) {
-                    const int az = U[2] >> 16;
-                    const T fz = (T)(U[2] & 0xffff) * (T)(1.0 / 65536.0);
-                    take = (az == zt) || (az + 1 == zt);
-                    const T wz = (az == zt) ? (T)1 - fz : fz;
-                    ea.ax = U[0] >> 16;
-                    ea.ay = U[1] >> 16;
-                    ea.fx = (T)(U[0] & 0xffff) * (T)(1.0 / 65536.0);
-                    ea.fy = (T)(U[1] & 0xffff) * (T)(1.0 / 65536.0);
-                    ea.w = gam[3 * (c.atom_base + a) + it.ch] * wz;
-                } else {
-                    const long long dz = (long long)zt * 65536LL - U[2];
-                    const long long remz = (long long)thr[c.atom_base + a] - dz * dz;
-                    take = remz > 0;
-                    oa.Ux = U[0];
-                    oa.Uy = U[1];
-                    oa.remz = remz;
-                }
-            }
-            const unsigned long long m = __ballot(take);
-            const int pos = base + __popcll(m & ((1ULL << lane) - 1ULL));
-            if (take) {
-                if (!occ) L.e[pos] = ea; else L.o[pos] = oa;
-            }
-            base += __popcll(m);
-        }
-        if (lane == 0) nl = base;
-    }
+    gather_plane_atoms<T>(c, occ, zt, it.ch, ulat, gam, thr, L.e, L.o, nl);
     __syncthreads();
     C2 *out = ws + c.off_fwd + (int64_t)slot * G::NP;
     if (occ) {
@@ -660,6 +673,210 @@ __global__ __launch_bounds__(NT) void k_rec_z(const typename Cx<T>::t *__restric
                 rspec[((int64_t)ch * N + k) * G::NP + pen] = C2{re[i * R1 + k1], im[i * R1 + k1]};
             }
     }
+}
+
+// ------------------------------------------------ split-plane xy transforms
+// For an FFT size whose half plane does not fit in LDS (N = 256: a 256 x 129
+// complex plane is 264 KB), the xy transforms run as separate passes over
+// planes in global memory.  Each FFT unit (R1 lanes) owns a private LDS
+// exchange region.  The column passes work in place: a unit reads its whole
+// column into registers before it writes the column back.
+template <typename T, int N>
+struct Split {
+    static constexpr int R1 = Shape<N>::R1, R2 = Shape<N>::R2, M = R2 / R1;
+    static constexpr int H = N / 2 + 1, NP = N * H, U = NT / R1;
+    static constexpr int XPAD = 1;                // pad per block of R2 in a region
+    static constexpr int XREG = N + R1 * XPAD;    // complex per unit region
+    __device__ static int rg(int k) { return k + (k / R2) * XPAD; }
+};
+
+// Row pass of a forward plane: x transform (R2C) of the rows r in [0, Ly)
+// that a fill produces, as packed row pairs; the half spectrum of spatial row
+// y0 + r is written to row (y0 + r) mod N of `plane` ([N][H]).  Other rows
+// are not written (the column pass reads them as zero).
+template <typename T, int N, class Fill>
+__device__ void rows_fwd(const Fill &fill, int y0, int Ly, typename Cx<T>::t *reg_all,
+                         const typename Cx<T>::t *tw, typename Cx<T>::t *__restrict__ plane) {
+    using C2 = typename Cx<T>::t;
+    using SG = Split<T, N>;
+    constexpr int R1 = SG::R1, R2 = SG::R2, M = SG::M, U = SG::U, H = SG::H;
+    const int unit = threadIdx.x / R1, n1 = threadIdx.x % R1;
+    C2 *reg = reg_all + unit * SG::XREG;
+    const int npairs = (Ly + 1) / 2;
+    for (int rd = 0; rd < (npairs + U - 1) / U; ++rd) {
+        const int r = 2 * (unit + U * rd);
+        const bool inside = r < Ly;
+        const bool has_b = r + 1 < Ly;
+        const bool live = inside && fill.any(r);
+        T re[R2], im[R2];
+        if (live) {
+            fill.rows(r, n1, re, im, true, has_b);
+            fft_unit<T, N, false>(re, im, n1, reg, 1, tw, true, SG::XPAD);
+        }
+        wave_sync();
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < M; ++i)
+#pragma unroll
+                for (int k1 = 0; k1 < R1; ++k1)
+                    reg[SG::rg(spec_index<N>(n1, i, k1))] = C2{re[i * R1 + k1], im[i * R1 + k1]};
+        }
+        wave_sync();
+        if (inside) {
+            C2 *ra = plane + (int64_t)((y0 + r) & (N - 1)) * H;
+            C2 *rb = plane + (int64_t)((y0 + r + 1) & (N - 1)) * H;
+            for (int k = n1; k <= N / 2; k += R1) {
+                C2 A = C2{(T)0, (T)0}, B = C2{(T)0, (T)0};
+                if (live) {
+                    const C2 zk = reg[SG::rg(k)], zn = reg[SG::rg((N - k) & (N - 1))];
+                    A = C2{(T)0.5 * (zk.x + zn.x), (T)0.5 * (zk.y - zn.y)};
+                    B = C2{(T)0.5 * (zk.y + zn.y), (T)-0.5 * (zk.x - zn.x)};
+                }
+                ra[k] = A;
+                if (has_b) rb[k] = B;
+            }
+        }
+        wave_sync();  // the region is reused by the next round
+    }
+}
+
+// Column pass of a forward plane, in place: y transform (C2C) of every column
+// kx in [0, N/2]; input rows outside the window y0 .. y0+Ly-1 (mod N) are zero.
+template <typename T, int N>
+__device__ void cols_fwd(int y0, int Ly, typename Cx<T>::t *reg_all, const typename Cx<T>::t *tw,
+                         typename Cx<T>::t *__restrict__ plane) {
+    using C2 = typename Cx<T>::t;
+    using SG = Split<T, N>;
+    constexpr int R1 = SG::R1, R2 = SG::R2, M = SG::M, U = SG::U, H = SG::H;
+    const int unit = threadIdx.x / R1, n1 = threadIdx.x % R1;
+    C2 *reg = reg_all + unit * SG::XREG;
+    for (int rd = 0; rd < (H + U - 1) / U; ++rd) {
+        const int col = unit + U * rd;
+        const bool live = col < H;
+        T re[R2], im[R2];
+#pragma unroll
+        for (int i = 0; i < R2; ++i) {
+            const int y = n1 + R1 * i;
+            re[i] = im[i] = (T)0;
+            if (live && ((y - y0) & (N - 1)) < Ly) {
+                const C2 v = plane[(int64_t)y * H + col];
+                re[i] = v.x;
+                im[i] = v.y;
+            }
+        }
+        fft_unit<T, N, false>(re, im, n1, reg, 1, tw, live, SG::XPAD);
+        if (live) {
+#pragma unroll
+            for (int i = 0; i < M; ++i)
+#pragma unroll
+                for (int k1 = 0; k1 < R1; ++k1)
+                    plane[(int64_t)spec_index<N>(n1, i, k1) * H + col] = C2{re[i * R1 + k1], im[i * R1 + k1]};
+        }
+        wave_sync();
+    }
+}
+
+// Ligand forward planes, row pass (one block per forward item, as
+// k_lig_fwd_xy).  With EDF the energy items are evaluated directly here
+// (final planes; the column pass skips them).
+template <typename T, int N, bool EDF>
+__global__ __launch_bounds__(NT) void k_fwd_rows(const int32_t *__restrict__ fwd_off, int n_cfg,
+                                                  const CfgDev *__restrict__ cfgs, const int32_t *__restrict__ ulat,
+                                                  const T *__restrict__ gam, const double *__restrict__ thr,
+                                                  const typename Cx<T>::t *__restrict__ twg,
+                                                  typename Cx<T>::t *__restrict__ ws) {
+    using C2 = typename Cx<T>::t;
+    using SG = Split<T, N>;
+    __shared__ C2 reg[SG::U * SG::XREG];
+    __shared__ C2 tw[N];
+    __shared__ union {
+        EAtom<T> e[MAXA];
+        OAtom o[MAXA];
+    } L;
+    __shared__ int nl;
+    const int ic = find_cfg(fwd_off, n_cfg, (int)blockIdx.x);
+    const CfgDev c = cfgs[ic];
+    const int item = (int)blockIdx.x - fwd_off[ic];
+    load_tw<T, N>(tw, twg);
+    if constexpr (EDF) {
+        if (item < c.Le) {
+            __syncthreads();
+            constexpr int DEA = (SG::U * SG::XREG) / (SG::H + N);
+            energy_plane_direct<T, N, DEA>(c, item, ulat, gam, tw, reg, ws);
+            return;
+        }
+    }
+    const int slot = EDF ? c.occ_slot0 + (item - c.Le) : item;
+    const bool occ = slot >= c.occ_slot0;
+    const int ch = occ ? 3 : slot / c.Le, p = occ ? slot - c.occ_slot0 : slot % c.Le;
+    const int zt = (occ ? c.zo0 : c.ze0) + p;
+    const int y0 = occ ? c.yo0 : c.ye0;
+    const int Ly = occ ? c.Lyo : c.Lye;
+    gather_plane_atoms<T>(c, occ, zt, ch, ulat, gam, thr, L.e, L.o, nl);
+    __syncthreads();
+    C2 *out = ws + c.off_fwd + (int64_t)slot * SG::NP;
+    if (occ) {
+        LigOccFill<T, N> f{L.o, nl, y0};
+        rows_fwd<T, N>(f, y0, Ly, reg, tw, out);
+    } else {
+        LigEnergyFill<T, N> f{L.e, nl, y0};
+        rows_fwd<T, N>(f, y0, Ly, reg, tw, out);
+    }
+}
+
+template <typename T, int N, bool EDF>
+__global__ __launch_bounds__(NT) void k_fwd_cols(const int32_t *__restrict__ fwd_off, int n_cfg,
+                                                  const CfgDev *__restrict__ cfgs,
+                                                  const typename Cx<T>::t *__restrict__ twg,
+                                                  typename Cx<T>::t *__restrict__ ws) {
+    using C2 = typename Cx<T>::t;
+    using SG = Split<T, N>;
+    __shared__ C2 reg[SG::U * SG::XREG];
+    __shared__ C2 tw[N];
+    const int ic = find_cfg(fwd_off, n_cfg, (int)blockIdx.x);
+    const CfgDev c = cfgs[ic];
+    const int item = (int)blockIdx.x - fwd_off[ic];
+    if (EDF && item < c.Le) return;  // written whole by the row pass
+    load_tw<T, N>(tw, twg);
+    __syncthreads();
+    const int slot = EDF ? c.occ_slot0 + (item - c.Le) : item;
+    const bool occ = slot >= c.occ_slot0;
+    cols_fwd<T, N>(occ ? c.yo0 : c.ye0, occ ? c.Lyo : c.Lye, reg, tw, ws + c.off_fwd + (int64_t)slot * SG::NP);
+}
+
+// Receptor planes: row pass and in-place column pass; block -> (channel, z).
+template <typename T, int N>
+__global__ __launch_bounds__(NT) void k_rec_rows(const T *__restrict__ grids, const uint8_t *__restrict__ occ,
+                                                  int n_rec, const typename Cx<T>::t *__restrict__ twg,
+                                                  typename Cx<T>::t *__restrict__ rxy) {
+    using C2 = typename Cx<T>::t;
+    using SG = Split<T, N>;
+    __shared__ C2 reg[SG::U * SG::XREG];
+    __shared__ C2 tw[N];
+    load_tw<T, N>(tw, twg);
+    __syncthreads();
+    const int ch = blockIdx.x / n_rec, z = blockIdx.x % n_rec;
+    const int64_t n2 = (int64_t)n_rec * n_rec;
+    C2 *out = rxy + ((int64_t)ch * n_rec + z) * SG::NP;
+    if (ch < 3) {
+        DenseFill<T, N, T> f{grids + (int64_t)ch * n2 * n_rec + z * n2, n_rec};
+        rows_fwd<T, N>(f, 0, n_rec, reg, tw, out);
+    } else {
+        DenseFill<T, N, uint8_t> f{occ + z * n2, n_rec};
+        rows_fwd<T, N>(f, 0, n_rec, reg, tw, out);
+    }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(NT) void k_rec_cols(int n_rec, const typename Cx<T>::t *__restrict__ twg,
+                                                  typename Cx<T>::t *__restrict__ rxy) {
+    using C2 = typename Cx<T>::t;
+    using SG = Split<T, N>;
+    __shared__ C2 reg[SG::U * SG::XREG];
+    __shared__ C2 tw[N];
+    load_tw<T, N>(tw, twg);
+    __syncthreads();
+    cols_fwd<T, N>(0, n_rec, reg, tw, rxy + (int64_t)blockIdx.x * SG::NP);
 }
 
 // Placed ligand atom as the fused energy transform uses it.
@@ -1356,6 +1573,178 @@ __global__ __launch_bounds__(NT) void k_reduce(const fftdg_partial *__restrict__
     }
 }
 
+// Split-plane inverse, column pass (one block per (configuration, valid z)):
+// inverse y transform of every column kx in [0, N/2] of the energy and
+// occupancy planes, rows y < Vy written back in place.
+template <typename T, int N, bool OCC>
+__global__ __launch_bounds__(NT) void k_inv_cols(const int32_t *__restrict__ inv_off, int n_cfg,
+                                                  const CfgDev *__restrict__ cfgs,
+                                                  typename Cx<T>::t *__restrict__ wsi,
+                                                  const typename Cx<T>::t *__restrict__ twg) {
+    using C2 = typename Cx<T>::t;
+    using SG = Split<T, N>;
+    constexpr int R1 = SG::R1, R2 = SG::R2, M = SG::M, U = SG::U, H = SG::H;
+    __shared__ C2 reg_all[SG::U * SG::XREG];
+    __shared__ C2 tw[N];
+    const int ic = find_cfg(inv_off, n_cfg, (int)blockIdx.x);
+    const CfgDev c = cfgs[ic];
+    const int Vy = c.V[1], Vz = c.V[2], tz = (int)blockIdx.x - inv_off[ic];
+    load_tw<T, N>(tw, twg);
+    __syncthreads();
+    const int unit = threadIdx.x / R1, n1 = threadIdx.x % R1;
+    C2 *reg = reg_all + unit * SG::XREG;
+    constexpr int NCH = OCC ? 2 : 1;
+    for (int och = 0; och < NCH; ++och) {
+        C2 *plane = wsi + c.off_inv + ((int64_t)och * Vz + tz) * SG::NP;
+        for (int rd = 0; rd < (H + U - 1) / U; ++rd) {
+            const int col = unit + U * rd;
+            const bool live = col < H;
+            T re[R2], im[R2];
+#pragma unroll
+            for (int i = 0; i < R2; ++i) {
+                re[i] = im[i] = (T)0;
+                if (live) {
+                    const C2 v = plane[(int64_t)(n1 + R1 * i) * H + col];
+                    re[i] = v.x;
+                    im[i] = v.y;
+                }
+            }
+            fft_unit<T, N, true>(re, im, n1, reg, 1, tw, live, SG::XPAD);
+            if (live) {
+#pragma unroll
+                for (int i = 0; i < M; ++i)
+#pragma unroll
+                    for (int k1 = 0; k1 < R1; ++k1) {
+                        const int y = spec_index<N>(n1, i, k1);
+                        if (y < Vy) plane[(int64_t)y * H + col] = C2{re[i * R1 + k1], im[i * R1 + k1]};
+                    }
+            }
+            wave_sync();
+        }
+    }
+}
+
+// Split-plane inverse, row pass: inverse x (C2R) of the row pairs y < Vy of
+// the planes left by k_inv_cols, clash bits from the occupancy plane, then
+// the energies and the max-shifted log-sum-exp partial of the plane (as
+// k_inv_xy_lse).
+template <typename T, int N, bool OCC>
+__global__ __launch_bounds__(NT) void k_inv_rows_lse(const int32_t *__restrict__ inv_off, int n_cfg,
+                                                      const CfgDev *__restrict__ cfgs,
+                                                      const typename Cx<T>::t *__restrict__ wsi, T beta, T inv_n3,
+                                                      const typename Cx<T>::t *__restrict__ twg,
+                                                      PlanePartial<T> *__restrict__ pp, T *__restrict__ psi_out,
+                                                      uint8_t *__restrict__ clash_out,
+                                                      unsigned int *__restrict__ e_count) {
+    using C2 = typename Cx<T>::t;
+    using SG = Split<T, N>;
+    constexpr int R1 = SG::R1, R2 = SG::R2, M = SG::M, U = SG::U, H = SG::H;
+    __shared__ C2 reg_all[SG::U * SG::XREG];
+    __shared__ C2 tw[N];
+    __shared__ uint32_t cmask[(N * N + 31) / 32];
+    __shared__ LseAcc<T> red[NT];
+    const int ic = find_cfg(inv_off, n_cfg, (int)blockIdx.x);
+    const CfgDev c = cfgs[ic];
+    const int Vx = c.V[0], Vy = c.V[1], Vz = c.V[2], tz = (int)blockIdx.x - inv_off[ic];
+    load_tw<T, N>(tw, twg);
+    for (int i = threadIdx.x; i < (N * N + 31) / 32; i += NT) cmask[i] = 0u;
+    const int unit = threadIdx.x / R1, n1 = threadIdx.x % R1;
+    C2 *reg = reg_all + unit * SG::XREG;
+    LseAcc<T> acc;
+    acc.init();
+    constexpr int NCH = OCC ? 2 : 1;
+    for (int pass = 0; pass < NCH; ++pass) {
+        const int och = OCC ? 1 - pass : 0;  // occupancy first
+        const C2 *src = wsi + c.off_inv + ((int64_t)och * Vz + tz) * SG::NP;
+        __syncthreads();
+        if (OCC && och == 0 && !psi_out) {
+            int free_local = 0;
+            for (int e = threadIdx.x; e < Vy * Vx; e += NT) free_local |= !((cmask[e >> 5] >> (e & 31)) & 1u);
+            if (!__syncthreads_or(free_local)) break;
+        }
+        if (och == 0 && threadIdx.x == 0 && e_count) atomicAdd(e_count, 1u);
+        const int npairs = (Vy + 1) / 2;
+        for (int rd = 0; rd < (npairs + U - 1) / U; ++rd) {
+            const int y = 2 * (unit + U * rd);
+            const bool live = y < Vy;
+            const bool has_b = y + 1 < Vy;
+            const C2 *ra = src + (int64_t)(live ? y : 0) * H;
+            const C2 *rb = src + (int64_t)(has_b ? y + 1 : 0) * H;
+            T re[R2], im[R2];
+#pragma unroll
+            for (int i = 0; i < R2; ++i) {
+                const int k = n1 + R1 * i;
+                re[i] = im[i] = (T)0;
+                if (live) {
+                    C2 a, bq = C2{(T)0, (T)0};
+                    if (k <= N / 2) {
+                        a = ra[k];
+                        if (has_b) bq = rb[k];
+                        if (k == 0 || k == N / 2) {
+                            a.y = (T)0;
+                            bq.y = (T)0;
+                        }
+                    } else {
+                        a = ra[N - k];
+                        if (has_b) bq = rb[N - k];
+                        a.y = -a.y;
+                        bq.y = -bq.y;
+                    }
+                    re[i] = a.x - bq.y;
+                    im[i] = a.y + bq.x;
+                }
+            }
+            fft_unit<T, N, true>(re, im, n1, reg, 1, tw, live, SG::XPAD);
+            if (live) {
+#pragma unroll
+                for (int i = 0; i < M; ++i)
+#pragma unroll
+                    for (int k1 = 0; k1 < R1; ++k1) {
+                        const int x = spec_index<N>(n1, i, k1);
+                        if (x >= Vx) continue;
+#pragma unroll
+                        for (int hh = 0; hh < 2; ++hh) {
+                            const int yy = y + hh;
+                            if (yy >= Vy) continue;
+                            const T v = (hh ? im[i * R1 + k1] : re[i * R1 + k1]) * inv_n3;
+                            const int bit = yy * Vx + x;
+                            if (OCC && och == 1) {
+                                if (v >= (T)0.5) atomicOr(&cmask[bit >> 5], 1u << (bit & 31));
+                            } else {
+                                const int lin = (tz * Vy + yy) * Vx + x;
+                                const bool cl = OCC ? ((cmask[bit >> 5] >> (bit & 31)) & 1u) : false;
+                                if (psi_out) psi_out[lin] = v;
+                                if (clash_out) clash_out[lin] = cl ? 1 : 0;
+                                if (!cl) acc.add(-beta * v, v, lin);
+                            }
+                        }
+                    }
+            }
+            wave_sync();
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int w = NT / 2; w > 0; w >>= 1) {
+        if (threadIdx.x < w) {
+            LseAcc<T> a = red[threadIdx.x];
+            a.merge(red[threadIdx.x + w]);
+            red[threadIdx.x] = a;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        const LseAcc<T> a = red[0];
+        PlanePartial<T> o;
+        o.m = a.m;
+        o.s = a.s;
+        o.psi_min = a.pmin;
+        o.n_finite = a.n;
+        o.argmin = a.amin;
+        pp[c.pp_base + tz] = o;
+    }
+}
+
 // Per-configuration descriptors of a finished scan (inputs of the learned
 // proposal), one block per ligand, FP64:
 //   x_c   = ln sum_s W_s Z_{c,s}            (Eq. 2 numerator of one configuration)
@@ -1727,6 +2116,76 @@ struct Launch {
     }
 };
 
+// Launch sequences for FFT sizes whose planes do not fit in LDS.
+template <typename T, int N>
+struct LaunchSplit {
+    using C2 = typename Cx<T>::t;
+    using G = Geo<T, N>;
+    static hipError_t rec_spectra(hipStream_t st, const void *grids, const uint8_t *occ, int n_rec, int n_ch,
+                                  const void *tw, void *rxy, void *rspec) {
+        hipLaunchKernelGGL((k_rec_rows<T, N>), dim3(n_ch * n_rec), dim3(NT), 0, st, (const T *)grids, occ, n_rec,
+                           (const C2 *)tw, (C2 *)rxy);
+        hipLaunchKernelGGL((k_rec_cols<T, N>), dim3(n_ch * n_rec), dim3(NT), 0, st, n_rec, (const C2 *)tw, (C2 *)rxy);
+        const int n_tiles = (G::NP + G::U - 1) / G::U;
+        hipLaunchKernelGGL((k_rec_z<T, N>), dim3(n_ch * n_tiles), dim3(NT), 0, st, (const C2 *)rxy, n_rec, n_tiles,
+                           (const C2 *)tw, (C2 *)rspec);
+        return hipGetLastError();
+    }
+    static hipError_t fwd(hipStream_t st, bool edf, const int32_t *fwd_off, int n_cfg, int n_items,
+                          const CfgDev *cfgs, const int32_t *ulat, const void *gam, const double *thr,
+                          const void *tw, void *ws) {
+        if (n_items <= 0) return hipSuccess;
+        if (edf) {
+            hipLaunchKernelGGL((k_fwd_rows<T, N, true>), dim3(n_items), dim3(NT), 0, st, fwd_off, n_cfg, cfgs, ulat,
+                               (const T *)gam, thr, (const C2 *)tw, (C2 *)ws);
+            hipLaunchKernelGGL((k_fwd_cols<T, N, true>), dim3(n_items), dim3(NT), 0, st, fwd_off, n_cfg, cfgs,
+                               (const C2 *)tw, (C2 *)ws);
+        } else {
+            hipLaunchKernelGGL((k_fwd_rows<T, N, false>), dim3(n_items), dim3(NT), 0, st, fwd_off, n_cfg, cfgs, ulat,
+                               (const T *)gam, thr, (const C2 *)tw, (C2 *)ws);
+            hipLaunchKernelGGL((k_fwd_cols<T, N, false>), dim3(n_items), dim3(NT), 0, st, fwd_off, n_cfg, cfgs,
+                               (const C2 *)tw, (C2 *)ws);
+        }
+        return hipGetLastError();
+    }
+    static hipError_t inv(hipStream_t st, bool occ, const int32_t *inv_off, int n_cfg, int n_items,
+                          const CfgDev *cfgs, const void *wsi, double beta, const void *tw, void *pp, void *psi_out,
+                          uint8_t *clash_out, unsigned int *e_count) {
+        if (n_items <= 0) return hipSuccess;
+        const T b = (T)beta, s = (T)(1.0 / ((double)N * N * N));
+        if (occ) {
+            hipLaunchKernelGGL((k_inv_cols<T, N, true>), dim3(n_items), dim3(NT), 0, st, inv_off, n_cfg, cfgs,
+                               (C2 *)wsi, (const C2 *)tw);
+            hipLaunchKernelGGL((k_inv_rows_lse<T, N, true>), dim3(n_items), dim3(NT), 0, st, inv_off, n_cfg, cfgs,
+                               (const C2 *)wsi, b, s, (const C2 *)tw, (PlanePartial<T> *)pp, (T *)psi_out, clash_out,
+                               e_count);
+        } else {
+            hipLaunchKernelGGL((k_inv_cols<T, N, false>), dim3(n_items), dim3(NT), 0, st, inv_off, n_cfg, cfgs,
+                               (C2 *)wsi, (const C2 *)tw);
+            hipLaunchKernelGGL((k_inv_rows_lse<T, N, false>), dim3(n_items), dim3(NT), 0, st, inv_off, n_cfg, cfgs,
+                               (const C2 *)wsi, b, s, (const C2 *)tw, (PlanePartial<T> *)pp, (T *)psi_out, clash_out,
+                               e_count);
+        }
+        return hipGetLastError();
+    }
+};
+
+template <typename T, int N>
+static const KernelSet *make_split_set() {
+    static const KernelSet s = {
+        N,
+        (int)sizeof(typename Cx<T>::t),
+        (int)sizeof(PlanePartial<T>),
+        Geo<T, N>::NP,
+        LaunchSplit<T, N>::rec_spectra,
+        LaunchSplit<T, N>::fwd,
+        Launch<T, N>::zprod,
+        LaunchSplit<T, N>::inv,
+        Launch<T, N>::merge,
+    };
+    return &s;
+}
+
 template <typename T, int N>
 static const KernelSet *make_set() {
     static const KernelSet s = {
@@ -1748,6 +2207,7 @@ const KernelSet *kernel_set(int precision, int n_fft) {
         if (n_fft == 32) return make_set<float, 32>();
         if (n_fft == 64) return make_set<float, 64>();
         if (n_fft == 128) return make_set<float, 128>();
+        if (n_fft == 256) return make_split_set<float, 256>();
     } else if (precision == FFTDG_F64) {
         if (n_fft == 32) return make_set<double, 32>();
         if (n_fft == 64) return make_set<double, 64>();

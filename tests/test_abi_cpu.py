@@ -46,7 +46,9 @@ def _desc(**kw):
 
 @pytest.mark.parametrize("kw", [
     dict(n_fft=96),                      # unsupported FFT edge
-    dict(n_fft=256),                     # 256 is not built
+    dict(n_fft=512),                     # beyond the largest built size
+    dict(precision=fd.F64, n_fft=256),   # 256 is FP32 only
+    dict(n_rec=300, n_fft=256),          # n_rec > n_fft
     dict(precision=fd.F64, n_fft=128),   # FP64 limited to 32/64
     dict(n_rec=200),                     # n_rec > n_fft
     dict(n_rec=2),
@@ -64,6 +66,15 @@ def test_create_rejects_bad_descriptions(kw):
     g = _desc(**kw)
     assert L.fftdg_create(ctypes.byref(h), ctypes.byref(g), 0, None) == fd._lib.E_INVALID
     assert not h.value
+
+
+def test_grid_tools_reject_bad_arguments_without_a_device():
+    L = fd.load()
+    g = _desc(n_rec=1)
+    assert L.fftdg_grids_build(0, None, ctypes.byref(g), 10, None, None, None, None, None, None) == fd._lib.E_INVALID
+    assert L.fftdg_grid_energies(0, None, None, None, 1, 1, None, None, None, None, None) == fd._lib.E_INVALID
+    assert L.fftdg_pair_energies(0, None, 0, None, None, None, None, 1, 1, None, None, None, None, 0,
+                                 None) == fd._lib.E_INVALID
 
 
 def test_create_null_arguments():
