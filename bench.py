@@ -286,9 +286,11 @@ def main():
     ap.add_argument("--chunk", type=int, default=0, help="configurations per chunk (0 = library default)")
     ap.add_argument("--energy-direct", type=int, default=-1, help="energy xy transforms: 0 FFT pass, 1 in the z kernel, 2 direct in the forward pass (default: autotuned)")
     ap.add_argument("--snap-pass", type=int, default=0, help="snapshots per z pass (0 = library default)")
-    ap.add_argument("--workload", default="c2", choices=["c2", "c3"],
+    ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c6"],
                     help="c2: the 8000-configuration T4L-sized scan (the metric's workload); "
-                         "c3: 141 ligands x 10 receptor snapshots (batched)")
+                         "c3: 141 ligands x 10 receptor snapshots (batched); "
+                         "c6: the c2 ligand on the 62 A whole-surface grid (248^3 in a 256^3 FFT)")
+    ap.add_argument("--n-rot", type=int, default=125, help="c6 only: rotations per conformer (8 conformers)")
     ap.add_argument("--cfg-scale", type=float, default=0.1, help="c3 only: scale of the 200-2000 configurations per ligand")
     ap.add_argument("--no-autotune", action="store_true", help="skip the schedule autotuner (setup, untimed)")
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
@@ -321,7 +323,12 @@ def main():
                           "configs_needed": {k: v for k, v in cn.items() if k != "per_ligand"}}), flush=True)
         return
 
-    w = synth.config2() if args.workload == "c2" else synth.config3(cfg_scale=args.cfg_scale)
+    if args.workload == "c2":
+        w = synth.config2()
+    elif args.workload == "c3":
+        w = synth.config3(cfg_scale=args.cfg_scale)
+    else:
+        w = synth.config6(n_rot=args.n_rot)
     n_snap = w.receptor.n_snap
     log(f"workload: {w.name}; {len(w.ligands)} ligands, {w.n_cfg_total} configurations, {n_snap} snapshots")
     ctx = fd.FFTDG.from_workload(w)
@@ -417,7 +424,9 @@ def main():
                    if args.workload == "c2" else
                    (f"batched: {len(w.ligands)} ligands of 8-40 atoms, {n_cfg} configurations "
                     f"(200-2000 per ligand x {args.cfg_scale}), {n_snap} jittered receptor snapshots, 128^3 FFT, "
-                    "occupancy clash mode, 300 K"),
+                    "occupancy clash mode, 300 K") if args.workload == "c3" else
+                   (f"whole-surface scan: 2600-atom cavity receptor, 248^3 grid @ 0.25 A (62 A) -> 256^3 FFT, "
+                    f"occupancy clash mode, 25-atom ligand x 8 conformers x {args.n_rot} rotations, 300 K"),
                    "n_cfg": n_cfg, "n_fft": w.n_fft, "n_rec": w.n_rec, "clash_mode": w.clash_mode,
                    "n_snap": n_snap, "parallelism": "single GPU", "tuning": ctx.get_tuning(),
                    "autotune": autotuned},
@@ -436,7 +445,8 @@ def main():
         "psi_min_kcal_mol": float(result["res"]["psi_min"][0]),
     }
     if args.workload != "c2":
-        rec["metric"] = METRIC + " [batched workload; not the headline line]"
+        rec["metric"] = METRIC + (" [batched workload; not the headline line]" if args.workload == "c3"
+                                  else " [whole-surface workload; not the headline line]")
         rec["dG_kcal_mol_per_ligand"] = [float(x) for x in result["res"]["dG"]]
         args.no_cpu_baseline = True
     if not args.no_cpu_baseline:

@@ -75,3 +75,60 @@ def test_n256_rejects_energy_mode_1():
     ctx = fd.FFTDG.from_workload(w)
     with pytest.raises(fd.FFTDGError):
         ctx.set_tuning(energy_xy_direct=1)
+
+
+def test_c6_full_size_sampled_against_oracle():
+    """Full whole-surface size (248^3 grid in a 256^3 FFT), in the schedule
+    the bench times (64 configurations per chunk, direct energy planes):
+    raw energies at 200 sampled valid translations against the oracle's
+    trilinear sums over Eq. 7 grid values evaluated at the needed nodes, and
+    clash bits at 200 sampled translations against the occupancy overlap
+    with the rasterised Eq. 10 receptor occupancy."""
+    import paper_1708_07045_amd as fd
+    from oracle import pairs
+    w = synth.config6(n_rot=2, n_conf=1)
+    ctx = _ctx(w, energy_xy_direct=2, configs_per_chunk=64)
+    b = fd.Batch(w.ligands)
+    L = w.ligands[0]
+    r = w.receptor
+    occ_r = pairs.occupancy_grid(r.xyz[0], r.sigma, w.occ_f, w.n_rec, w.h, w.origin)
+    gamma = oracle.ligand_weights(L)
+    thr = oracle.occ_thresholds(L, w.occ_f, w.h)
+    rng = np.random.default_rng(256)
+    for c in range(L.n_cfg):
+        print(f"c6 full-size cfg {c}", flush=True)
+        psi, clash = ctx.energy_grid(0, b, c, w.T)
+        psi, clash = psi.cpu().numpy().astype(np.float64), clash.cpu().numpy()
+        u, box = oracle.place_cfg(w, 0, c)
+        Vz, Vy, Vx = oracle.valid_shape(w, box)
+        assert psi.shape == (Vz, Vy, Vx)
+        # energies at sampled translations
+        ts = np.stack([rng.integers(0, V, 200) for V in (Vx, Vy, Vz)], axis=1)   # (tx, ty, tz)
+        fl = np.floor(u).astype(np.int64)
+        f = u - fl
+        nodes, wts = [], []
+        for dz in (0, 1):
+            for dy in (0, 1):
+                for dx in (0, 1):
+                    d = np.array([dx, dy, dz])
+                    nodes.append(fl[None, :, :] + d + ts[:, None, :])                   # [T][n][3]
+                    wts.append(np.prod(np.where(d == 1, f, 1 - f), axis=1))              # [n]
+        allnodes = np.concatenate([nd.reshape(-1, 3) for nd in nodes])
+        uniq, inv = np.unique(allnodes, axis=0, return_inverse=True)
+        gv = pairs.grid_values(r.xyz[0], r.q, r.sigma, r.eps, w.origin[None, :] + w.h * uniq)
+        gv = gv[inv.ravel()].reshape(8, ts.shape[0], L.n_atoms, 3)
+        ref = np.zeros(ts.shape[0])
+        for k in range(8):
+            ref += np.einsum("tic,ic,i->t", gv[k], gamma, wts[k])
+        got = psi[ts[:, 2], ts[:, 1], ts[:, 0]]
+        assert np.linalg.norm(got - ref) <= 1e-5 * np.linalg.norm(ref)
+        assert np.max(np.abs(got - ref)) <= 1e-5 * np.max(np.abs(ref))
+        # clash bits at sampled translations
+        pts = np.argwhere(oracle.occ_dense(w.n_fft, u, thr))[:, ::-1]                  # (x, y, z) mod N
+        N = w.n_fft
+        for t in ts[:200]:
+            q = (pts + t) % N
+            inside = np.all(q < w.n_rec, axis=1)
+            q = q[inside]
+            want = bool(np.any(occ_r[q[:, 2], q[:, 1], q[:, 0]]))
+            assert bool(clash[t[2], t[1], t[0]]) == want, t

@@ -59,3 +59,24 @@ def test_exclusion_is_inert_far_away():
     one = pairs.pair_energies([[0, 0, 0]], [0.5], [3.0], [0.0], [[[10.0, 0, 0]]], [-0.4], [3.0], [0.0])
     assert one[0, 0] == pytest.approx(332.05 * 0.5 * -0.4 / 10.0, rel=1e-15)
     assert one[0, 1] == 0.0 and one[0, 2] == 0.0
+
+
+def test_point_grid_values_equal_the_grid_builder():
+    w = _w()
+    g, o = oracle.receptor_grids(w)
+    n = w.n_rec
+    idx = np.random.default_rng(3).integers(0, n, (300, 3))   # (x, y, z)
+    pts = w.origin[None, :] + w.h * idx
+    r = w.receptor
+    v = pairs.grid_values(r.xyz[0], r.q, r.sigma, r.eps, pts)
+    want = np.stack([g[ch][idx[:, 2], idx[:, 1], idx[:, 0]] for ch in range(3)], axis=1)
+    np.testing.assert_allclose(v, want, rtol=1e-12, atol=1e-12)
+    occ = pairs.occupancy_values(r.xyz[0], r.sigma, w.occ_f, pts)
+    np.testing.assert_array_equal(occ, o[idx[:, 2], idx[:, 1], idx[:, 0]])
+
+
+def test_rasterised_occupancy_equals_the_grid_builder():
+    w = _w()
+    _, o = oracle.receptor_grids(w)
+    r = w.receptor
+    np.testing.assert_array_equal(pairs.occupancy_grid(r.xyz[0], r.sigma, w.occ_f, w.n_rec, w.h, w.origin), o)

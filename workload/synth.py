@@ -339,6 +339,18 @@ def config3(seed: int = ROOT_SEED, n_ligands: int = 141, n_snap: int = 10,
                     300.0, "f32", rec, ligs)
 
 
+def config6(seed: int = ROOT_SEED, n_rot: int = 1000, n_conf: int = 8) -> Workload:
+    """Whole-surface case: the config-2 receptor and ligand on a 62 A grid at
+    0.25 A (248 points) zero-padded to a 256^3 FFT, covering the entire
+    receptor surface (the paper's larger grid); occupancy mode, FP32."""
+    w = config2(seed, n_rot, n_conf)
+    n_rec, h = 248, 0.25
+    return Workload("c6: 2600-atom cavity receptor, 248^3 @ 0.25 A (62 A) -> 256^3 FFT, occ, "
+                    f"25-atom ligand x {n_conf} conf x {n_rot} rot, f32",
+                    n_rec, 256, h, _grid_origin(np.zeros(3), n_rec, h), "occ", 10.0, 0.5,
+                    300.0, "f32", w.receptor, w.ligands)
+
+
 def tiny(seed: int = 1, n_rec: int = 8, n_fft: Optional[int] = None, h: float = 1.0,
          n_rec_atoms: int = 6, n_lig_atoms: int = 2, n_cfg: int = 3,
          clash_mode: str = "occ", occ_f: float = 0.5, precision: str = "f64",
