@@ -740,39 +740,55 @@ __device__ void rows_fwd(const Fill &fill, int y0, int Ly, typename Cx<T>::t *re
     }
 }
 
-// Column pass of a forward plane, in place: y transform (C2C) of every column
-// kx in [0, N/2]; input rows outside the window y0 .. y0+Ly-1 (mod N) are zero.
+// Column pass over a tile of CT = U consecutive columns of a plane ([N][H]
+// in global memory), one column per FFT unit: the tile is staged through LDS
+// with coalesced row reads and writes, and each unit transforms its column
+// in place in the tile (the column doubles as its exchange area).  Forward:
+// rows outside the window y0 .. y0+Ly-1 (mod N) read as zero and all N rows
+// are written; inverse: every row is read and rows y < rows_out written.
 template <typename T, int N>
-__device__ void cols_fwd(int y0, int Ly, typename Cx<T>::t *reg_all, const typename Cx<T>::t *tw,
-                         typename Cx<T>::t *__restrict__ plane) {
+struct Tile {
+    static constexpr int CT = NT / Shape<N>::R1;  // columns per tile (one per unit)
+    static constexpr int TS = CT + 1;             // LDS row stride (complex)
+    static constexpr int NTILE = (N / 2 + 1 + CT - 1) / CT;
+};
+
+template <typename T, int N, bool INV>
+__device__ void cols_tile(typename Cx<T>::t *__restrict__ plane, int tile, int y0, int Ly, int rows_out,
+                          typename Cx<T>::t *tb, const typename Cx<T>::t *tw) {
     using C2 = typename Cx<T>::t;
-    using SG = Split<T, N>;
-    constexpr int R1 = SG::R1, R2 = SG::R2, M = SG::M, U = SG::U, H = SG::H;
+    constexpr int R1 = Shape<N>::R1, R2 = Shape<N>::R2, M = R2 / R1, H = N / 2 + 1;
+    constexpr int CT = Tile<T, N>::CT, TS = Tile<T, N>::TS;
+    const int c0 = tile * CT;
+    for (int e = threadIdx.x; e < N * CT; e += NT) {
+        const int row = e / CT, cc = e - row * CT, col = c0 + cc;
+        C2 v = C2{(T)0, (T)0};
+        if (col < H && (INV || ((row - y0) & (N - 1)) < Ly)) v = plane[(int64_t)row * H + col];
+        tb[row * TS + cc] = v;
+    }
+    __syncthreads();
     const int unit = threadIdx.x / R1, n1 = threadIdx.x % R1;
-    C2 *reg = reg_all + unit * SG::XREG;
-    for (int rd = 0; rd < (H + U - 1) / U; ++rd) {
-        const int col = unit + U * rd;
-        const bool live = col < H;
-        T re[R2], im[R2];
+    const bool live = c0 + unit < H;
+    C2 *colp = tb + unit;
+    T re[R2], im[R2];
 #pragma unroll
-        for (int i = 0; i < R2; ++i) {
-            const int y = n1 + R1 * i;
-            re[i] = im[i] = (T)0;
-            if (live && ((y - y0) & (N - 1)) < Ly) {
-                const C2 v = plane[(int64_t)y * H + col];
-                re[i] = v.x;
-                im[i] = v.y;
-            }
-        }
-        fft_unit<T, N, false>(re, im, n1, reg, 1, tw, live, SG::XPAD);
-        if (live) {
+    for (int i = 0; i < R2; ++i) {
+        const C2 v = colp[(n1 + R1 * i) * TS];
+        re[i] = v.x;
+        im[i] = v.y;
+    }
+    fft_unit<T, N, INV>(re, im, n1, colp, TS, tw, live);
+    wave_sync();  // the column is private to this unit
+    if (live) {
 #pragma unroll
-            for (int i = 0; i < M; ++i)
+        for (int i = 0; i < M; ++i)
 #pragma unroll
-                for (int k1 = 0; k1 < R1; ++k1)
-                    plane[(int64_t)spec_index<N>(n1, i, k1) * H + col] = C2{re[i * R1 + k1], im[i * R1 + k1]};
-        }
-        wave_sync();
+            for (int k1 = 0; k1 < R1; ++k1) colp[spec_index<N>(n1, i, k1) * TS] = C2{re[i * R1 + k1], im[i * R1 + k1]};
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < rows_out * CT; e += NT) {
+        const int row = e / CT, cc = e - row * CT, col = c0 + cc;
+        if (col < H) plane[(int64_t)row * H + col] = tb[row * TS + cc];
     }
 }
 
@@ -830,18 +846,19 @@ __global__ __launch_bounds__(NT) void k_fwd_cols(const int32_t *__restrict__ fwd
                                                   const typename Cx<T>::t *__restrict__ twg,
                                                   typename Cx<T>::t *__restrict__ ws) {
     using C2 = typename Cx<T>::t;
-    using SG = Split<T, N>;
-    __shared__ C2 reg[SG::U * SG::XREG];
+    using TL = Tile<T, N>;
+    __shared__ C2 tb[N * TL::TS];
     __shared__ C2 tw[N];
-    const int ic = find_cfg(fwd_off, n_cfg, (int)blockIdx.x);
+    const int bi = (int)blockIdx.x / TL::NTILE, tile = (int)blockIdx.x % TL::NTILE;
+    const int ic = find_cfg(fwd_off, n_cfg, bi);
     const CfgDev c = cfgs[ic];
-    const int item = (int)blockIdx.x - fwd_off[ic];
+    const int item = bi - fwd_off[ic];
     if (EDF && item < c.Le) return;  // written whole by the row pass
     load_tw<T, N>(tw, twg);
-    __syncthreads();
     const int slot = EDF ? c.occ_slot0 + (item - c.Le) : item;
     const bool occ = slot >= c.occ_slot0;
-    cols_fwd<T, N>(occ ? c.yo0 : c.ye0, occ ? c.Lyo : c.Lye, reg, tw, ws + c.off_fwd + (int64_t)slot * SG::NP);
+    cols_tile<T, N, false>(ws + c.off_fwd + (int64_t)slot * Geo<T, N>::NP, tile, occ ? c.yo0 : c.ye0,
+                           occ ? c.Lyo : c.Lye, N, tb, tw);
 }
 
 // Receptor planes: row pass and in-place column pass; block -> (channel, z).
@@ -871,12 +888,12 @@ template <typename T, int N>
 __global__ __launch_bounds__(NT) void k_rec_cols(int n_rec, const typename Cx<T>::t *__restrict__ twg,
                                                   typename Cx<T>::t *__restrict__ rxy) {
     using C2 = typename Cx<T>::t;
-    using SG = Split<T, N>;
-    __shared__ C2 reg[SG::U * SG::XREG];
+    using TL = Tile<T, N>;
+    __shared__ C2 tb[N * TL::TS];
     __shared__ C2 tw[N];
     load_tw<T, N>(tw, twg);
-    __syncthreads();
-    cols_fwd<T, N>(0, n_rec, reg, tw, rxy + (int64_t)blockIdx.x * SG::NP);
+    const int plane = (int)blockIdx.x / TL::NTILE, tile = (int)blockIdx.x % TL::NTILE;
+    cols_tile<T, N, false>(rxy + (int64_t)plane * Geo<T, N>::NP, tile, 0, n_rec, N, tb, tw);
 }
 
 // Placed ligand atom as the fused energy transform uses it.
@@ -1582,46 +1599,18 @@ __global__ __launch_bounds__(NT) void k_inv_cols(const int32_t *__restrict__ inv
                                                   typename Cx<T>::t *__restrict__ wsi,
                                                   const typename Cx<T>::t *__restrict__ twg) {
     using C2 = typename Cx<T>::t;
-    using SG = Split<T, N>;
-    constexpr int R1 = SG::R1, R2 = SG::R2, M = SG::M, U = SG::U, H = SG::H;
-    __shared__ C2 reg_all[SG::U * SG::XREG];
+    using TL = Tile<T, N>;
+    __shared__ C2 tb[N * TL::TS];
     __shared__ C2 tw[N];
-    const int ic = find_cfg(inv_off, n_cfg, (int)blockIdx.x);
-    const CfgDev c = cfgs[ic];
-    const int Vy = c.V[1], Vz = c.V[2], tz = (int)blockIdx.x - inv_off[ic];
-    load_tw<T, N>(tw, twg);
-    __syncthreads();
-    const int unit = threadIdx.x / R1, n1 = threadIdx.x % R1;
-    C2 *reg = reg_all + unit * SG::XREG;
     constexpr int NCH = OCC ? 2 : 1;
-    for (int och = 0; och < NCH; ++och) {
-        C2 *plane = wsi + c.off_inv + ((int64_t)och * Vz + tz) * SG::NP;
-        for (int rd = 0; rd < (H + U - 1) / U; ++rd) {
-            const int col = unit + U * rd;
-            const bool live = col < H;
-            T re[R2], im[R2];
-#pragma unroll
-            for (int i = 0; i < R2; ++i) {
-                re[i] = im[i] = (T)0;
-                if (live) {
-                    const C2 v = plane[(int64_t)(n1 + R1 * i) * H + col];
-                    re[i] = v.x;
-                    im[i] = v.y;
-                }
-            }
-            fft_unit<T, N, true>(re, im, n1, reg, 1, tw, live, SG::XPAD);
-            if (live) {
-#pragma unroll
-                for (int i = 0; i < M; ++i)
-#pragma unroll
-                    for (int k1 = 0; k1 < R1; ++k1) {
-                        const int y = spec_index<N>(n1, i, k1);
-                        if (y < Vy) plane[(int64_t)y * H + col] = C2{re[i * R1 + k1], im[i * R1 + k1]};
-                    }
-            }
-            wave_sync();
-        }
-    }
+    const int per = NCH * TL::NTILE;
+    const int bi = (int)blockIdx.x / per, rem = (int)blockIdx.x % per;
+    const int och = rem / TL::NTILE, tile = rem % TL::NTILE;
+    const int ic = find_cfg(inv_off, n_cfg, bi);
+    const CfgDev c = cfgs[ic];
+    const int Vy = c.V[1], Vz = c.V[2], tz = bi - inv_off[ic];
+    load_tw<T, N>(tw, twg);
+    cols_tile<T, N, true>(wsi + c.off_inv + ((int64_t)och * Vz + tz) * Geo<T, N>::NP, tile, 0, N, Vy, tb, tw);
 }
 
 // Split-plane inverse, row pass: inverse x (C2R) of the row pairs y < Vy of
@@ -2125,7 +2114,8 @@ struct LaunchSplit {
                                   const void *tw, void *rxy, void *rspec) {
         hipLaunchKernelGGL((k_rec_rows<T, N>), dim3(n_ch * n_rec), dim3(NT), 0, st, (const T *)grids, occ, n_rec,
                            (const C2 *)tw, (C2 *)rxy);
-        hipLaunchKernelGGL((k_rec_cols<T, N>), dim3(n_ch * n_rec), dim3(NT), 0, st, n_rec, (const C2 *)tw, (C2 *)rxy);
+        hipLaunchKernelGGL((k_rec_cols<T, N>), dim3(n_ch * n_rec * Tile<T, N>::NTILE), dim3(NT), 0, st, n_rec,
+                           (const C2 *)tw, (C2 *)rxy);
         const int n_tiles = (G::NP + G::U - 1) / G::U;
         hipLaunchKernelGGL((k_rec_z<T, N>), dim3(n_ch * n_tiles), dim3(NT), 0, st, (const C2 *)rxy, n_rec, n_tiles,
                            (const C2 *)tw, (C2 *)rspec);
@@ -2138,13 +2128,13 @@ struct LaunchSplit {
         if (edf) {
             hipLaunchKernelGGL((k_fwd_rows<T, N, true>), dim3(n_items), dim3(NT), 0, st, fwd_off, n_cfg, cfgs, ulat,
                                (const T *)gam, thr, (const C2 *)tw, (C2 *)ws);
-            hipLaunchKernelGGL((k_fwd_cols<T, N, true>), dim3(n_items), dim3(NT), 0, st, fwd_off, n_cfg, cfgs,
-                               (const C2 *)tw, (C2 *)ws);
+            hipLaunchKernelGGL((k_fwd_cols<T, N, true>), dim3(n_items * Tile<T, N>::NTILE), dim3(NT), 0, st, fwd_off,
+                               n_cfg, cfgs, (const C2 *)tw, (C2 *)ws);
         } else {
             hipLaunchKernelGGL((k_fwd_rows<T, N, false>), dim3(n_items), dim3(NT), 0, st, fwd_off, n_cfg, cfgs, ulat,
                                (const T *)gam, thr, (const C2 *)tw, (C2 *)ws);
-            hipLaunchKernelGGL((k_fwd_cols<T, N, false>), dim3(n_items), dim3(NT), 0, st, fwd_off, n_cfg, cfgs,
-                               (const C2 *)tw, (C2 *)ws);
+            hipLaunchKernelGGL((k_fwd_cols<T, N, false>), dim3(n_items * Tile<T, N>::NTILE), dim3(NT), 0, st, fwd_off,
+                               n_cfg, cfgs, (const C2 *)tw, (C2 *)ws);
         }
         return hipGetLastError();
     }
@@ -2154,14 +2144,14 @@ struct LaunchSplit {
         if (n_items <= 0) return hipSuccess;
         const T b = (T)beta, s = (T)(1.0 / ((double)N * N * N));
         if (occ) {
-            hipLaunchKernelGGL((k_inv_cols<T, N, true>), dim3(n_items), dim3(NT), 0, st, inv_off, n_cfg, cfgs,
-                               (C2 *)wsi, (const C2 *)tw);
+            hipLaunchKernelGGL((k_inv_cols<T, N, true>), dim3(n_items * 2 * Tile<T, N>::NTILE), dim3(NT), 0, st,
+                               inv_off, n_cfg, cfgs, (C2 *)wsi, (const C2 *)tw);
             hipLaunchKernelGGL((k_inv_rows_lse<T, N, true>), dim3(n_items), dim3(NT), 0, st, inv_off, n_cfg, cfgs,
                                (const C2 *)wsi, b, s, (const C2 *)tw, (PlanePartial<T> *)pp, (T *)psi_out, clash_out,
                                e_count);
         } else {
-            hipLaunchKernelGGL((k_inv_cols<T, N, false>), dim3(n_items), dim3(NT), 0, st, inv_off, n_cfg, cfgs,
-                               (C2 *)wsi, (const C2 *)tw);
+            hipLaunchKernelGGL((k_inv_cols<T, N, false>), dim3(n_items * Tile<T, N>::NTILE), dim3(NT), 0, st,
+                               inv_off, n_cfg, cfgs, (C2 *)wsi, (const C2 *)tw);
             hipLaunchKernelGGL((k_inv_rows_lse<T, N, false>), dim3(n_items), dim3(NT), 0, st, inv_off, n_cfg, cfgs,
                                (const C2 *)wsi, b, s, (const C2 *)tw, (PlanePartial<T> *)pp, (T *)psi_out, clash_out,
                                e_count);
