@@ -132,3 +132,33 @@ def test_c6_full_size_sampled_against_oracle():
             q = q[inside]
             want = bool(np.any(occ_r[q[:, 2], q[:, 1], q[:, 0]]))
             assert bool(clash[t[2], t[1], t[0]]) == want, t
+
+
+def test_n256_graph_replays_and_pose_resampling():
+    """The 256-point launch sequence captured as a graph replays bit for bit
+    (eager work and synchronizations in between); poses resampled from the
+    256-point scan are clash-free valid translations with the exported
+    energies."""
+    import torch
+    import paper_1708_07045_amd as fd
+    w = _w(n_rot=5, n_conf=2)
+    ctx = _ctx(w, energy_xy_direct=2, configs_per_chunk=4)
+    b = fd.Batch(w.ligands)
+    print("n256 graph replays", flush=True)
+    ref = ctx.scan(b, w.T).cpu().numpy()
+    ctx.set_tuning(use_graph=1)
+    out = ctx.alloc_partials(b)
+    for rep in range(3):
+        ctx.scan(b, w.T, out)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), ref)
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
+    ctx.set_tuning(use_graph=0)
+    print("n256 pose resampling", flush=True)
+    cfg, t, psi = ctx.sample_poses(b, out, 0, 0, w.T, synth.uniforms(71, 40))
+    for k in range(len(cfg)):
+        e, cl = ctx.energy_grid(0, b, int(cfg[k]), w.T)
+        tx, ty, tz = t[k]
+        assert not bool(cl[tz, ty, tx].item())
+        assert abs(float(e[tz, ty, tx].item()) - psi[k]) <= 1e-6 * max(1.0, abs(psi[k]))
