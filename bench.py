@@ -296,6 +296,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-is", action="store_true", help="skip the configurations-needed measurement")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the pose-resampling and grid-spacing measurements after the timed steps "
+                         "(for profiler runs that should hold the timed kernels only)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one 1 GiB device copy before timing (counter calibration)")
     ap.add_argument("--is-only", action="store_true", help="only the configurations-needed measurement")
@@ -438,8 +441,9 @@ def main():
         "roofline": roof,
         "kernels": kernels,
         "precision": precision_vs_oracle(args, result),
-        "pose_resampling": pose_resampling(ctx, batch, out, w.T) if args.workload == "c2" else None,
-        "spacing_study": spacing_study(w, ctx, batch, out) if args.workload == "c2" else None,
+        "pose_resampling": pose_resampling(ctx, batch, out, w.T)
+        if args.workload == "c2" and not args.no_extras else None,
+        "spacing_study": spacing_study(w, ctx, batch, out) if args.workload == "c2" and not args.no_extras else None,
         "bpmf_kcal_mol": float(result["B"][0, 0]),
         "dG_kcal_mol": float(result["res"]["dG"][0]),
         "psi_min_kcal_mol": float(result["res"]["psi_min"][0]),
