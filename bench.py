@@ -120,6 +120,62 @@ def copy_calibration():
     torch.cuda.empty_cache()
 
 
+def copy_bandwidth(stream=None, n_bytes: int = 1 << 31, reps: int = 5) -> float:
+    """Measured device-to-device copy rate (bytes read + bytes written per
+    second, GB/s) of a plain copy kernel over n_bytes, timed with HIP events."""
+    import torch
+    a = torch.ones(n_bytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    gbps = 2.0 * n_bytes * reps / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del a, b
+    torch.cuda.empty_cache()
+    return gbps
+
+
+def cpu_fft_baseline(w, budget_s: float):
+    """The paper's own method on the host: FP64 real-to-complex 3D FFTs
+    (scipy.fft, all host threads) for each configuration, over a bounded,
+    evenly strided sample of the same configurations."""
+    import numpy as np
+    import oracle
+    from oracle import fft_cpu
+    go, oo = oracle.receptor_grids(w)
+    spec = fft_cpu.receptor_spectra(w, go, oo)
+    n_all = w.ligands[0].n_cfg
+    fft_cpu.scan(w, spec, 0, np.array([0]))  # transform plans and first-touch pages, untimed
+    t0 = time.perf_counter()
+    fft_cpu.scan(w, spec, 0, np.array([1, n_all // 3, n_all // 2, n_all - 1]))
+    rate = 4 / (time.perf_counter() - t0)
+    n = int(min(n_all, max(4, rate * budget_s)))
+    sel = np.linspace(0, n_all - 1, n).astype(int)
+    t0 = time.perf_counter()
+    fft_cpu.scan(w, spec, 0, sel)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "configs/s", "cores": fft_cpu._workers(), "kind": "fft_cpu",
+            "sample": f"{n} of {n_all} configurations (evenly strided), FP64 scipy.fft (pocketfft) rfftn/irfftn "
+                      f"of the {w.n_fft}^3 grids, 4 forward + 2 inverse transforms per configuration, {dt:.1f} s"}
+
+
+# Timings the paper quotes for this path (Table 4): CPU wall time for one
+# ligand's gas-phase BPMF on T4L, CPU model and precision not stated.  The
+# configurations per BPMF are not stated for the table; ~1000 is assumed
+# for the rates.
+PAPER_CPU_TIMES = {
+    "source": "Table 4 (CPU time per ligand, p-xylene; CPU not specified, precision not stated)",
+    "fft_16A_0.25A_s": 2 * 60 + 19, "fft_16A_0.125A_s": 28 * 60 + 26, "fft_62A_0.25A_s": 7 * 3600 + 3 * 60 + 10,
+    "configs_per_s_if_1000_configs": {"16A_0.25A": 1000 / 139.0, "16A_0.125A": 1000 / 1706.0,
+                                      "62A_0.25A": 1000 / 25390.0},
+}
+
+
 def cpu_baseline(w, budget_s: float):
     """The FP64 oracle on the host cores over a bounded, evenly strided sample
     of the same configurations; returns configs/s and the sample."""
@@ -359,6 +415,8 @@ def main():
         autotuned = {"choice": tun, "ms_per_cfg_snapshot": ms, "seconds": time.perf_counter() - t0}
         log(f"autotuned schedule {tun} ({ms * 1e3:.2f} us per configuration and snapshot on the sample)")
 
+    copy_gbps = copy_bandwidth()
+    log(f"device copy: {copy_gbps:.0f} GB/s (read + write)")
     if args.copy_calibration:
         copy_calibration()
     result = {}
@@ -406,6 +464,7 @@ def main():
             traffic = per_cfg * n_cfg * args.steps / prof["zprod"][1]   # bytes per launch
     roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "copy_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps,
             "avg_launch_us": kd["avg_launch_us"], "alg_bytes_per_launch": kd["alg_bytes_per_launch"]}
     # whole path: algorithmic bytes of all scan kernels per configuration
     path_bytes = sum(prof[k][2] for k in ("lig_fwd_xy", "zprod", "inv_xy_lse", "merge")) / args.steps
@@ -438,6 +497,8 @@ def main():
         "evaluated_translations_per_s": cfg_s * n_snap * w.n_fft ** 3,
         "path_alg_bytes_per_cfg": path_bytes / n_cfg,
         "path_alg_GBps": path_bytes / (ms_step / 1e3) / 1e9,
+        "path_frac_of_peak": path_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
+        "path_frac_of_copy": path_bytes / (ms_step / 1e3) / 1e9 / copy_gbps,
         "roofline": roof,
         "kernels": kernels,
         "precision": precision_vs_oracle(args, result),
@@ -456,6 +517,9 @@ def main():
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         rec["cpu_baseline"] = cpu_baseline(w, args.cpu_budget)
+        log("cpu baseline (FFT method, scipy) ...")
+        rec["cpu_fft_baseline"] = cpu_fft_baseline(w, args.cpu_budget * 2 / 3)
+        rec["paper_cpu_times"] = PAPER_CPU_TIMES
     else:
         rec["cpu_baseline"] = None
     if args.workload == "c2" and not args.no_is:
