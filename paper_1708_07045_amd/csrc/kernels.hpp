@@ -26,8 +26,9 @@ struct KernelSet {
     // kernel (else read from forward planes written by fwd)
     // n_snap snapshots per launch: spectra spec_stride and outputs inv_stride
     // complex elements apart
-    // zhalf: every configuration's energy planes lie in [0, n_fft/2)
-    hipError_t (*zprod)(hipStream_t, bool occ, bool edirect, bool zhalf, const CfgDev *cfgs, const int32_t *zcfg, int nz,
+    // zhalf: 1 = every configuration's energy planes lie in [0, n_fft/2);
+    // 2 = that, and some occupancy window spans more than n_fft/2 planes
+    hipError_t (*zprod)(hipStream_t, bool occ, bool edirect, int zhalf, const CfgDev *cfgs, const int32_t *zcfg, int nz,
                         const void *ws, const void *rspec, const void *tw, void *wsi, const int32_t *ulat,
                         const void *gam, int n_snap, int64_t spec_stride, int64_t inv_stride);
     // e_count (nullable): incremented once per energy plane transformed

@@ -219,7 +219,7 @@ struct Plan {
         size_t z0, nz;            // scanned configurations (local indices)
         int64_t ws_fwd, ws_inv;   // complex elements used
         int pp;                   // plane partial slots used
-        bool zhalf;               // every scanned configuration's energy planes lie in [0, n_fft/2)
+        int zhalf;                // 1: every scanned configuration's energy planes lie in [0, n_fft/2); 2: and some occupancy window is longer than n_fft/2
     };
     std::vector<Chunk> chunks;
     std::vector<int32_t> fwd_off, inv_off;
@@ -409,7 +409,7 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
         int nscan = 0;
         int64_t wf = 0, wi = 0;
         int pp = 0;
-        bool zhalf = true;
+        bool zhalf = true, olong = false;
         while (c < ncfg) {
             CfgDev &d = P.cfg[c];
             if (d.scanned) {
@@ -429,6 +429,7 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
                 ni += d.V[2];
                 P.zcfg.push_back(local);
                 zhalf = zhalf && d.ze0 >= 0 && d.ze0 + d.Le <= ctx->g.n_fft / 2;
+                olong = olong || (occ && d.Lo > ctx->g.n_fft / 2);
                 wf += f;
                 wi += iv;
                 pp += d.V[2];
@@ -451,7 +452,7 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
         ch.ws_fwd = wf;
         ch.ws_inv = wi;
         ch.pp = pp;
-        ch.zhalf = zhalf;
+        ch.zhalf = zhalf ? (olong ? 2 : 1) : 0;
         P.max_fwd = std::max(P.max_fwd, wf);
         P.max_inv = std::max(P.max_inv, wi);
         P.max_pp = std::max(P.max_pp, pp);

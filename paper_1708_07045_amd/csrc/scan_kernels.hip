@@ -120,6 +120,14 @@ __device__ __forceinline__ float2 buf_load(__amdgpu_buffer_rsrc_t r, int off, fl
 __device__ __forceinline__ double2 buf_load(__amdgpu_buffer_rsrc_t r, int off, double2 *) {
     return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, 0, 0));
 }
+// soff: a wave-uniform part of the offset, carried in an SGPR.  Only the
+// VGPR part is range-checked, so the sum must lie inside the descriptor.
+__device__ __forceinline__ float2 buf_load(__amdgpu_buffer_rsrc_t r, int off, int soff, float2 *) {
+    return __builtin_bit_cast(float2, __builtin_amdgcn_raw_buffer_load_b64(r, off, soff, 0));
+}
+__device__ __forceinline__ double2 buf_load(__amdgpu_buffer_rsrc_t r, int off, int soff, double2 *) {
+    return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, soff, 0));
+}
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, float2 v) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
 }
@@ -924,7 +932,7 @@ struct DAtom {
 // spectra stay in registers while the product and inverse run for each of
 // n_snap receptor snapshots (spectra spec_stride apart, outputs inv_stride
 // apart).
-template <typename T, int N, bool OCC, bool EDIRECT, bool MULTI, bool ZH>
+template <typename T, int N, bool OCC, bool EDIRECT, bool MULTI, int ZH>
 __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, const int32_t *__restrict__ zcfg,
                                                int nz, int n_tiles, const typename Cx<T>::t *__restrict__ ws,
                                                const typename Cx<T>::t *__restrict__ rspec,
@@ -971,13 +979,119 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
     const int pen = tile * P + p;
     const bool ok = pen < NP;
     const int nchunk = EDIRECT ? (c.n_atoms + AC - 1) / AC : 0;
-    // ZH (launch-wide): every configuration's energy planes lie in [0, N/2),
-    // so the upper half of the z inputs is zero: not loaded, first FFT stage
-    // pruned
-    constexpr bool half = ZH && !EDIRECT;
+    // ZH (launch-wide) > 0: every configuration's energy planes lie in
+    // [0, N/2), so the upper half of the z inputs is zero: not loaded, first
+    // FFT stage pruned.  ZH == 2: some occupancy window is longer than N/2
+    // planes (a separate instantiation keeps the common one's registers low).
+    constexpr bool half = ZH > 0 && !EDIRECT;
+    constexpr bool olong = ZH == 2;
     // element e of this lane's pencil in the wave region
     auto eaddr = [&](int e) { return e * PW + (e / R2) * PAD; };
-    if constexpr (!MULTI) {
+    if constexpr (!MULTI && half) {
+    // Every energy window lies in the lower half of the pencil.  The planes
+    // of the next channel (energy channels, then occupancy) are loaded while
+    // the current one is transformed.  Energy planes sit at z = ze0 + s.  The
+    // occupancy window is loaded from z = 0 instead of z = zo0: the circular
+    // correlation of the shifted ligand grid is the wanted one shifted by
+    // zo0, C(t) = C'(t + zo0 mod N), so the store takes element z to
+    // translation t = z - zo0 mod N.
+    constexpr int HZ = R2 / 2;
+    const int po = ok ? pen : NP * N;  // out of every descriptor's range
+    const int rlane = (M * n1 * NP + (ok ? pen : 0)) * (int)sizeof(C2);
+    C2 pf[HZ];
+    auto fetch = [&](int ch) {
+        if (ch < 3) {
+            const auto rs = make_rsrc(ws + c.off_fwd + (int64_t)ch * c.Le * NP, c.Le * NP * (int)sizeof(C2));
+#pragma unroll
+            for (int i = 0; i < HZ; ++i) {
+                const int s = (n1 + R1 * i - c.ze0) & (N - 1);
+                pf[i] = buf_load(rs, (s * NP + po) * (int)sizeof(C2), (C2 *)nullptr);
+            }
+        } else {
+            const auto rs = make_rsrc(ws + c.off_fwd + (int64_t)c.occ_slot0 * NP, c.Lo * NP * (int)sizeof(C2));
+#pragma unroll
+            for (int i = 0; i < HZ; ++i)
+                pf[i] = buf_load(rs, ((n1 + R1 * i) * NP + po) * (int)sizeof(C2), (C2 *)nullptr);
+        }
+    };
+    T er[R2], ei[R2];
+#pragma unroll
+    for (int i = 0; i < R2; ++i) er[i] = ei[i] = (T)0;
+    fetch(0);
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        T re[R2], im[R2];
+#pragma unroll
+        for (int i = 0; i < HZ; ++i) {
+            re[i] = pf[i].x;
+            im[i] = pf[i].y;
+            re[i + HZ] = im[i + HZ] = (T)0;
+        }
+        if (ch < 2 || OCC) fetch(ch + 1);
+        fft_unit<T, N, false, true>(re, im, n1, ex, PW, tw, true, PAD);
+        const auto rr = make_rsrc(rspec + (int64_t)ch * N * NP, N * NP * (int)sizeof(C2));
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) {
+                // k = R2 k1 + M n1 + i: the lane part in the VGPR offset
+                const C2 r = buf_load(rr, rlane, (R2 * k1 + i) * NP * (int)sizeof(C2), (C2 *)nullptr);
+                const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
+                er[i * R1 + k1] += r.x * lr + r.y * li;  // R * conj(L)
+                ei[i * R1 + k1] += r.y * lr - r.x * li;
+            }
+    }
+    const int Vz = c.V[2];
+    fft_unit_rev<T, N, true>(er, ei, n1, ex, PW, tw, true, PAD);
+    {
+        // valid z-translations only: tz >= Vz lies beyond the descriptor
+        const auto rd = make_rsrc(wsi + c.off_inv, Vz * NP * (int)sizeof(C2));
+#pragma unroll
+        for (int i = 0; i < R2; ++i)
+            buf_store(rd, ((n1 + R1 * i) * NP + po) * (int)sizeof(C2), C2{er[i], ei[i]});
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    if (OCC) {
+        T re[R2], im[R2];
+#pragma unroll
+        for (int i = 0; i < HZ; ++i) {
+            re[i] = pf[i].x;
+            im[i] = pf[i].y;
+            re[i + HZ] = im[i + HZ] = (T)0;
+        }
+        if (!olong || c.Lo <= N / 2) {
+            fft_unit<T, N, false, true>(re, im, n1, ex, PW, tw, true, PAD);
+        } else {
+            // a window longer than half the pencil: its upper planes now
+            const auto rs = make_rsrc(ws + c.off_fwd + (int64_t)c.occ_slot0 * NP, c.Lo * NP * (int)sizeof(C2));
+#pragma unroll
+            for (int i = HZ; i < R2; ++i) {
+                const C2 v = buf_load(rs, ((n1 + R1 * i) * NP + po) * (int)sizeof(C2), (C2 *)nullptr);
+                re[i] = v.x;
+                im[i] = v.y;
+            }
+            fft_unit<T, N, false>(re, im, n1, ex, PW, tw, true, PAD);
+        }
+        const auto rr = make_rsrc(rspec + (int64_t)3 * N * NP, N * NP * (int)sizeof(C2));
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) {
+                // k = R2 k1 + M n1 + i: the lane part in the VGPR offset
+                const C2 r = buf_load(rr, rlane, (R2 * k1 + i) * NP * (int)sizeof(C2), (C2 *)nullptr);
+                const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
+                re[i * R1 + k1] = r.x * lr + r.y * li;
+                im[i * R1 + k1] = r.y * lr - r.x * li;
+            }
+        fft_unit_rev<T, N, true>(re, im, n1, ex, PW, tw, true, PAD);
+        const auto rd = make_rsrc(wsi + c.off_inv + (int64_t)Vz * NP, Vz * NP * (int)sizeof(C2));
+#pragma unroll
+        for (int i = 0; i < R2; ++i) {
+            const int t = (n1 + R1 * i - c.zo0) & (N - 1);
+            buf_store(rd, (t * NP + po) * (int)sizeof(C2), C2{re[i], im[i]});
+        }
+    }
+    } else if constexpr (!MULTI) {
     T er[R2], ei[R2];
 #pragma unroll
     for (int i = 0; i < R2; ++i) er[i] = ei[i] = (T)0;
@@ -2056,7 +2170,7 @@ struct Launch {
                                ulat, (const T *)gam, thr, (const C2 *)tw, (C2 *)ws);
         return hipGetLastError();
     }
-    static hipError_t zprod(hipStream_t st, bool occ, bool edirect, bool zhalf, const CfgDev *cfgs, const int32_t *zcfg,
+    static hipError_t zprod(hipStream_t st, bool occ, bool edirect, int zhalf, const CfgDev *cfgs, const int32_t *zcfg,
                             int nz, const void *ws, const void *rspec, const void *tw, void *wsi,
                             const int32_t *ulat, const void *gam, int n_snap, int64_t spec_stride,
                             int64_t inv_stride) {
@@ -2073,12 +2187,13 @@ struct Launch {
         hipLaunchKernelGGL((k_zprod<T, N, O, E, false, Z>), dim3((unsigned)nb), dim3(NT), 0, st, cfgs, zcfg, \
                            nz, n_tiles, (const C2 *)ws, (const C2 *)rspec, (const C2 *)tw, (C2 *)wsi, ulat,    \
                            (const T *)gam, n_snap, spec_stride, inv_stride)
-        if (occ && edirect) FFTDG_ZPROD(true, true, false);
-        else if (occ && zhalf) FFTDG_ZPROD(true, false, true);
-        else if (occ) FFTDG_ZPROD(true, false, false);
-        else if (edirect) FFTDG_ZPROD(false, true, false);
-        else if (zhalf) FFTDG_ZPROD(false, false, true);
-        else FFTDG_ZPROD(false, false, false);
+        if (occ && edirect) FFTDG_ZPROD(true, true, 0);
+        else if (occ && zhalf == 2) FFTDG_ZPROD(true, false, 2);
+        else if (occ && zhalf) FFTDG_ZPROD(true, false, 1);
+        else if (occ) FFTDG_ZPROD(true, false, 0);
+        else if (edirect) FFTDG_ZPROD(false, true, 0);
+        else if (zhalf) FFTDG_ZPROD(false, false, 1);
+        else FFTDG_ZPROD(false, false, 0);
 #undef FFTDG_ZPROD
         return hipGetLastError();
     }
