@@ -157,20 +157,29 @@ __device__ __forceinline__ void plane_copy(typename Cx<T>::t *Pl, typename Cx<T>
             if (q < NPAIR) v[j] = reinterpret_cast<const Pair *>(g)[q];
         }
     }
+    // (row, column) of element 2q, q = threadIdx.x + j NT, stepped by 2 NT
+    // elements per j instead of divided out per element
+    constexpr int DY = (2 * NT) / H, DX = (2 * NT) % H;
+    int y0 = (2 * (int)threadIdx.x) / H, x0 = 2 * (int)threadIdx.x - y0 * H;
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
         const int q = threadIdx.x + j * NT;
         if (q < NPAIR) {
-            const int e0 = 2 * q, e1 = 2 * q + 1;
-            const int y0 = e0 / H, x0 = e0 - y0 * H;
-            const int y1 = e1 / H, x1 = e1 - y1 * H;
+            const bool wrap = x0 + 1 == H;
+            const int o0 = y0 * S + x0, o1 = wrap ? (y0 + 1) * S : o0 + 1;
             if (TO_LDS) {
-                Pl[y0 * S + x0] = v[j].a;
-                Pl[y1 * S + x1] = v[j].b;
+                Pl[o0] = v[j].a;
+                Pl[o1] = v[j].b;
             } else {
-                v[j].a = Pl[y0 * S + x0];
-                v[j].b = Pl[y1 * S + x1];
+                v[j].a = Pl[o0];
+                v[j].b = Pl[o1];
             }
+        }
+        x0 += DX;
+        y0 += DY;
+        if (x0 >= H) {
+            x0 -= H;
+            ++y0;
         }
     }
     if (!TO_LDS) {
@@ -1402,6 +1411,91 @@ struct LseAcc {
     }
 };
 
+__device__ __forceinline__ float lse_exp(float d) { return __builtin_amdgcn_exp2f(d * 1.4426950408889634f); }
+__device__ __forceinline__ double lse_exp(double d) { return exp(d); }
+
+// Outputs of one lane after the C2R transform of storage rows (y, y+1):
+// slot (i R1 + k1) holds x = spec_index(n1, i, k1) of row y in re and of
+// row y+1 in im.  Flag bit (i R1 + k1) * 2 + h stands for (x, y + h).
+// The occupancy pass returns the clash flags (C >= 1/2, Eq. 10) of the
+// valid translations; the energy pass exports if asked and folds the
+// clash-free values into the Eq. 2 partial in two sweeps over registers
+// (local maximum of -beta psi, then the sum of exponentials), keeping the
+// lowest linear index among equal minima.
+template <typename T, int N, bool OCC>
+__device__ __forceinline__ uint32_t row_pair_epilogue(T *re, T *im, int n1, int y, int Vx, int Vy, int tz,
+                                                      bool occ_pass, uint32_t clash, T inv_n3, T beta,
+                                                      T *__restrict__ psi_out, uint8_t *__restrict__ clash_out,
+                                                      LseAcc<T> &acc, uint32_t &valid) {
+    constexpr int R1 = Shape<N>::R1, R2 = Shape<N>::R2, M = R2 / R1;
+    static_assert(2 * R2 <= 32, "one flag word per row pair");
+    // slot s = i R1 + k1; value of (x, y + h) in (h ? im : re)[s]; bit 2 s + h
+    uint32_t vb = 0;
+#pragma unroll
+    for (int sl = 0; sl < R2; ++sl) {
+        const int x = spec_index<N>(n1, sl / R1, sl % R1);
+        re[sl] *= inv_n3;
+        im[sl] *= inv_n3;
+        vb |= (uint32_t)(x < Vx && y < Vy) << (2 * sl);
+        vb |= (uint32_t)(x < Vx && y + 1 < Vy) << (2 * sl + 1);
+    }
+    valid = vb;
+    if (OCC && occ_pass) {
+        uint32_t cb = 0;
+#pragma unroll
+        for (int sl = 0; sl < R2; ++sl) {
+            cb |= (uint32_t)(re[sl] >= (T)0.5) << (2 * sl);
+            cb |= (uint32_t)(im[sl] >= (T)0.5) << (2 * sl + 1);
+        }
+        return cb & vb;
+    }
+    if (psi_out || clash_out) {
+#pragma unroll
+        for (int sl = 0; sl < R2; ++sl)
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const int x = spec_index<N>(n1, sl / R1, sl % R1), b = 2 * sl + h;
+                if ((vb >> b) & 1u) {
+                    const int lin = (tz * Vy + y + h) * Vx + x;
+                    if (psi_out) psi_out[lin] = h ? im[sl] : re[sl];
+                    if (clash_out) clash_out[lin] = OCC ? (uint8_t)((clash >> b) & 1u) : (uint8_t)0;
+                }
+            }
+    }
+    const uint32_t use = vb & ~(OCC ? clash : 0u);
+    if (use == 0u) return 0u;
+    // minimum psi (its -beta multiple is the maximum of the exponents)
+    T pm = (T)INFINITY;
+    int am = 0x7fffffff;
+#pragma unroll
+    for (int sl = 0; sl < R2; ++sl)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const T v = h ? im[sl] : re[sl];
+            const int lin = (tz * Vy + y + h) * Vx + spec_index<N>(n1, sl / R1, sl % R1);
+            const bool better = ((use >> (2 * sl + h)) & 1u) && (v < pm || (v == pm && lin < am));
+            pm = better ? v : pm;
+            am = better ? lin : am;
+        }
+    const T ml = -beta * pm;
+    T sm = (T)0;
+#pragma unroll
+    for (int sl = 0; sl < R2; ++sl)
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const T e = lse_exp(-beta * (h ? im[sl] : re[sl]) - ml);
+            sm += ((use >> (2 * sl + h)) & 1u) ? e : (T)0;
+        }
+    LseAcc<T> o;
+    o.m = ml;
+    o.s = sm;
+    o.pmin = pm;
+    o.amin = am;
+    o.n = __builtin_popcount(use);
+    acc.merge(o);
+    return 0u;
+}
+
 // Inverse xy + clash mask + Eq. 2 partials for one valid z-translation.
 // In a scan (no energy export) the energy channel of a plane whose every
 // translation clashes is not transformed: those energies are infinite by the
@@ -1416,28 +1510,27 @@ __global__ __launch_bounds__(NT) void k_inv_xy_lse(const int32_t *__restrict__ i
     using C2 = typename Cx<T>::t;
     using G = Geo<T, N>;
     constexpr int R1 = G::R1, R2 = G::R2, M = G::M, S = G::S, U = G::U, NP = G::NP;
+    constexpr int MAXR = (N / 2 + U - 1) / U;  // rounds of row pairs
     static_assert(N + (R1 - 1) * G::RPAD <= 2 * S, "row-pair exchange must fit in two rows");
     __shared__ C2 Pl[N * S];
     __shared__ C2 tw[N];
-    __shared__ uint32_t cmask[(N * N + 31) / 32];
+    __shared__ uint32_t cflags[MAXR * NT];  // per thread and round: clash flags of its outputs
     __shared__ LseAcc<T> red[NT];
     const int ic = find_cfg(inv_off, n_cfg, (int)blockIdx.x);
     const CfgDev c = cfgs[ic];
     const int Vx = c.V[0], Vy = c.V[1], Vz = c.V[2], tz = (int)blockIdx.x - inv_off[ic];
     load_tw<T, N>(tw, twg);
-    for (int i = threadIdx.x; i < (N * N + 31) / 32; i += NT) cmask[i] = 0u;
     const int unit = threadIdx.x / R1, n1 = threadIdx.x % R1;
     LseAcc<T> acc;
     acc.init();
+    int any_free = 0;
     constexpr int NCH = OCC ? 2 : 1;
     for (int pass = 0; pass < NCH; ++pass) {
         const int och = OCC ? 1 - pass : 0;  // occupancy first
         const C2 *src = wsi + c.off_inv + ((int64_t)och * Vz + tz) * NP;
         if (OCC && och == 0 && !psi_out) {
             // any clash-free translation on this plane?
-            int free_local = 0;
-            for (int e = threadIdx.x; e < Vy * Vx; e += NT) free_local |= !((cmask[e >> 5] >> (e & 31)) & 1u);
-            if (!__syncthreads_or(free_local)) break;
+            if (!__syncthreads_or(any_free)) break;
         }
         if (och == 0 && threadIdx.x == 0 && e_count) atomicAdd(e_count, 1u);
         __syncthreads();
@@ -1449,20 +1542,16 @@ __global__ __launch_bounds__(NT) void k_inv_xy_lse(const int32_t *__restrict__ i
         for (int rd = 0; rd < rounds_b; ++rd) {
             const int col = unit + U * rd;
             const bool live = col < N / 2;
+            const bool c0 = col == 0;
 #pragma unroll
             for (int i = 0; i < R2; ++i) {
                 const int ky = n1 + R1 * i;
                 re[i] = im[i] = (T)0;
                 if (live) {
-                    if (col == 0) {
-                        const C2 a = Pl[ky * S], bq = Pl[ky * S + N / 2];
-                        re[i] = a.x - bq.y;
-                        im[i] = a.y + bq.x;
-                    } else {
-                        const C2 v = Pl[ky * S + col];
-                        re[i] = v.x;
-                        im[i] = v.y;
-                    }
+                    const C2 v = Pl[ky * S + col];
+                    const C2 bq = c0 ? Pl[ky * S + N / 2] : C2{(T)0, (T)0};
+                    re[i] = v.x - bq.y;
+                    im[i] = v.y + bq.x;
                 }
             }
             C2 *cp = Pl + (live ? col : 0);
@@ -1475,7 +1564,7 @@ __global__ __launch_bounds__(NT) void k_inv_xy_lse(const int32_t *__restrict__ i
                     for (int k1 = 0; k1 < R1; ++k1) {
                         const int y = spec_index<N>(n1, i, k1);
                         if (y < Vy) {
-                            if (col == 0) {
+                            if (c0) {
                                 Pl[y * S] = C2{re[i * R1 + k1], (T)0};
                                 Pl[y * S + N / 2] = C2{im[i * R1 + k1], (T)0};
                             } else {
@@ -1498,49 +1587,27 @@ __global__ __launch_bounds__(NT) void k_inv_xy_lse(const int32_t *__restrict__ i
                 const int k = n1 + R1 * i;
                 re[i] = im[i] = (T)0;
                 if (live) {
-                    C2 a, bq;
-                    if (k <= N / 2) {
-                        a = row[k];
-                        bq = row[S + k];
-                        if (k == 0 || k == N / 2) {
-                            a.y = (T)0;
-                            bq.y = (T)0;
-                        }
-                    } else {
-                        a = row[N - k];
-                        bq = row[S + N - k];
-                        a.y = -a.y;
-                        bq.y = -bq.y;
-                    }
+                    // row values at k (k <= N/2) or conj at N - k; kx = 0, N/2 are real
+                    const int kk = k <= N / 2 ? k : N - k;
+                    C2 a = row[kk], bq = row[S + kk];
+                    const T sg = (k == 0 || k == N / 2) ? (T)0 : (k < N / 2 ? (T)1 : (T)-1);
+                    a.y *= sg;
+                    bq.y *= sg;
                     re[i] = a.x - bq.y;
                     im[i] = a.y + bq.x;
                 }
             }
             fft_unit<T, N, true>(re, im, n1, row, 1, tw, live, G::RPAD);
             if (live) {
-#pragma unroll
-                for (int i = 0; i < M; ++i)
-#pragma unroll
-                    for (int k1 = 0; k1 < R1; ++k1) {
-                        const int x = spec_index<N>(n1, i, k1);
-                        if (x >= Vx) continue;
-#pragma unroll
-                        for (int h = 0; h < 2; ++h) {
-                            const int yy = y + h;
-                            if (yy >= Vy) continue;
-                            const T v = (h ? im[i * R1 + k1] : re[i * R1 + k1]) * inv_n3;
-                            const int bit = yy * Vx + x;
-                            if (OCC && och == 1) {
-                                if (v >= (T)0.5) atomicOr(&cmask[bit >> 5], 1u << (bit & 31));
-                            } else {
-                                const int lin = (tz * Vy + yy) * Vx + x;
-                                const bool cl = OCC ? ((cmask[bit >> 5] >> (bit & 31)) & 1u) : false;
-                                if (psi_out) psi_out[lin] = v;
-                                if (clash_out) clash_out[lin] = cl ? 1 : 0;
-                                if (!cl) acc.add(-beta * v, v, lin);
-                            }
-                        }
-                    }
+                uint32_t &cw = cflags[rd * NT + threadIdx.x];  // written and read by this thread only
+                uint32_t vb;
+                const uint32_t f = row_pair_epilogue<T, N, OCC>(re, im, n1, y, Vx, Vy, tz, OCC && och == 1,
+                                                                (OCC && och == 0) ? cw : 0u, inv_n3, beta, psi_out,
+                                                                clash_out, acc, vb);
+                if (OCC && och == 1) {
+                    cw = f;
+                    any_free |= (vb & ~f) != 0u;
+                }
             }
         }
     }
@@ -1744,26 +1811,25 @@ __global__ __launch_bounds__(NT) void k_inv_rows_lse(const int32_t *__restrict__
     constexpr int R1 = SG::R1, R2 = SG::R2, M = SG::M, U = SG::U, H = SG::H;
     __shared__ C2 reg_all[SG::U * SG::XREG];
     __shared__ C2 tw[N];
-    __shared__ uint32_t cmask[(N * N + 31) / 32];
+    constexpr int MAXR = (N / 2 + U - 1) / U;  // rounds of row pairs
+    __shared__ uint32_t cflags[MAXR * NT];     // per thread and round: clash flags of its outputs
     __shared__ LseAcc<T> red[NT];
     const int ic = find_cfg(inv_off, n_cfg, (int)blockIdx.x);
     const CfgDev c = cfgs[ic];
     const int Vx = c.V[0], Vy = c.V[1], Vz = c.V[2], tz = (int)blockIdx.x - inv_off[ic];
     load_tw<T, N>(tw, twg);
-    for (int i = threadIdx.x; i < (N * N + 31) / 32; i += NT) cmask[i] = 0u;
     const int unit = threadIdx.x / R1, n1 = threadIdx.x % R1;
     C2 *reg = reg_all + unit * SG::XREG;
     LseAcc<T> acc;
     acc.init();
+    int any_free = 0;
     constexpr int NCH = OCC ? 2 : 1;
     for (int pass = 0; pass < NCH; ++pass) {
         const int och = OCC ? 1 - pass : 0;  // occupancy first
         const C2 *src = wsi + c.off_inv + ((int64_t)och * Vz + tz) * SG::NP;
         __syncthreads();
         if (OCC && och == 0 && !psi_out) {
-            int free_local = 0;
-            for (int e = threadIdx.x; e < Vy * Vx; e += NT) free_local |= !((cmask[e >> 5] >> (e & 31)) & 1u);
-            if (!__syncthreads_or(free_local)) break;
+            if (!__syncthreads_or(any_free)) break;
         }
         if (och == 0 && threadIdx.x == 0 && e_count) atomicAdd(e_count, 1u);
         const int npairs = (Vy + 1) / 2;
@@ -1799,29 +1865,15 @@ __global__ __launch_bounds__(NT) void k_inv_rows_lse(const int32_t *__restrict__
             }
             fft_unit<T, N, true>(re, im, n1, reg, 1, tw, live, SG::XPAD);
             if (live) {
-#pragma unroll
-                for (int i = 0; i < M; ++i)
-#pragma unroll
-                    for (int k1 = 0; k1 < R1; ++k1) {
-                        const int x = spec_index<N>(n1, i, k1);
-                        if (x >= Vx) continue;
-#pragma unroll
-                        for (int hh = 0; hh < 2; ++hh) {
-                            const int yy = y + hh;
-                            if (yy >= Vy) continue;
-                            const T v = (hh ? im[i * R1 + k1] : re[i * R1 + k1]) * inv_n3;
-                            const int bit = yy * Vx + x;
-                            if (OCC && och == 1) {
-                                if (v >= (T)0.5) atomicOr(&cmask[bit >> 5], 1u << (bit & 31));
-                            } else {
-                                const int lin = (tz * Vy + yy) * Vx + x;
-                                const bool cl = OCC ? ((cmask[bit >> 5] >> (bit & 31)) & 1u) : false;
-                                if (psi_out) psi_out[lin] = v;
-                                if (clash_out) clash_out[lin] = cl ? 1 : 0;
-                                if (!cl) acc.add(-beta * v, v, lin);
-                            }
-                        }
-                    }
+                uint32_t &cw = cflags[rd * NT + threadIdx.x];  // written and read by this thread only
+                uint32_t vb;
+                const uint32_t f = row_pair_epilogue<T, N, OCC>(re, im, n1, y, Vx, Vy, tz, OCC && och == 1,
+                                                                (OCC && och == 0) ? cw : 0u, inv_n3, beta, psi_out,
+                                                                clash_out, acc, vb);
+                if (OCC && och == 1) {
+                    cw = f;
+                    any_free |= (vb & ~f) != 0u;
+                }
             }
             wave_sync();
         }
