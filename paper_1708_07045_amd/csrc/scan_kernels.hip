@@ -52,9 +52,14 @@ struct Geo {
     static constexpr int U = NT / R1;    // FFT units per workgroup
     // z-pencil kernels: each wavefront owns PW whole pencils (R1 lanes each);
     // its exchange region holds N elements per pencil plus PAD complex per
-    // block of R2 elements.
+    // block of R2 elements.  Element e of pencil pl sits at e PW + (e / R2)
+    // PAD + pl.  The 64 lanes reading at once differ in n1 (block e / R2)
+    // and pl, so their complex offsets differ by n1 PAD + pl (mod the bank
+    // count): PAD = 64 / R1 makes those 64 offsets distinct, every bank is
+    // hit equally often and a read takes the minimum number of LDS passes
+    // (N = 32 keeps 8: its 16 pencils per wave already spread the offsets).
     static constexpr int PW = 64 / R1;
-    static constexpr int PAD = 8;
+    static constexpr int PAD = R1 == 16 ? 4 : 8;
     static constexpr int WREG = N * PW + R1 * PAD;
 };
 
