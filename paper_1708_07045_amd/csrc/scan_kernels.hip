@@ -60,6 +60,14 @@ struct Geo {
     // (N = 32 keeps 8: its 16 pencils per wave already spread the offsets).
     static constexpr int PW = 64 / R1;
     static constexpr int PAD = R1 == 16 ? 4 : 8;
+    // Receptor spectra, per channel: element (k, pencil).  When a z-kernel
+    // lane's outputs come in adjacent pairs k, k + 1 (M = 2) and FP32, the
+    // pairs are interleaved per pencil, [k / 2][pencil][2], so one 16-byte
+    // load brings both; otherwise [k][pencil].
+    static constexpr bool KPAIR = M == 2 && sizeof(T) == 4;
+    __host__ __device__ static constexpr int rs_index(int k, int pen) {
+        return KPAIR ? (k & ~1) * NP + 2 * pen + (k & 1) : k * NP + pen;
+    }
     static constexpr int WREG = N * PW + R1 * PAD;
 };
 
@@ -132,6 +140,9 @@ __device__ __forceinline__ float2 buf_load(__amdgpu_buffer_rsrc_t r, int off, in
 }
 __device__ __forceinline__ double2 buf_load(__amdgpu_buffer_rsrc_t r, int off, int soff, double2 *) {
     return __builtin_bit_cast(double2, __builtin_amdgcn_raw_buffer_load_b128(r, off, soff, 0));
+}
+__device__ __forceinline__ float4 buf_load4(__amdgpu_buffer_rsrc_t r, int off, int soff) {
+    return __builtin_bit_cast(float4, __builtin_amdgcn_raw_buffer_load_b128(r, off, soff, 0));
 }
 __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, float2 v) {
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, off, 0, 0);
@@ -692,7 +703,7 @@ __global__ __launch_bounds__(NT) void k_rec_z(const typename Cx<T>::t *__restric
 #pragma unroll
             for (int k1 = 0; k1 < R1; ++k1) {
                 const int k = spec_index<N>(n1, i, k1);
-                rspec[((int64_t)ch * N + k) * G::NP + pen] = C2{re[i * R1 + k1], im[i * R1 + k1]};
+                rspec[(int64_t)ch * N * G::NP + G::rs_index(k, pen)] = C2{re[i * R1 + k1], im[i * R1 + k1]};
             }
     }
 }
@@ -1011,7 +1022,8 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
     // translation t = z - zo0 mod N.
     constexpr int HZ = R2 / 2;
     const int po = ok ? pen : NP * N;  // out of every descriptor's range
-    const int rlane = (M * n1 * NP + (ok ? pen : 0)) * (int)sizeof(C2);
+    // receptor offsets: lane part (VGPR) + uniform part (SGPR)
+    const int rlane = (M * n1 * NP + (G::KPAIR ? 2 : 1) * (ok ? pen : 0)) * (int)sizeof(C2);
     C2 pf[HZ];
     auto fetch = [&](int ch) {
         if (ch < 3) {
@@ -1044,16 +1056,31 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
         if (ch < 2 || OCC) fetch(ch + 1);
         fft_unit<T, N, false, true>(re, im, n1, ex, PW, tw, true, PAD);
         const auto rr = make_rsrc(rspec + (int64_t)ch * N * NP, N * NP * (int)sizeof(C2));
-#pragma unroll
-        for (int i = 0; i < M; ++i)
+        if constexpr (G::KPAIR) {
 #pragma unroll
             for (int k1 = 0; k1 < R1; ++k1) {
-                // k = R2 k1 + M n1 + i: the lane part in the VGPR offset
-                const C2 r = buf_load(rr, rlane, (R2 * k1 + i) * NP * (int)sizeof(C2), (C2 *)nullptr);
-                const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
-                er[i * R1 + k1] += r.x * lr + r.y * li;  // R * conj(L)
-                ei[i * R1 + k1] += r.y * lr - r.x * li;
+                // k = R2 k1 + 2 n1 + i, i = 0, 1 in one load
+                const float4 r2 = buf_load4(rr, rlane, R2 * k1 * NP * (int)sizeof(C2));
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const T rx = i ? r2.z : r2.x, ry = i ? r2.w : r2.y;
+                    const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
+                    er[i * R1 + k1] += rx * lr + ry * li;  // R * conj(L)
+                    ei[i * R1 + k1] += ry * lr - rx * li;
+                }
             }
+        } else {
+#pragma unroll
+            for (int i = 0; i < M; ++i)
+#pragma unroll
+                for (int k1 = 0; k1 < R1; ++k1) {
+                    // k = R2 k1 + M n1 + i: the lane part in the VGPR offset
+                    const C2 r = buf_load(rr, rlane, (R2 * k1 + i) * NP * (int)sizeof(C2), (C2 *)nullptr);
+                    const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
+                    er[i * R1 + k1] += r.x * lr + r.y * li;  // R * conj(L)
+                    ei[i * R1 + k1] += r.y * lr - r.x * li;
+                }
+        }
     }
     const int Vz = c.V[2];
     fft_unit_rev<T, N, true>(er, ei, n1, ex, PW, tw, true, PAD);
@@ -1087,16 +1114,29 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
             fft_unit<T, N, false>(re, im, n1, ex, PW, tw, true, PAD);
         }
         const auto rr = make_rsrc(rspec + (int64_t)3 * N * NP, N * NP * (int)sizeof(C2));
-#pragma unroll
-        for (int i = 0; i < M; ++i)
+        if constexpr (G::KPAIR) {
 #pragma unroll
             for (int k1 = 0; k1 < R1; ++k1) {
-                // k = R2 k1 + M n1 + i: the lane part in the VGPR offset
-                const C2 r = buf_load(rr, rlane, (R2 * k1 + i) * NP * (int)sizeof(C2), (C2 *)nullptr);
-                const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
-                re[i * R1 + k1] = r.x * lr + r.y * li;
-                im[i * R1 + k1] = r.y * lr - r.x * li;
+                const float4 r2 = buf_load4(rr, rlane, R2 * k1 * NP * (int)sizeof(C2));
+#pragma unroll
+                for (int i = 0; i < 2; ++i) {
+                    const T rx = i ? r2.z : r2.x, ry = i ? r2.w : r2.y;
+                    const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
+                    re[i * R1 + k1] = rx * lr + ry * li;
+                    im[i * R1 + k1] = ry * lr - rx * li;
+                }
             }
+        } else {
+#pragma unroll
+            for (int i = 0; i < M; ++i)
+#pragma unroll
+                for (int k1 = 0; k1 < R1; ++k1) {
+                    const C2 r = buf_load(rr, rlane, (R2 * k1 + i) * NP * (int)sizeof(C2), (C2 *)nullptr);
+                    const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
+                    re[i * R1 + k1] = r.x * lr + r.y * li;
+                    im[i * R1 + k1] = r.y * lr - r.x * li;
+                }
+        }
         fft_unit_rev<T, N, true>(re, im, n1, ex, PW, tw, true, PAD);
         const auto rd = make_rsrc(wsi + c.off_inv + (int64_t)Vz * NP, Vz * NP * (int)sizeof(C2));
 #pragma unroll
@@ -1188,7 +1228,7 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
 #pragma unroll
             for (int k1 = 0; k1 < R1; ++k1) {
                 const int k = spec_index<N>(n1, i, k1);
-                const C2 r = buf_load(rr, (k * NP + (ok ? pen : 0)) * (int)sizeof(C2), (C2 *)nullptr);
+                const C2 r = buf_load(rr, G::rs_index(k, ok ? pen : 0) * (int)sizeof(C2), (C2 *)nullptr);
                 const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
                 er[i * R1 + k1] += r.x * lr + r.y * li;  // R * conj(L)
                 ei[i * R1 + k1] += r.y * lr - r.x * li;
@@ -1221,7 +1261,7 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
 #pragma unroll
             for (int k1 = 0; k1 < R1; ++k1) {
                 const int k = spec_index<N>(n1, i, k1);
-                const C2 r = buf_load(rr, (k * NP + (ok ? pen : 0)) * (int)sizeof(C2), (C2 *)nullptr);
+                const C2 r = buf_load(rr, G::rs_index(k, ok ? pen : 0) * (int)sizeof(C2), (C2 *)nullptr);
                 const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
                 re[i * R1 + k1] = r.x * lr + r.y * li;
                 im[i * R1 + k1] = r.y * lr - r.x * li;
@@ -1326,7 +1366,7 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
 #pragma unroll
                 for (int k1 = 0; k1 < R1; ++k1) {
                     const int k = spec_index<N>(n1, i, k1);
-                    const C2 r = buf_load(rr, (k * NP + pr) * (int)sizeof(C2), (C2 *)nullptr);
+                    const C2 r = buf_load(rr, G::rs_index(k, pr) * (int)sizeof(C2), (C2 *)nullptr);
                     const T a = lr[ch][i * R1 + k1], bq = li[ch][i * R1 + k1];
                     er[i * R1 + k1] += r.x * a + r.y * bq;  // R * conj(L)
                     ei[i * R1 + k1] += r.y * a - r.x * bq;
@@ -1359,7 +1399,7 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
 #pragma unroll
                 for (int k1 = 0; k1 < R1; ++k1) {
                     const int k = spec_index<N>(n1, i, k1);
-                    const C2 r = buf_load(rr, (k * NP + pr) * (int)sizeof(C2), (C2 *)nullptr);
+                    const C2 r = buf_load(rr, G::rs_index(k, pr) * (int)sizeof(C2), (C2 *)nullptr);
                     const T a = orr[i * R1 + k1], bq = oi[i * R1 + k1];
                     re[i * R1 + k1] = r.x * a + r.y * bq;
                     im[i * R1 + k1] = r.y * a - r.x * bq;
