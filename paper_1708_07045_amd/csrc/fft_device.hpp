@@ -150,11 +150,19 @@ __device__ __forceinline__ void wave_sync() {
 // wave_sync(), not with a workgroup barrier.  `live` = false makes the unit
 // skip its LDS traffic.
 // ZHI: the inputs x[z], z >= N/2 (slots n2 >= R2/2) are zero and not read.
-template <typename T, int N, bool INV, bool ZHI = false>
+// ROT: element e = b R2 + r of the exchange goes to slot b R2 + (r + b) mod
+// R2 instead of e (pad unused), a rotation inside each block of R2: for an
+// exchange strided through a column of a plane, whose stride puts the
+// blocks the R1 lanes read at once on the same bank, it gives them distinct
+// banks.
+template <typename T, int N, bool INV, bool ZHI = false, bool ROT = false>
 __device__ __forceinline__ void fft_unit(T *re, T *im, int n1, typename Cx<T>::t *ex, int es,
                                          const typename Cx<T>::t *tw, bool live, int pad = 0) {
     using C2 = typename Cx<T>::t;
     constexpr int R1 = Shape<N>::R1, R2 = Shape<N>::R2, M = R2 / R1;
+    auto slot = [&](int e) {
+        return ROT ? ((e / R2) * R2 + (e % R2 + e / R2) % R2) * es : e * es + (e / R2) * pad;
+    };
     dft_reg<R2, INV, T, ZHI>(re, im);
 #pragma unroll
     for (int k2 = 1; k2 < R2; ++k2) cmul_tw(re[k2], im[k2], tw[n1 * k2], INV);
@@ -163,7 +171,7 @@ __device__ __forceinline__ void fft_unit(T *re, T *im, int n1, typename Cx<T>::t
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2) {
             const int e = k2 * R1 + n1;
-            ex[e * es + (e / R2) * pad] = C2{re[k2], im[k2]};
+            ex[slot(e)] = C2{re[k2], im[k2]};
         }
     }
     wave_sync();
@@ -173,7 +181,7 @@ __device__ __forceinline__ void fft_unit(T *re, T *im, int n1, typename Cx<T>::t
 #pragma unroll
             for (int a = 0; a < R1; ++a) {
                 const int e = (n1 * M + i) * R1 + a;
-                C2 v = ex[e * es + (e / R2) * pad];
+                C2 v = ex[slot(e)];
                 re[i * R1 + a] = v.x;
                 im[i * R1 + a] = v.y;
             }

@@ -398,7 +398,7 @@ __device__ void xy_forward(const Fill &fill, int y0, int Ly, typename Cx<T>::t *
             }
         }
         C2 *col = Pl + (live ? c : 0);
-        fft_unit<T, N, false>(re, im, n1, col, S, tw, live);
+        fft_unit<T, N, false, false, true>(re, im, n1, col, S, tw, live);
         wave_sync();  // column c (and column N/2 for c = 0) is private to this unit
         if (live) {
 #pragma unroll
@@ -810,7 +810,7 @@ __device__ void cols_tile(typename Cx<T>::t *__restrict__ plane, int tile, int y
         re[i] = v.x;
         im[i] = v.y;
     }
-    fft_unit<T, N, INV>(re, im, n1, colp, TS, tw, live);
+    fft_unit<T, N, INV, false, true>(re, im, n1, colp, TS, tw, live);
     wave_sync();  // the column is private to this unit
     if (live) {
 #pragma unroll
@@ -1600,7 +1600,7 @@ __global__ __launch_bounds__(NT) void k_inv_xy_lse(const int32_t *__restrict__ i
                 }
             }
             C2 *cp = Pl + (live ? col : 0);
-            fft_unit<T, N, true>(re, im, n1, cp, S, tw, live);
+            fft_unit<T, N, true, false, true>(re, im, n1, cp, S, tw, live);
             wave_sync();  // column col (and N/2 for col = 0) is private to this unit
             if (live) {
 #pragma unroll
