@@ -63,10 +63,14 @@ struct Geo {
     // Receptor spectra, per channel: element (k, pencil).  When a z-kernel
     // lane's outputs come in adjacent pairs k, k + 1 (M = 2) and FP32, the
     // pairs are interleaved per pencil, [k / 2][pencil][2], so one 16-byte
-    // load brings both; otherwise [k][pencil].
+    // load brings both.  Otherwise the PW pencils of a wavefront are kept
+    // together, [pencil / PW][k][PW]: the R1 lanes of a pencil read R1
+    // consecutive k, so each load of a wavefront is one contiguous run.
     static constexpr bool KPAIR = M == 2 && sizeof(T) == 4;
+    static_assert(NP % (64 / R1) == 0, "pencil groups tile the half spectrum");
     __host__ __device__ static constexpr int rs_index(int k, int pen) {
-        return KPAIR ? (k & ~1) * NP + 2 * pen + (k & 1) : k * NP + pen;
+        return KPAIR ? (k & ~1) * NP + 2 * pen + (k & 1)
+                     : ((pen / PW) * N + k) * PW + pen % PW;
     }
     static constexpr int WREG = N * PW + R1 * PAD;
 };
@@ -1022,8 +1026,12 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
     // translation t = z - zo0 mod N.
     constexpr int HZ = R2 / 2;
     const int po = ok ? pen : NP * N;  // out of every descriptor's range
-    // receptor offsets: lane part (VGPR) + uniform part (SGPR)
-    const int rlane = (M * n1 * NP + (G::KPAIR ? 2 : 1) * (ok ? pen : 0)) * (int)sizeof(C2);
+    // receptor offsets: lane part (VGPR) + uniform part (SGPR); element
+    // k = R2 k1 + M n1 + i, uniform part k - M n1 (scaled by the k stride)
+    const int pr0 = ok ? pen : 0;
+    const int rlane = (G::KPAIR ? M * n1 * NP + 2 * pr0 : ((pr0 / PW) * N + M * n1) * PW + pr0 % PW) *
+                      (int)sizeof(C2);
+    constexpr int KS = G::KPAIR ? NP : PW;  // element stride of k outside the pairs
     C2 pf[HZ];
     auto fetch = [&](int ch) {
         if (ch < 3) {
@@ -1060,7 +1068,7 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
 #pragma unroll
             for (int k1 = 0; k1 < R1; ++k1) {
                 // k = R2 k1 + 2 n1 + i, i = 0, 1 in one load
-                const float4 r2 = buf_load4(rr, rlane, R2 * k1 * NP * (int)sizeof(C2));
+                const float4 r2 = buf_load4(rr, rlane, R2 * k1 * KS * (int)sizeof(C2));
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
                     const T rx = i ? r2.z : r2.x, ry = i ? r2.w : r2.y;
@@ -1075,7 +1083,7 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
 #pragma unroll
                 for (int k1 = 0; k1 < R1; ++k1) {
                     // k = R2 k1 + M n1 + i: the lane part in the VGPR offset
-                    const C2 r = buf_load(rr, rlane, (R2 * k1 + i) * NP * (int)sizeof(C2), (C2 *)nullptr);
+                    const C2 r = buf_load(rr, rlane, (R2 * k1 + i) * KS * (int)sizeof(C2), (C2 *)nullptr);
                     const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
                     er[i * R1 + k1] += r.x * lr + r.y * li;  // R * conj(L)
                     ei[i * R1 + k1] += r.y * lr - r.x * li;
@@ -1117,7 +1125,7 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
         if constexpr (G::KPAIR) {
 #pragma unroll
             for (int k1 = 0; k1 < R1; ++k1) {
-                const float4 r2 = buf_load4(rr, rlane, R2 * k1 * NP * (int)sizeof(C2));
+                const float4 r2 = buf_load4(rr, rlane, R2 * k1 * KS * (int)sizeof(C2));
 #pragma unroll
                 for (int i = 0; i < 2; ++i) {
                     const T rx = i ? r2.z : r2.x, ry = i ? r2.w : r2.y;
@@ -1131,7 +1139,7 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
             for (int i = 0; i < M; ++i)
 #pragma unroll
                 for (int k1 = 0; k1 < R1; ++k1) {
-                    const C2 r = buf_load(rr, rlane, (R2 * k1 + i) * NP * (int)sizeof(C2), (C2 *)nullptr);
+                    const C2 r = buf_load(rr, rlane, (R2 * k1 + i) * KS * (int)sizeof(C2), (C2 *)nullptr);
                     const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
                     re[i * R1 + k1] = r.x * lr + r.y * li;
                     im[i * R1 + k1] = r.y * lr - r.x * li;
