@@ -60,16 +60,16 @@ struct Geo {
     // (N = 32 keeps 8: its 16 pencils per wave already spread the offsets).
     static constexpr int PW = 64 / R1;
     static constexpr int PAD = R1 == 16 ? 4 : 8;
-    // Receptor spectra, per channel: element (k, pencil).  When a z-kernel
-    // lane's outputs come in adjacent pairs k, k + 1 (M = 2) and FP32, the
-    // pairs are interleaved per pencil, [k / 2][pencil][2], so one 16-byte
-    // load brings both.  Otherwise the PW pencils of a wavefront are kept
-    // together, [pencil / PW][k][PW]: the R1 lanes of a pencil read R1
-    // consecutive k, so each load of a wavefront is one contiguous run.
+    // Receptor spectra, per channel: element (k, pencil), with the PW
+    // pencils of a z-kernel wavefront kept together, [pencil / PW][k][PW]:
+    // the R1 lanes of a pencil read consecutive k, so each receptor load of
+    // a wavefront is one contiguous run.  When a lane's outputs come in
+    // adjacent pairs k, k + 1 (M = 2) and FP32, the pairs are interleaved,
+    // [pencil / PW][k / 2][PW][2], so one 16-byte load brings both.
     static constexpr bool KPAIR = M == 2 && sizeof(T) == 4;
     static_assert(NP % (64 / R1) == 0, "pencil groups tile the half spectrum");
     __host__ __device__ static constexpr int rs_index(int k, int pen) {
-        return KPAIR ? (k & ~1) * NP + 2 * pen + (k & 1)
+        return KPAIR ? ((pen / PW) * (N / 2) + k / 2) * (2 * PW) + 2 * (pen % PW) + (k & 1)
                      : ((pen / PW) * N + k) * PW + pen % PW;
     }
     static constexpr int WREG = N * PW + R1 * PAD;
@@ -1029,9 +1029,10 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
     // receptor offsets: lane part (VGPR) + uniform part (SGPR); element
     // k = R2 k1 + M n1 + i, uniform part k - M n1 (scaled by the k stride)
     const int pr0 = ok ? pen : 0;
-    const int rlane = (G::KPAIR ? M * n1 * NP + 2 * pr0 : ((pr0 / PW) * N + M * n1) * PW + pr0 % PW) *
+    const int rlane = (G::KPAIR ? ((pr0 / PW) * (N / 2) + n1) * (2 * PW) + 2 * (pr0 % PW)
+                                : ((pr0 / PW) * N + M * n1) * PW + pr0 % PW) *
                       (int)sizeof(C2);
-    constexpr int KS = G::KPAIR ? NP : PW;  // element stride of k outside the pairs
+    constexpr int KS = PW;  // element stride of k outside the pairs
     C2 pf[HZ];
     auto fetch = [&](int ch) {
         if (ch < 3) {
