@@ -933,6 +933,53 @@ __global__ __launch_bounds__(NT) void k_rec_cols(int n_rec, const typename Cx<T>
     cols_tile<T, N, false>(rxy + (int64_t)plane * Geo<T, N>::NP, tile, 0, n_rec, N, tb, tw);
 }
 
+// Receptor-spectrum reads of the z kernel.  Lane n1 of pencil pr0 holds the
+// spectral slots i R1 + k1, k = R2 k1 + M n1 + i; rs_lane is the lane part of
+// their offsets (bytes), the rest is wave-uniform and travels in the SGPR
+// offset.  rprod forms R * conj(L) of one channel for all slots: ACC adds
+// it to (er, ei), otherwise it overwrites (lr, li) in place.
+template <typename T, int N>
+__device__ __forceinline__ int rs_lane(int n1, int pr0) {
+    using G = Geo<T, N>;
+    constexpr int PW = G::PW;
+    return (G::KPAIR ? ((pr0 / PW) * (N / 2) + n1) * (2 * PW) + 2 * (pr0 % PW)
+                     : ((pr0 / PW) * N + G::M * n1) * PW + pr0 % PW) *
+           (int)sizeof(typename Cx<T>::t);
+}
+
+template <typename T, int N, bool ACC>
+__device__ __forceinline__ void rprod(__amdgpu_buffer_rsrc_t rr, int rlane, T *lr, T *li, T *er, T *ei) {
+    using G = Geo<T, N>;
+    using C2 = typename Cx<T>::t;
+    constexpr int R1 = G::R1, R2 = G::R2, M = G::M, KS = G::PW;  // KS: element stride of k
+    auto put = [&](int sl, T rx, T ry) {
+        const T a = lr[sl], b = li[sl];
+        if (ACC) {
+            er[sl] += rx * a + ry * b;
+            ei[sl] += ry * a - rx * b;
+        } else {
+            lr[sl] = rx * a + ry * b;
+            li[sl] = ry * a - rx * b;
+        }
+    };
+    if constexpr (G::KPAIR) {
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) {
+            const float4 r2 = buf_load4(rr, rlane, R2 * k1 * KS * (int)sizeof(C2));  // k and k + 1
+            put(k1, r2.x, r2.y);
+            put(R1 + k1, r2.z, r2.w);
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < M; ++i)
+#pragma unroll
+            for (int k1 = 0; k1 < R1; ++k1) {
+                const C2 r = buf_load(rr, rlane, (R2 * k1 + i) * KS * (int)sizeof(C2), (C2 *)nullptr);
+                put(i * R1 + k1, r.x, r.y);
+            }
+    }
+}
+
 // Placed ligand atom as the fused energy transform uses it.
 template <typename T>
 struct DAtom {
@@ -971,7 +1018,7 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
                                                int n_snap, int64_t spec_stride, int64_t inv_stride) {
     using C2 = typename Cx<T>::t;
     using G = Geo<T, N>;
-    constexpr int R1 = G::R1, R2 = G::R2, M = G::M, P = G::U, NP = G::NP, H = G::H;
+    constexpr int R1 = G::R1, R2 = G::R2, P = G::U, NP = G::NP, H = G::H;
     constexpr int AC = 64;  // atoms per XY table chunk
     constexpr int PW = G::PW, PAD = G::PAD;
     __shared__ C2 buf[4 * G::WREG];
@@ -1007,6 +1054,7 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
     C2 *ex = wbuf + zl.pl;
     const int pen = tile * P + p;
     const bool ok = pen < NP;
+    const int rlane = rs_lane<T, N>(n1, ok ? pen : 0);  // receptor offsets, lane part
     const int nchunk = EDIRECT ? (c.n_atoms + AC - 1) / AC : 0;
     // ZH (launch-wide) > 0: every configuration's energy planes lie in
     // [0, N/2), so the upper half of the z inputs is zero: not loaded, first
@@ -1026,13 +1074,6 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
     // translation t = z - zo0 mod N.
     constexpr int HZ = R2 / 2;
     const int po = ok ? pen : NP * N;  // out of every descriptor's range
-    // receptor offsets: lane part (VGPR) + uniform part (SGPR); element
-    // k = R2 k1 + M n1 + i, uniform part k - M n1 (scaled by the k stride)
-    const int pr0 = ok ? pen : 0;
-    const int rlane = (G::KPAIR ? ((pr0 / PW) * (N / 2) + n1) * (2 * PW) + 2 * (pr0 % PW)
-                                : ((pr0 / PW) * N + M * n1) * PW + pr0 % PW) *
-                      (int)sizeof(C2);
-    constexpr int KS = PW;  // element stride of k outside the pairs
     C2 pf[HZ];
     auto fetch = [&](int ch) {
         if (ch < 3) {
@@ -1064,32 +1105,7 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
         }
         if (ch < 2 || OCC) fetch(ch + 1);
         fft_unit<T, N, false, true>(re, im, n1, ex, PW, tw, true, PAD);
-        const auto rr = make_rsrc(rspec + (int64_t)ch * N * NP, N * NP * (int)sizeof(C2));
-        if constexpr (G::KPAIR) {
-#pragma unroll
-            for (int k1 = 0; k1 < R1; ++k1) {
-                // k = R2 k1 + 2 n1 + i, i = 0, 1 in one load
-                const float4 r2 = buf_load4(rr, rlane, R2 * k1 * KS * (int)sizeof(C2));
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    const T rx = i ? r2.z : r2.x, ry = i ? r2.w : r2.y;
-                    const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
-                    er[i * R1 + k1] += rx * lr + ry * li;  // R * conj(L)
-                    ei[i * R1 + k1] += ry * lr - rx * li;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < M; ++i)
-#pragma unroll
-                for (int k1 = 0; k1 < R1; ++k1) {
-                    // k = R2 k1 + M n1 + i: the lane part in the VGPR offset
-                    const C2 r = buf_load(rr, rlane, (R2 * k1 + i) * KS * (int)sizeof(C2), (C2 *)nullptr);
-                    const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
-                    er[i * R1 + k1] += r.x * lr + r.y * li;  // R * conj(L)
-                    ei[i * R1 + k1] += r.y * lr - r.x * li;
-                }
-        }
+        rprod<T, N, true>(make_rsrc(rspec + (int64_t)ch * N * NP, N * NP * (int)sizeof(C2)), rlane, re, im, er, ei);
     }
     const int Vz = c.V[2];
     fft_unit_rev<T, N, true>(er, ei, n1, ex, PW, tw, true, PAD);
@@ -1100,6 +1116,7 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
         for (int i = 0; i < R2; ++i)
             buf_store(rd, ((n1 + R1 * i) * NP + po) * (int)sizeof(C2), C2{er[i], ei[i]});
     }
+    // the energy stores are issued before any occupancy work is scheduled
     __builtin_amdgcn_sched_barrier(0);
     if (OCC) {
         T re[R2], im[R2];
@@ -1122,30 +1139,8 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
             }
             fft_unit<T, N, false>(re, im, n1, ex, PW, tw, true, PAD);
         }
-        const auto rr = make_rsrc(rspec + (int64_t)3 * N * NP, N * NP * (int)sizeof(C2));
-        if constexpr (G::KPAIR) {
-#pragma unroll
-            for (int k1 = 0; k1 < R1; ++k1) {
-                const float4 r2 = buf_load4(rr, rlane, R2 * k1 * KS * (int)sizeof(C2));
-#pragma unroll
-                for (int i = 0; i < 2; ++i) {
-                    const T rx = i ? r2.z : r2.x, ry = i ? r2.w : r2.y;
-                    const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
-                    re[i * R1 + k1] = rx * lr + ry * li;
-                    im[i * R1 + k1] = ry * lr - rx * li;
-                }
-            }
-        } else {
-#pragma unroll
-            for (int i = 0; i < M; ++i)
-#pragma unroll
-                for (int k1 = 0; k1 < R1; ++k1) {
-                    const C2 r = buf_load(rr, rlane, (R2 * k1 + i) * KS * (int)sizeof(C2), (C2 *)nullptr);
-                    const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
-                    re[i * R1 + k1] = r.x * lr + r.y * li;
-                    im[i * R1 + k1] = r.y * lr - r.x * li;
-                }
-        }
+        rprod<T, N, false>(make_rsrc(rspec + (int64_t)3 * N * NP, N * NP * (int)sizeof(C2)), rlane, re, im, nullptr,
+                           nullptr);
         fft_unit_rev<T, N, true>(re, im, n1, ex, PW, tw, true, PAD);
         const auto rd = make_rsrc(wsi + c.off_inv + (int64_t)Vz * NP, Vz * NP * (int)sizeof(C2));
 #pragma unroll
@@ -1231,17 +1226,7 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
             }
         }
         fft_unit<T, N, false, half>(re, im, n1, ex, PW, tw, true, PAD);
-        const auto rr = make_rsrc(rspec + (int64_t)ch * N * NP, N * NP * (int)sizeof(C2));
-#pragma unroll
-        for (int i = 0; i < M; ++i)
-#pragma unroll
-            for (int k1 = 0; k1 < R1; ++k1) {
-                const int k = spec_index<N>(n1, i, k1);
-                const C2 r = buf_load(rr, G::rs_index(k, ok ? pen : 0) * (int)sizeof(C2), (C2 *)nullptr);
-                const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
-                er[i * R1 + k1] += r.x * lr + r.y * li;  // R * conj(L)
-                ei[i * R1 + k1] += r.y * lr - r.x * li;
-            }
+        rprod<T, N, true>(make_rsrc(rspec + (int64_t)ch * N * NP, N * NP * (int)sizeof(C2)), rlane, re, im, er, ei);
     }
     const int Vz = c.V[2];
     const int po = ok ? pen : NP * N;  // out of every descriptor's range
@@ -1264,17 +1249,8 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
             im[i] = v.y;
         }
         fft_unit<T, N, false>(re, im, n1, ex, PW, tw, true, PAD);
-        const auto rr = make_rsrc(rspec + (int64_t)3 * N * NP, N * NP * (int)sizeof(C2));
-#pragma unroll
-        for (int i = 0; i < M; ++i)
-#pragma unroll
-            for (int k1 = 0; k1 < R1; ++k1) {
-                const int k = spec_index<N>(n1, i, k1);
-                const C2 r = buf_load(rr, G::rs_index(k, ok ? pen : 0) * (int)sizeof(C2), (C2 *)nullptr);
-                const T lr = re[i * R1 + k1], li = im[i * R1 + k1];
-                re[i * R1 + k1] = r.x * lr + r.y * li;
-                im[i * R1 + k1] = r.y * lr - r.x * li;
-            }
+        rprod<T, N, false>(make_rsrc(rspec + (int64_t)3 * N * NP, N * NP * (int)sizeof(C2)), rlane, re, im, nullptr,
+                           nullptr);
         fft_unit_rev<T, N, true>(re, im, n1, ex, PW, tw, true, PAD);
         const auto rd = make_rsrc(wsi + c.off_inv + (int64_t)Vz * NP, Vz * NP * (int)sizeof(C2));
 #pragma unroll
@@ -1361,7 +1337,6 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
     }
     const int Vz = c.V[2];
     const int po = ok ? pen : NP * N;  // out of every descriptor's range
-    const int pr = ok ? pen : 0;
 #pragma unroll 1
     for (int sn = 0; sn < n_snap; ++sn) {
         T er[R2], ei[R2];
@@ -1369,17 +1344,8 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
         for (int i = 0; i < R2; ++i) er[i] = ei[i] = (T)0;
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
-            const auto rr = make_rsrc(rspec + sn * spec_stride + (int64_t)ch * N * NP, N * NP * (int)sizeof(C2));
-#pragma unroll
-            for (int i = 0; i < M; ++i)
-#pragma unroll
-                for (int k1 = 0; k1 < R1; ++k1) {
-                    const int k = spec_index<N>(n1, i, k1);
-                    const C2 r = buf_load(rr, G::rs_index(k, pr) * (int)sizeof(C2), (C2 *)nullptr);
-                    const T a = lr[ch][i * R1 + k1], bq = li[ch][i * R1 + k1];
-                    er[i * R1 + k1] += r.x * a + r.y * bq;  // R * conj(L)
-                    ei[i * R1 + k1] += r.y * a - r.x * bq;
-                }
+            rprod<T, N, true>(make_rsrc(rspec + sn * spec_stride + (int64_t)ch * N * NP, N * NP * (int)sizeof(C2)),
+                              rlane, lr[ch], li[ch], er, ei);
         }
         fft_unit_rev<T, N, true>(er, ei, n1, ex, PW, tw, true, PAD);
         // valid z-translations only: tz >= Vz lies beyond the descriptor
@@ -1402,17 +1368,13 @@ __global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, c
 #pragma unroll 1
         for (int sn = 0; sn < n_snap; ++sn) {
             T re[R2], im[R2];
-            const auto rr = make_rsrc(rspec + sn * spec_stride + (int64_t)3 * N * NP, N * NP * (int)sizeof(C2));
 #pragma unroll
-            for (int i = 0; i < M; ++i)
-#pragma unroll
-                for (int k1 = 0; k1 < R1; ++k1) {
-                    const int k = spec_index<N>(n1, i, k1);
-                    const C2 r = buf_load(rr, G::rs_index(k, pr) * (int)sizeof(C2), (C2 *)nullptr);
-                    const T a = orr[i * R1 + k1], bq = oi[i * R1 + k1];
-                    re[i * R1 + k1] = r.x * a + r.y * bq;
-                    im[i * R1 + k1] = r.y * a - r.x * bq;
-                }
+            for (int i = 0; i < R2; ++i) {
+                re[i] = orr[i];
+                im[i] = oi[i];
+            }
+            rprod<T, N, false>(make_rsrc(rspec + sn * spec_stride + (int64_t)3 * N * NP, N * NP * (int)sizeof(C2)),
+                               rlane, re, im, nullptr, nullptr);
             fft_unit_rev<T, N, true>(re, im, n1, ex, PW, tw, true, PAD);
             const auto rd =
                 make_rsrc(wsi + sn * inv_stride + c.off_inv + (int64_t)Vz * NP, Vz * NP * (int)sizeof(C2));
@@ -1481,7 +1443,7 @@ __device__ __forceinline__ uint32_t row_pair_epilogue(T *re, T *im, int n1, int 
                                                       bool occ_pass, uint32_t clash, T inv_n3, T beta,
                                                       T *__restrict__ psi_out, uint8_t *__restrict__ clash_out,
                                                       LseAcc<T> &acc, uint32_t &valid) {
-    constexpr int R1 = Shape<N>::R1, R2 = Shape<N>::R2, M = R2 / R1;
+    constexpr int R1 = Shape<N>::R1, R2 = Shape<N>::R2;
     static_assert(2 * R2 <= 32, "one flag word per row pair");
     // slot s = i R1 + k1; value of (x, y + h) in (h ? im : re)[s]; bit 2 s + h
     uint32_t vb = 0;
@@ -1862,7 +1824,7 @@ __global__ __launch_bounds__(NT) void k_inv_rows_lse(const int32_t *__restrict__
                                                       unsigned int *__restrict__ e_count) {
     using C2 = typename Cx<T>::t;
     using SG = Split<T, N>;
-    constexpr int R1 = SG::R1, R2 = SG::R2, M = SG::M, U = SG::U, H = SG::H;
+    constexpr int R1 = SG::R1, R2 = SG::R2, U = SG::U, H = SG::H;
     __shared__ C2 reg_all[SG::U * SG::XREG];
     __shared__ C2 tw[N];
     constexpr int MAXR = (N / 2 + U - 1) / U;  // rounds of row pairs
