@@ -242,7 +242,10 @@ def configs_needed(args):
     S = w.receptor.n_snap
     log(f"configs needed: {len(w.ligands)} ligands, {b.n_cfg} configurations x {S} snapshots")
     ctx_f = prop.make_context(w)
-    ctx_c = prop.make_context(w, prop.coarse_desc(w))
+    # coarse pre-scan at twice the spacing against every snapshot (with
+    # --is-coarse-first-snapshot: the first one only, ten times cheaper, but
+    # its ranking does not carry over to the other jittered snapshots)
+    ctx_c = prop.make_context(w, prop.coarse_desc(w), snapshots=args.is_coarse_snapshots)
     ctx_f.autotune(b, T, max_cfgs=2048)
     ctx_c.autotune(b, T, max_cfgs=2048)
 
@@ -339,6 +342,7 @@ def configs_needed(args):
                      "cost = distinct fine-scanned configurations (+ coarse pre-scan at its cost ratio)",
         "replicates": args.is_reps,
         "coarse_cost_ratio": rho,
+        "coarse_snapshots": w.receptor.n_snap if args.is_coarse_snapshots is None else len(args.is_coarse_snapshots),
         "mixture_alpha": alpha,
         "mixture_tau_nats": tau_of,
         "train_seconds": t_train,
@@ -384,7 +388,10 @@ def main():
     ap.add_argument("--is-epochs", type=int, default=20)
     ap.add_argument("--is-tune-ligands", type=int, default=12)
     ap.add_argument("--is-detail", default="", help="write per-ligand configurations-needed results here (JSON)")
+    ap.add_argument("--is-coarse-first-snapshot", action="store_true",
+                    help="coarse pre-scan against the first snapshot only")
     args = ap.parse_args()
+    args.is_coarse_snapshots = [0] if args.is_coarse_first_snapshot else None
     if args.gpus != 1:
         print(f"bench.py: this implementation runs on one GPU; --gpus {args.gpus} is not supported "
               "(the scan would shard by ligand, snapshot and configuration chunk)", file=sys.stderr)

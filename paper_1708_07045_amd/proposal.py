@@ -43,22 +43,25 @@ def coarse_desc(w, factor: int = 2) -> dict:
     return dict(n_rec=n_rec, n_fft=w.n_fft // factor, h=h, origin=centre - 0.5 * (n_rec - 1) * h)
 
 
-def make_context(w, grid: Optional[dict] = None, device: int = 0):
-    """Context with receptor grids of every snapshot built and set."""
+def make_context(w, grid: Optional[dict] = None, device: int = 0, snapshots=None):
+    """Context with receptor grids of every snapshot (or of the listed ones,
+    equally weighted) built and set."""
     import torch
     g = dict(n_rec=w.n_rec, n_fft=w.n_fft, h=w.h, origin=w.origin)
     if grid:
         g.update(grid)
     ctx = fd.FFTDG(g["n_rec"], g["n_fft"], g["h"], g["origin"], w.precision, w.clash_mode, w.ljr_cap, w.occ_f,
                    device)
+    snaps = list(range(w.receptor.n_snap)) if snapshots is None else list(snapshots)
     gl, ol = [], []
-    for s in range(w.receptor.n_snap):
+    for s in snaps:
         gg, oo = ctx.receptor_grids(w.receptor.xyz[s], w.receptor.q, w.receptor.sigma, w.receptor.eps)
         gl.append(gg)
         ol.append(oo)
     grids = torch.stack(gl).contiguous()
     occ = torch.stack(ol).contiguous() if w.clash_mode == "occ" else None
-    ctx.set_receptors(grids, occ, w.receptor.weights)
+    wts = w.receptor.weights if snapshots is None else np.full(len(snaps), 1.0 / len(snaps))
+    ctx.set_receptors(grids, occ, wts)
     ctx._grids = (grids, occ)
     return ctx
 
