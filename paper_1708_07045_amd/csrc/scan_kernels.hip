@@ -1530,7 +1530,7 @@ __global__ __launch_bounds__(NT) void k_inv_xy_lse(const int32_t *__restrict__ i
     static_assert(N + (R1 - 1) * G::RPAD <= 2 * S, "row-pair exchange must fit in two rows");
     __shared__ C2 Pl[N * S];
     __shared__ C2 tw[N];
-    __shared__ uint32_t cflags[MAXR * NT];  // per thread and round: clash flags of its outputs
+    __shared__ uint32_t cflags[MAXR * NT];  // per thread and round: its outputs not folded in
     __shared__ LseAcc<T> red[NT];
     const int ic = find_cfg(inv_off, n_cfg, (int)blockIdx.x);
     const CfgDev c = cfgs[ic];
@@ -1597,6 +1597,11 @@ __global__ __launch_bounds__(NT) void k_inv_xy_lse(const int32_t *__restrict__ i
         for (int rd = 0; rd < rounds_a; ++rd) {
             const int y = 2 * (unit + U * rd);
             const bool live = y < Vy;
+            // energy pass of a scan: a wavefront whose row pairs hold no
+            // clash-free valid translation has nothing to add
+            if (OCC && och == 0 && !psi_out && !clash_out &&
+                !__any(live && cflags[rd * NT + threadIdx.x] != ~0u))
+                continue;
             C2 *row = Pl + (live ? y * S : 0);
 #pragma unroll
             for (int i = 0; i < R2; ++i) {
@@ -1615,13 +1620,15 @@ __global__ __launch_bounds__(NT) void k_inv_xy_lse(const int32_t *__restrict__ i
             }
             fft_unit<T, N, true>(re, im, n1, row, 1, tw, live, G::RPAD);
             if (live) {
-                uint32_t &cw = cflags[rd * NT + threadIdx.x];  // written and read by this thread only
+                // per thread and round: the outputs NOT to fold in (invalid or
+                // clashing); written and read by this thread only
+                uint32_t &cw = cflags[rd * NT + threadIdx.x];
                 uint32_t vb;
                 const uint32_t f = row_pair_epilogue<T, N, OCC>(re, im, n1, y, Vx, Vy, tz, OCC && och == 1,
                                                                 (OCC && och == 0) ? cw : 0u, inv_n3, beta, psi_out,
                                                                 clash_out, acc, vb);
                 if (OCC && och == 1) {
-                    cw = f;
+                    cw = ~(vb & ~f);
                     any_free |= (vb & ~f) != 0u;
                 }
             }
