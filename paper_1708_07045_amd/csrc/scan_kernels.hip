@@ -1427,6 +1427,37 @@ struct LseAcc {
     }
 };
 
+// Workgroup reduction of the per-thread partials in a fixed tree: a
+// butterfly over the lanes of each wavefront (shuffles, no barrier), then
+// thread 0 merges the wavefronts' results in order and stores the plane
+// partial.  red holds one entry per wavefront.
+template <typename T>
+__device__ __forceinline__ void block_partial_store(LseAcc<T> a, LseAcc<T> *red, PlanePartial<T> *out) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        LseAcc<T> o;
+        o.m = __shfl_xor(a.m, off);
+        o.s = __shfl_xor(a.s, off);
+        o.pmin = __shfl_xor(a.pmin, off);
+        o.n = __shfl_xor(a.n, off);
+        o.amin = __shfl_xor(a.amin, off);
+        a.merge(o);
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        LseAcc<T> r = red[0];
+        for (int w = 1; w < NT / 64; ++w) r.merge(red[w]);
+        PlanePartial<T> o;
+        o.m = r.m;
+        o.s = r.s;
+        o.psi_min = r.pmin;
+        o.n_finite = r.n;
+        o.argmin = r.amin;
+        *out = o;
+    }
+}
+
 __device__ __forceinline__ float lse_exp(float d) { return __builtin_amdgcn_exp2f(d * 1.4426950408889634f); }
 __device__ __forceinline__ double lse_exp(double d) { return exp(d); }
 
@@ -1531,7 +1562,7 @@ __global__ __launch_bounds__(NT) void k_inv_xy_lse(const int32_t *__restrict__ i
     __shared__ C2 Pl[N * S];
     __shared__ C2 tw[N];
     __shared__ uint32_t cflags[MAXR * NT];  // per thread and round: its outputs not folded in
-    __shared__ LseAcc<T> red[NT];
+    __shared__ LseAcc<T> red[NT / 64];
     const int ic = find_cfg(inv_off, n_cfg, (int)blockIdx.x);
     const CfgDev c = cfgs[ic];
     const int Vx = c.V[0], Vy = c.V[1], Vz = c.V[2], tz = (int)blockIdx.x - inv_off[ic];
@@ -1634,27 +1665,7 @@ __global__ __launch_bounds__(NT) void k_inv_xy_lse(const int32_t *__restrict__ i
             }
         }
     }
-    // workgroup reduction in a fixed tree
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = NT / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            LseAcc<T> a = red[threadIdx.x];
-            a.merge(red[threadIdx.x + w]);
-            red[threadIdx.x] = a;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const LseAcc<T> a = red[0];
-        PlanePartial<T> o;
-        o.m = a.m;
-        o.s = a.s;
-        o.psi_min = a.pmin;
-        o.n_finite = a.n;
-        o.argmin = a.amin;
-        pp[c.pp_base + tz] = o;
-    }
+    block_partial_store(acc, red, pp + c.pp_base + tz);
 }
 
 // Per configuration: merge its plane partials (fixed order, working precision).
@@ -1836,7 +1847,7 @@ __global__ __launch_bounds__(NT) void k_inv_rows_lse(const int32_t *__restrict__
     __shared__ C2 tw[N];
     constexpr int MAXR = (N / 2 + U - 1) / U;  // rounds of row pairs
     __shared__ uint32_t cflags[MAXR * NT];     // per thread and round: clash flags of its outputs
-    __shared__ LseAcc<T> red[NT];
+    __shared__ LseAcc<T> red[NT / 64];
     const int ic = find_cfg(inv_off, n_cfg, (int)blockIdx.x);
     const CfgDev c = cfgs[ic];
     const int Vx = c.V[0], Vy = c.V[1], Vz = c.V[2], tz = (int)blockIdx.x - inv_off[ic];
@@ -1901,26 +1912,7 @@ __global__ __launch_bounds__(NT) void k_inv_rows_lse(const int32_t *__restrict__
             wave_sync();
         }
     }
-    red[threadIdx.x] = acc;
-    __syncthreads();
-    for (int w = NT / 2; w > 0; w >>= 1) {
-        if (threadIdx.x < w) {
-            LseAcc<T> a = red[threadIdx.x];
-            a.merge(red[threadIdx.x + w]);
-            red[threadIdx.x] = a;
-        }
-        __syncthreads();
-    }
-    if (threadIdx.x == 0) {
-        const LseAcc<T> a = red[0];
-        PlanePartial<T> o;
-        o.m = a.m;
-        o.s = a.s;
-        o.psi_min = a.pmin;
-        o.n_finite = a.n;
-        o.argmin = a.amin;
-        pp[c.pp_base + tz] = o;
-    }
+    block_partial_store(acc, red, pp + c.pp_base + tz);
 }
 
 // Per-configuration descriptors of a finished scan (inputs of the learned
