@@ -1,0 +1,66 @@
+"""Bookkeeping of the benchmark line (CPU only): the z pass's algorithmic
+flops, the FP32 vector peak it is rated against, and the recorded HBM
+traffic, which applies only while the kernel sources match."""
+import importlib.util
+import math
+import os
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_vector_peak_from_unit_counts(bench):
+    # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
+    assert bench.VALU_FP32_PEAK_TFLOPS == pytest.approx(78.6432)
+    assert bench.VALU_FP32_PACKED_PEAK_TFLOPS == pytest.approx(157.2864)
+
+
+def test_zpass_flops_count(bench):
+    N = 128
+    pencils = N * (N // 2 + 1)
+    t = 5 * N * math.log2(N)
+    # occupancy mode: 4 forward + 2 inverse transforms, 3 x 8 + 6 flops per point
+    want = pencils * (6 * t + N * 30)
+    assert bench.zpass_flops(N, True, 1, 1, 1) == pytest.approx(want)
+    assert bench.zpass_flops(N, True, 1, 1, 1) == pytest.approx(255.5904e6)
+    # cap mode: 3 forward + 1 inverse, 3 x 8 flops per point
+    assert bench.zpass_flops(N, False, 1, 1, 1) == pytest.approx(pencils * (4 * t + N * 24))
+    # linear in configurations; forward transforms shared by the snapshots of a pass
+    assert bench.zpass_flops(N, True, 10, 1, 1) == pytest.approx(10 * want)
+    one_pass = bench.zpass_flops(N, True, 1, 4, 4)
+    per_snap = bench.zpass_flops(N, True, 1, 4, 1)
+    assert one_pass == pytest.approx(per_snap - 3 * pencils * 4 * t)
+
+
+def test_recorded_traffic_follows_sources_and_schedule(bench, tmp_path, monkeypatch):
+    prof = tmp_path / "traffic.md"
+    digest = bench.kernel_source_digest()
+    prof.write_text("\n".join([
+        "# summary", "", f"- hbm_bytes_per_cfg: 1234.5", "- configs_per_chunk: 512", "- energy_xy_direct: 2",
+        f"- kernel_source_sha256: `{digest}`", ""]))
+    monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
+    tun = {"configs_per_chunk": 256, "energy_xy_direct": 2}
+    assert bench.recorded_traffic(tun) == pytest.approx(1234.5)
+    assert bench.recorded_traffic({"configs_per_chunk": 64, "energy_xy_direct": 2}) is None
+    assert bench.recorded_traffic({"configs_per_chunk": 512, "energy_xy_direct": 0}) is None
+    prof.write_text(prof.read_text().replace(digest, "0" * 64))
+    assert bench.recorded_traffic(tun) is None
+
+
+def test_committed_traffic_profile_is_parsable(bench):
+    rec = {}
+    for line in open(bench.TRAFFIC_PROFILE):
+        if line.startswith("- ") and ": " in line:
+            k, v = line[2:].split(": ", 1)
+            rec[k.strip()] = v.strip().strip("`")
+    assert float(rec["hbm_bytes_per_cfg"]) > 1e6
+    assert len(rec["kernel_source_sha256"]) == 64
