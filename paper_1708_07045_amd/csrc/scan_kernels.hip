@@ -1464,11 +1464,14 @@ __device__ __forceinline__ double lse_exp(double d) { return exp(d); }
 // Outputs of one lane after the C2R transform of storage rows (y, y+1):
 // slot (i R1 + k1) holds x = spec_index(n1, i, k1) of row y in re and of
 // row y+1 in im.  Flag bit (i R1 + k1) * 2 + h stands for (x, y + h).
-// The occupancy pass returns the clash flags (C >= 1/2, Eq. 10) of the
-// valid translations; the energy pass exports if asked and folds the
-// clash-free values into the Eq. 2 partial in two sweeps over registers
-// (local maximum of -beta psi, then the sum of exponentials), keeping the
-// lowest linear index among equal minima.
+// The energies and occupancies are scaled by inv_n3 in place.  `valid`
+// receives the bits of the box-valid translations.  The occupancy pass
+// returns the clash flags (C >= 1/2, Eq. 10) of the valid translations; the
+// energy pass takes in `clash` the translations to leave out (bits outside
+// `valid` are ignored), exports if asked, and folds the rest into the Eq. 2
+// partial in two sweeps over registers (the minimum energy, whose -beta
+// multiple is the largest exponent, then the sum of exponentials), keeping
+// the lowest linear index among equal minima.
 template <typename T, int N, bool OCC>
 __device__ __forceinline__ uint32_t row_pair_epilogue(T *re, T *im, int n1, int y, int Vx, int Vy, int tz,
                                                       bool occ_pass, uint32_t clash, T inv_n3, T beta,
