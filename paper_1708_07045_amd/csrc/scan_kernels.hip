@@ -1007,9 +1007,13 @@ struct DAtom {
 // along z, store the valid z-translations only.  The ligand's forward
 // spectra stay in registers while the product and inverse run for each of
 // n_snap receptor snapshots (spectra spec_stride apart, outputs inv_stride
-// apart).
+// apart).  The 128-point FP32 long-window instantiation (ZH == 2) is held to
+// 3 waves per SIMD (168 VGPRs, no spills), the occupancy of the common one;
+// the allocator would otherwise take 172 and leave it at 2.
 template <typename T, int N, bool OCC, bool EDIRECT, bool MULTI, int ZH>
-__global__ __launch_bounds__(NT) void k_zprod(const CfgDev *__restrict__ cfgs, const int32_t *__restrict__ zcfg,
+__global__ __launch_bounds__(NT)
+__attribute__((amdgpu_waves_per_eu((ZH == 2 && N == 128 && sizeof(T) == 4 && !EDIRECT && !MULTI) ? 3 : 1)))
+void k_zprod(const CfgDev *__restrict__ cfgs, const int32_t *__restrict__ zcfg,
                                                int nz, int n_tiles, const typename Cx<T>::t *__restrict__ ws,
                                                const typename Cx<T>::t *__restrict__ rspec,
                                                const typename Cx<T>::t *__restrict__ twg,
