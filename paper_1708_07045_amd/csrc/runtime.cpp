@@ -207,13 +207,14 @@ size_t csize() {
 }
 
 struct Plan {
-    // per configuration (batch order)
+    // per configuration (plan order: batch order for a one-configuration
+    // plan, else grouped by z-window class; global_cfg is the batch index)
     std::vector<CfgDev> cfg;
     std::vector<int32_t> U;        // lattice coords, [sum atoms][3]
     std::vector<int32_t> cfg_lig;  // ligand of each configuration
-    // chunks: contiguous configuration ranges
+    // chunks: contiguous ranges of the plan order
     struct Chunk {
-        int c0, c1;               // configurations [c0, c1)
+        int c0, c1;               // plan positions [c0, c1)
         size_t off0;              // start of this chunk's fwd_off / inv_off (c1-c0+1 entries each)
         size_t nfwd, ninv;        // forward planes, valid z translations
         size_t z0, nz;            // scanned configurations (local indices)
@@ -394,6 +395,25 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
         if (!any)
             return set_err(ctx, FFTDG_E_NOVALID, "ligand " + std::to_string(l) +
                                                      " has no box-valid translation in any configuration");
+    }
+    // Plan order.  A chunk gets the pruned z transforms only if every one of
+    // its configurations has its energy planes in [0, n_fft/2), and the
+    // cheaper of those two instantiations only if no occupancy window is
+    // longer than n_fft/2, so configurations are grouped by these two tests
+    // (stable: batch order within a group; unscanned ones last).  Partials
+    // are still written at each configuration's batch index (global_cfg).
+    if (!only_one) {
+        auto group = [&](const CfgDev &d) {
+            if (!d.scanned) return 3;
+            if (!(d.ze0 >= 0 && d.ze0 + d.Le <= N / 2)) return 2;
+            return (occ && d.Lo > N / 2) ? 1 : 0;
+        };
+        std::vector<int> ord(ncfg);
+        for (int i = 0; i < ncfg; ++i) ord[i] = i;
+        std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) { return group(P.cfg[x]) < group(P.cfg[y]); });
+        std::vector<CfgDev> pc(ncfg);
+        for (int i = 0; i < ncfg; ++i) pc[i] = P.cfg[ord[i]];
+        P.cfg.swap(pc);
     }
     // chunks
     const int64_t NP = ctx->ks->np;
