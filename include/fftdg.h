@@ -322,7 +322,7 @@ int fftdg_set_tuning(fftdg_ctx *ctx, const fftdg_tuning *t);
 /* Autotuner: times the candidate schedules (configurations per chunk in
  * {64, 128, 256, 512}, energy_xy_direct in {0, 1, 2}, snapshots_per_pass in
  * {1, n_snap} when there are several snapshots, use_graph in {0, 1}) with
- * HIP events on an evenly
+ * HIP events, each by the fastest of four runs after a warm-up, on an evenly
  * strided sample of at most max_cfgs configurations of the batch (all
  * receptor snapshots), keeps the fastest in the context and writes it to
  * out (may be NULL); ms_host (may be NULL) receives its time per sampled

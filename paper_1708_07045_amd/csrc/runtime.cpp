@@ -1083,7 +1083,7 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
         ctx->snap_group = t.snapshots_per_pass;
         ctx->use_graph = t.use_graph != 0;
         float tmin = INFINITY;
-        for (int rep = 0; rep < 3 && !err; ++rep) {
+        for (int rep = 0; rep < 5 && !err; ++rep) {  // a warm-up run, then the fastest of four
             Plan P;
             if ((err = build_plan(ctx, &bs, false, -1, P))) break;
             if (hipEventRecord(e0, ctx->stream) != hipSuccess) err = FFTDG_E_DEVICE;
