@@ -226,7 +226,7 @@ struct Plan {
     std::vector<int32_t> fwd_off, inv_off;
     std::vector<int32_t> zcfg;
     int64_t max_fwd = 0, max_inv = 0;
-    int max_pp = 0;
+    int64_t total_pp = 0;  // plane partial slots of the whole plan (per snapshot)
 };
 
 int validate_batch(fftdg_ctx *ctx, const fftdg_batch *b) {
@@ -420,6 +420,7 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
     const int nout = occ ? 2 : 1;
     const int64_t limit_c = (int64_t)(ctx->ws_limit / (size_t)ctx->ks->cbytes);
     int c = 0;
+    int64_t ppt = 0;  // plane partial slots of the chunks before this one
     while (c < ncfg) {
         Plan::Chunk ch{};
         ch.c0 = c;
@@ -441,7 +442,7 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
                 if (nscan > 0 && (nscan >= ctx->chunk_cfgs || wf + f + wi + iv > limit_c)) break;
                 d.off_fwd = wf;
                 d.off_inv = wi;
-                d.pp_base = pp;
+                d.pp_base = (int32_t)(ppt + pp);
                 const int local = c - ch.c0;
                 P.fwd_off.push_back(nf);
                 P.inv_off.push_back(ni);
@@ -456,7 +457,7 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
                 ++nscan;
             } else {
                 d.off_fwd = d.off_inv = 0;
-                d.pp_base = pp;
+                d.pp_base = (int32_t)(ppt + pp);
                 d.occ_slot0 = 0;
                 P.fwd_off.push_back(nf);
                 P.inv_off.push_back(ni);
@@ -475,7 +476,9 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
         ch.zhalf = zhalf ? (olong ? 2 : 1) : 0;
         P.max_fwd = std::max(P.max_fwd, wf);
         P.max_inv = std::max(P.max_inv, wi);
-        P.max_pp = std::max(P.max_pp, pp);
+        ppt += pp;
+        if (ppt > INT32_MAX) return set_err(ctx, FFTDG_E_INVALID, "scan: more than 2^31 valid z-translations in one batch");
+        P.total_pp = ppt;
         P.chunks.push_back(ch);
     }
     return FFTDG_OK;
@@ -538,7 +541,10 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     const int grp = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)(s_end - s_begin), room / inv1,
                                                                   (int64_t)ctx->snap_group}));
     if ((rc = reserve(ctx, ctx->ws_inv, cb * (size_t)inv1 * grp))) return rc;
-    if ((rc = reserve(ctx, ctx->pp, (size_t)ctx->ks->ppbytes * (size_t)std::max(P.max_pp, 1)))) return rc;
+    // plane partials of the whole scan, one region per snapshot, merged into
+    // configuration partials once per snapshot after the last chunk
+    const size_t pp_snap = (size_t)ctx->ks->ppbytes * (size_t)std::max<int64_t>(P.total_pp, 1);
+    if ((rc = reserve(ctx, ctx->pp, pp_snap * (size_t)(s_end - s_begin)))) return rc;
     HIPCHK(ctx, hipMemcpyAsync(ctx->tables.p, h, total, hipMemcpyHostToDevice, ctx->stream));
     HIPCHK(ctx, hipEventRecord(ctx->staging_ev, ctx->stream));
     ctx->staging_used = true;
@@ -584,18 +590,22 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
             // inverse xy: occupancy planes always, energy planes only where the
             // plane has a clash-free translation (counted on the device)
             const double b_inv_fixed = (occ ? 0.5 * b_inv : 0.0) + pb * ch.pp;
+            void *pp_s = (char *)ctx->pp.p + pp_snap * (size_t)(s - s_begin);
             HIPCHK(ctx, timed(ctx, FFTDG_K_INV, b_inv_fixed, [&] {
                        return ks->inv(st, occ, dinv + ch.off0, ch.c1 - ch.c0, (int)ch.ninv, ccfg, wsi_s, beta,
-                                      ctx->tw.p, ctx->pp.p, psi_out, clash_out,
+                                      ctx->tw.p, pp_s, psi_out, clash_out,
                                       ctx->prof ? (unsigned int *)ctx->prof_cnt.p : nullptr);
                    }));
-            if (out)
-                HIPCHK(ctx, timed(ctx, FFTDG_K_MERGE, pb * ch.pp + sizeof(fftdg_partial) * (double)(ch.c1 - ch.c0), [&] {
-                           return ks->merge(st, ccfg, ch.c1 - ch.c0, ctx->pp.p, out + (size_t)s * ncfg);
-                       }));
           }
         }
     }
+    if (out)
+        for (int s = s_begin; s < s_end; ++s) {
+            const void *pp_s = (const char *)ctx->pp.p + pp_snap * (size_t)(s - s_begin);
+            HIPCHK(ctx, timed(ctx, FFTDG_K_MERGE, pb * (double)P.total_pp + sizeof(fftdg_partial) * (double)ncfg, [&] {
+                       return ks->merge(st, dcfg, ncfg, pp_s, out + (size_t)s * ncfg);
+                   }));
+        }
     return FFTDG_OK;
     };
     const bool graph_ok = ctx->use_graph && !ctx->prof && !psi_out && !clash_out && out;
