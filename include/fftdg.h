@@ -171,7 +171,10 @@ int fftdg_set_receptors(fftdg_ctx *ctx, int32_t n_snap, const void *grids_dev,
  * FP64, exact integer box), runs the FFT correlation against every receptor
  * snapshot and writes out_dev[snap * n_cfg_total + c] (device) for all
  * snapshots and configurations.  Temperature T_K > 0.  Asynchronous: keep
- * out_dev alive until the stream passes this call.
+ * out_dev alive until the stream passes this call.  Besides the chunk
+ * workspaces the context holds one plane partial (20 B in FP32, 32 B in
+ * FP64) per valid z-translation of the batch and snapshot until the scan's
+ * final merge; E_INVALID if a batch has more than 2^31 of them per snapshot.
  * Errors: E_STATE (no receptors), E_INVALID, E_NOVALID (a ligand without
  * any box-valid translation), E_NOMEM, E_DEVICE. */
 int fftdg_scan(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, fftdg_partial *out_dev);
