@@ -8,7 +8,7 @@ only common module is `workload.synth`, which draws inputs.
 `oracle.c` holds the per-translation definitions (Eq. 7 grids, placement,
 the direct trilinear form of Eq. 8, the clash test of Eq. 10, partial sums of
 Eq. 2); `estimators.py` holds the averages of Eqs. 2, 12 and 13 and the
-importance-sampling and bootstrap estimators; `mlp.py` the FP64 network.
+importance-sampling estimators; `mlp.py` the FP64 network.
 """
 from __future__ import annotations
 

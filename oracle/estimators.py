@@ -7,9 +7,7 @@ Each function is the plain formula from the paper, in double precision:
     (average box-valid region, counted in grid points times h^3);
   - standard binding free energy, Eqs. 12-13, with the sign reading
     -kT ln(V_site C0) (Omega / 8 pi^2 = V_site);
-  - importance-sampled and uniformly subsampled forms of Eq. 2 over
-    configurations, and the bootstrap over configurations used for the
-    convergence figure of the results section;
+  - the importance-sampled form of Eq. 2 over configurations;
   - not in the paper: the learned proposal's stratified sampling plan
     (exact top stratum + defensive-mixture draws, weighted forms of Eq. 2)
     and the per-configuration scan descriptors it takes as inputs.
@@ -101,38 +99,6 @@ def bpmf_is(logz_cfg: np.ndarray, n_total: float, idx: np.ndarray, q: np.ndarray
     if val == -math.inf:
         return math.inf
     return -kT(T) * (val - math.log(n_total))
-
-
-def bpmf_uniform_subsample(logz_cfg, n_total, idx, T):
-    P = len(logz_cfg)
-    return bpmf_is(logz_cfg, n_total, idx, np.full(P, 1.0 / P), T)
-
-
-def bootstrap_sigma(partials: np.ndarray, T: float, n_draw: int, reps: int,
-                    rng: np.random.Generator) -> float:
-    """Standard deviation of Eq. 2 over `reps` bootstrap sets of n_draw
-    configurations drawn with replacement (all translations of a drawn
-    configuration move together)."""
-    p = np.asarray(partials, dtype=np.float64)
-    vals = []
-    for _ in range(reps):
-        sel = rng.integers(0, p.shape[0], n_draw)
-        vals.append(bpmf(p[sel], T))
-    v = np.asarray(vals)
-    v = v[np.isfinite(v)]
-    return float(np.std(v)) if v.size > 1 else math.inf
-
-
-def rmse(x, y) -> float:
-    """Eq. 14."""
-    x, y = np.asarray(x, float), np.asarray(y, float)
-    return float(np.sqrt(np.mean((x - y) ** 2)))
-
-
-def armse(x, y) -> float:
-    """Eq. 15."""
-    x, y = np.asarray(x, float), np.asarray(y, float)
-    return float(np.sqrt(np.mean((x - y - (x.mean() - y.mean())) ** 2)))
 
 
 def proposal(yhat: np.ndarray, alpha: float, tau: float) -> np.ndarray:

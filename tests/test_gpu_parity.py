@@ -182,6 +182,29 @@ def test_single_point_charge_gpu():
 
 
 # ------------------------------------------------------------------ partials, B, dG
+def _argmin_parity(w, go, oo, lig, c0, am_gpu, parts, precision):
+    """argmin (linear index (tz Vy + ty) Vx + tx of the lowest energy, lowest
+    index on ties, -1 with nothing finite).  FP64: identical to the oracle's.
+    FP32: identical wherever the oracle's minimum is unique by more than
+    1e-5 max|Psi| (the energy tolerance); elsewhere the GPU's pick must be a
+    clash-free translation whose oracle energy lies within that margin of the
+    minimum."""
+    am_g = np.asarray(am_gpu, np.int64)
+    am_o = parts[:, 5].astype(np.int64)
+    fin = parts[:, 3] > 0
+    np.testing.assert_array_equal(am_g[~fin], -1)
+    if precision == "f64":
+        np.testing.assert_array_equal(am_g[fin], am_o[fin])
+        return
+    for c in np.flatnonzero(fin & (am_g != am_o)):
+        r = oracle.config_eval(w, go, oo, lig, int(c))
+        psi = r["psi"].ravel()
+        ok = np.ones(psi.size, bool) if r["clash"] is None else r["clash"].ravel() == 0
+        k = int(am_g[c])
+        assert 0 <= k < psi.size and ok[k], (c0 + c, k)
+        assert psi[k] - psi[am_o[c]] <= 1e-5 * np.max(np.abs(psi)), (c0 + c, k, am_o[c], psi[k], psi[am_o[c]])
+
+
 def _scan_parity(w, precision, tolB, **tuning):
     import torch
     ctx, grids, occ = _gpu_setup(w, precision, **tuning)
@@ -207,6 +230,7 @@ def _scan_parity(w, precision, tolB, **tuning):
             lz_o = est.log_z(parts)
             assert np.max(np.abs(kt * (lz_g[fin] - lz_o[fin]))) < tolB
             assert np.max(np.abs(g["psi_min"][fin] - parts[fin, 4])) < tolB
+            _argmin_parity(w, go, oo, l, c0, g["argmin"], parts, precision)
             Bo.append(est.bpmf(parts, w.T))
             assert abs(B[l, s] - Bo[-1]) < tolB, (l, s, B[l, s], Bo[-1])
         vs = est.v_site(boxes, w.n_rec, w.h)

@@ -366,6 +366,32 @@ def test_is_estimators():
     assert abs(z) < 4
 
 
+def test_proposal_mixture_closed_forms():
+    """Defensive mixture q = (1 - alpha) softmax(yhat / tau) + alpha / P,
+    checked against values worked out by hand."""
+    # yhat = (0, ln 3): softmax = (1/4, 3/4); alpha = 0.2 -> 0.8 * (1/4, 3/4) + 0.1
+    q = est.proposal(np.array([0.0, math.log(3.0)]), 0.2, 1.0)
+    np.testing.assert_allclose(q, [0.3, 0.7], rtol=0, atol=1e-15)
+    # tau divides the log weights: yhat = (0, 2 ln 3) at tau = 2 is the same mixture
+    q2 = est.proposal(np.array([0.0, 2.0 * math.log(3.0)]), 0.2, 2.0)
+    np.testing.assert_allclose(q2, [0.3, 0.7], rtol=0, atol=1e-15)
+    # three configurations, yhat = (ln 1, ln 2, ln 5): softmax = (1/8, 2/8, 5/8)
+    q3 = est.proposal(np.log([1.0, 2.0, 5.0]), 0.0, 1.0)
+    np.testing.assert_allclose(q3, [0.125, 0.25, 0.625], rtol=0, atol=1e-15)
+    # alpha = 1: uniform whatever the prediction
+    y = np.random.default_rng(9).normal(0, 30, 50)
+    np.testing.assert_allclose(est.proposal(y, 1.0, 0.7), np.full(50, 1 / 50), rtol=0, atol=1e-15)
+    # a shift of every prediction leaves q unchanged; sum is one; floor alpha / P
+    for alpha in (0.0, 0.1, 0.5):
+        qa = est.proposal(y, alpha, 1.3)
+        assert qa.sum() == pytest.approx(1.0, abs=1e-13)
+        assert np.all(qa >= alpha / 50 - 1e-17)
+        np.testing.assert_allclose(est.proposal(y + 123.0, alpha, 1.3), qa, rtol=1e-12)
+    # huge predictions do not overflow (the softmax is max-shifted)
+    qb = est.proposal(np.array([1000.0, 1000.0 - math.log(4.0)]), 0.0, 1.0)
+    np.testing.assert_allclose(qb, [0.8, 0.2], rtol=0, atol=1e-14)
+
+
 def test_inverse_cdf_sample():
     q = np.array([0.1, 0.2, 0.3, 0.4])
     u = np.array([0.0, 0.0999, 0.1000001, 0.2999, 0.3000001, 0.59, 0.61, 0.999999])
