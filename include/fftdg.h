@@ -212,6 +212,7 @@ int fftdg_reduce(fftdg_ctx *ctx, const fftdg_batch *b, const fftdg_partial *p_de
  * every launch the library makes (for benchmarks).  Kernel ids:
  *   0 ligand xy forward   1 z-pencil product   2 inverse xy + log-sum-exp
  *   3 plane merge         4 receptor spectra   5 FP64 reduce
+ *   6 ligand occupancy runs (fused path)       7 clash test on bits (fused path)
  * fftdg_profile(ctx, 1) clears the counters and starts recording; 0 stops.
  * fftdg_profile_read synchronizes the stream and returns, for kernel id k,
  * the summed event time (ms), the launch count and the algorithmic HBM
@@ -223,7 +224,9 @@ int fftdg_reduce(fftdg_ctx *ctx, const fftdg_batch *b, const fftdg_partial *p_de
 #define FFTDG_K_MERGE 3
 #define FFTDG_K_SPECTRA 4
 #define FFTDG_K_REDUCE 5
-#define FFTDG_N_KERNELS 6
+#define FFTDG_K_RUNS 6
+#define FFTDG_K_CLASH 7
+#define FFTDG_N_KERNELS 8
 int fftdg_profile(fftdg_ctx *ctx, int enable);
 int fftdg_profile_read(fftdg_ctx *ctx, int32_t kernel_id, double *ms_host, int64_t *launches_host,
                        double *alg_bytes_host);
@@ -312,19 +315,33 @@ int fftdg_pair_energies(int device, void *hip_stream, int32_t n_rec_atoms, const
  *                      scans whose launch shapes, buffers and temperature
  *                      are unchanged (the new placement tables are uploaded
  *                      first); not used while profiling or exporting
- *                      energies.  Default 0. */
+ *                      energies.  Default 0;
+ *   fused              1 (default where available: n_fft <= 128): only the
+ *                      three energy channels go through the FFT, their z
+ *                      inputs formed inside the z-pencil kernel from the
+ *                      per-atom factors of the trilinear stencil's DFT (no
+ *                      forward planes in HBM); in OCC mode the clash test of
+ *                      Eq. 10 is made exactly on bits (ligand occupancy runs
+ *                      against OR-dilated receptor occupancy rows) before the
+ *                      z pass, and only z-translations with a clash-free
+ *                      translation are stored and inverse-transformed.
+ *                      energy_xy_direct and snapshots_per_pass are then not
+ *                      used.  0: the occupancy channel as a fourth FFT
+ *                      channel thresholded at 1/2 (the paper's formulation). */
 typedef struct {
     int32_t configs_per_chunk;
     int32_t energy_xy_direct;
     int32_t snapshots_per_pass;
     int32_t use_graph;
+    int32_t fused;
 } fftdg_tuning;
 int fftdg_get_tuning(const fftdg_ctx *ctx, fftdg_tuning *out);
 int fftdg_set_tuning(fftdg_ctx *ctx, const fftdg_tuning *t);
 
 /* Autotuner: times the candidate schedules (configurations per chunk in
- * {64, 128, 256, 512}, energy_xy_direct in {0, 1, 2}, snapshots_per_pass in
- * {1, n_snap} when there are several snapshots, use_graph in {0, 1}) with
+ * {64, 128, 256, 512}, use_graph in {0, 1}, and fused = 1 where available or
+ * fused = 0 with energy_xy_direct in {0, 1, 2} and snapshots_per_pass in
+ * {1, n_snap} when there are several snapshots) with
  * HIP events, each by the fastest of four runs after a warm-up, on an evenly
  * strided sample of at most max_cfgs configurations of the batch (all
  * receptor snapshots), keeps the fastest in the context and writes it to

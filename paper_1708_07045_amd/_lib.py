@@ -39,7 +39,12 @@ class GridDesc(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("configs_per_chunk", ctypes.c_int32), ("energy_xy_direct", ctypes.c_int32),
-                ("snapshots_per_pass", ctypes.c_int32), ("use_graph", ctypes.c_int32)]
+                ("snapshots_per_pass", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("fused", ctypes.c_int32)]
+
+
+def _tuning_dict(t: Tuning) -> dict:
+    return {"configs_per_chunk": t.configs_per_chunk, "energy_xy_direct": t.energy_xy_direct,
+            "snapshots_per_pass": t.snapshots_per_pass, "use_graph": t.use_graph, "fused": t.fused}
 
 
 class BatchC(ctypes.Structure):
@@ -61,7 +66,7 @@ EXPORTS = ["fftdg_version", "fftdg_status_string", "fftdg_create", "fftdg_destro
 N_FEATURES = 18
 N_SCAN_FEATURES = 3
 
-KERNEL_NAMES = ["lig_fwd_xy", "zprod", "inv_xy_lse", "merge", "rec_spectra", "reduce"]
+KERNEL_NAMES = ["lig_fwd_xy", "zprod", "inv_xy_lse", "merge", "rec_spectra", "reduce", "lig_runs", "clash"]
 
 _lib = None
 
@@ -216,11 +221,11 @@ class FFTDG:
     def get_tuning(self) -> dict:
         t = Tuning()
         self._check(self.L.fftdg_get_tuning(self.h_ctx, ctypes.byref(t)))
-        return {"configs_per_chunk": t.configs_per_chunk, "energy_xy_direct": t.energy_xy_direct,
-                "snapshots_per_pass": t.snapshots_per_pass, "use_graph": t.use_graph}
+        return _tuning_dict(t)
 
     def set_tuning(self, configs_per_chunk: Optional[int] = None, energy_xy_direct: Optional[int] = None,
-                   snapshots_per_pass: Optional[int] = None, use_graph: Optional[int] = None):
+                   snapshots_per_pass: Optional[int] = None, use_graph: Optional[int] = None,
+                   fused: Optional[int] = None):
         cur = self.get_tuning()
         if configs_per_chunk is not None:
             cur["configs_per_chunk"] = int(configs_per_chunk)
@@ -230,8 +235,10 @@ class FFTDG:
             cur["snapshots_per_pass"] = int(snapshots_per_pass)
         if use_graph is not None:
             cur["use_graph"] = int(use_graph)
+        if fused is not None:
+            cur["fused"] = int(fused)
         t = Tuning(cur["configs_per_chunk"], cur["energy_xy_direct"], cur["snapshots_per_pass"],
-                   cur["use_graph"])
+                   cur["use_graph"], cur["fused"])
         self._check(self.L.fftdg_set_tuning(self.h_ctx, ctypes.byref(t)))
 
     def autotune(self, batch: "Batch", T: float, max_cfgs: int = 2048):
@@ -241,8 +248,7 @@ class FFTDG:
         ms = ctypes.c_double()
         self._check(self.L.fftdg_autotune(self.h_ctx, ctypes.byref(batch.c), float(T), int(max_cfgs),
                                           ctypes.byref(t), ctypes.byref(ms)))
-        return ({"configs_per_chunk": t.configs_per_chunk, "energy_xy_direct": t.energy_xy_direct,
-                 "snapshots_per_pass": t.snapshots_per_pass, "use_graph": t.use_graph}, ms.value)
+        return _tuning_dict(t), ms.value
 
     def set_chunk(self, n: int):
         self.set_tuning(configs_per_chunk=n)

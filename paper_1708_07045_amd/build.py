@@ -6,8 +6,8 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfftdg.so")
-SOURCES = ["scan_kernels.hip", "mlp.hip", "runtime.cpp"]
-HEADERS = ["fft_device.hpp", "scan_types.hpp", "kernels.hpp"]
+SOURCES = ["scan_kernels.hip", "fused_kernels.hip", "mlp.hip", "runtime.cpp"]
+HEADERS = ["fft_device.hpp", "scan_types.hpp", "kernels.hpp", "scan_common.hpp", "fused.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

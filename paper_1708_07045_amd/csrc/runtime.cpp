@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "../../include/fftdg.h"
+#include "fused.hpp"
 #include "kernels.hpp"
 #include "scan_types.hpp"
 
@@ -36,8 +37,10 @@ struct fftdg_ctx {
     hipStream_t stream = nullptr;
     std::string err;
     const KernelSet *ks = nullptr;
+    const FusedSet *fs = nullptr;  // fused path (nullptr where not built)
     int n_ch = 3;  // receptor/ligand channels: 3 energy (+1 occupancy)
     DevBuf tw, rspec, rxy, ws_fwd, ws_inv, pp, tables, red_B, red_res, red_off, red_W;
+    DevBuf dil, runs, run_cnt, fbits, lives;  // fused path: receptor bit rows, ligand runs, clash results
     DevBuf sir_psi, sir_clash, sir_u, sir_lin, sir_psi_out;  // pose resampling
     int n_snap = 0;
     std::vector<double> W;
@@ -49,6 +52,7 @@ struct fftdg_ctx {
     int edirect = 0;  // energy xy transforms: 0 FFT pass, 1 inside the z kernel, 2 direct in the forward pass
     int snap_group = 1;  // snapshots per z launch (limited by workspace)
     bool use_graph = false;
+    bool fused = false;  // fused path selected (tuning)
     hipStream_t cap_stream = nullptr;   // capture only; graphs run on `stream`
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -68,6 +72,7 @@ struct fftdg_ctx {
     int64_t prof_n[FFTDG_N_KERNELS] = {0};
     double prof_bytes[FFTDG_N_KERNELS] = {0};
     DevBuf prof_cnt;  // energy planes transformed by the inverse-xy kernel
+    bool prof_fused = false;  // the counted planes were also written by the fused z kernel
 };
 
 namespace {
@@ -221,11 +226,17 @@ struct Plan {
         int64_t ws_fwd, ws_inv;   // complex elements used
         int pp;                   // plane partial slots used
         int zhalf;                // 1: every scanned configuration's energy planes lie in [0, n_fft/2); 2: and some occupancy window is longer than n_fft/2
+        // fused path
+        int nitems;               // clash-test items (tz, 64-row group)
+        int64_t nruns, nfree;     // run slots, free-bit words
+        int max_atoms;            // most atoms of a scanned configuration
     };
     std::vector<Chunk> chunks;
-    std::vector<int32_t> fwd_off, inv_off;
+    std::vector<int32_t> fwd_off, inv_off, item_off;
     std::vector<int32_t> zcfg;
+    bool fused = false;  // planned for the fused path
     int64_t max_fwd = 0, max_inv = 0;
+    int64_t max_runs = 0, max_free = 0, max_items = 0, max_chunk_cfgs = 0;
     int64_t total_pp = 0;  // plane partial slots of the whole plan (per snapshot)
 };
 
@@ -301,6 +312,22 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
         thr[i] = occ ? occ_threshold(g, b->sigma[i]) : 0.0;
         reach[i] = occ && thr[i] >= 1.0 ? isqrt_lt((long long)thr[i]) : -1;
     }
+    const bool fz = ctx->fused && ctx->fs != nullptr;
+    P.fused = fz;
+    // fused path: slots for a configuration's occupancy runs, at most one per
+    // atom chord plus one per (atom, row of its ball) (union segments never
+    // outnumber the balls meeting the row)
+    std::vector<int64_t> run_cap(b->n_lig, 0);
+    if (fz && occ)
+        for (int l = 0; l < b->n_lig; ++l) {
+            int64_t cap = b->atom_off[l + 1] - b->atom_off[l];
+            for (int i = b->atom_off[l]; i < b->atom_off[l + 1]; ++i)
+                if (reach[i] >= 0) {
+                    const int64_t r = 2 * (reach[i] >> 16) + 2;
+                    cap += r * r;
+                }
+            run_cap[l] = cap;
+        }
     std::atomic<int> bad(-1), bad_geom(-1);
     auto work = [&](int c_begin, int c_end) {
         for (int c = c_begin; c < c_end; ++c) {
@@ -330,6 +357,7 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
             // energy channel planes and rows (trilinear corners floor(u), floor(u)+1)
             int zlo = 1 << 30, zhi = -(1 << 30), ylo = 1 << 30, yhi = -(1 << 30);
             long long ozlo = 1LL << 40, ozhi = -(1LL << 40), oylo = 1LL << 40, oyhi = -(1LL << 40);
+            long long oxlo = 1LL << 40, oxhi = -(1LL << 40);
             for (int i = 0; i < na; ++i) {
                 const int az = U[3 * i + 2] >> 16, ay = U[3 * i + 1] >> 16;
                 zlo = std::min(zlo, az);
@@ -343,6 +371,8 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
                     ozhi = std::max(ozhi, floordiv(U[3 * i + 2] + s, 65536LL));
                     oylo = std::min(oylo, -floordiv(-(U[3 * i + 1] - s), 65536LL));
                     oyhi = std::max(oyhi, floordiv(U[3 * i + 1] + s, 65536LL));
+                    oxlo = std::min(oxlo, -floordiv(-(U[3 * i] - s), 65536LL));
+                    oxhi = std::max(oxhi, floordiv(U[3 * i] + s, 65536LL));
                     if (2 * s / 65536 + 2 >= N) {
                         int exp = -1;
                         bad_geom.compare_exchange_strong(exp, c);
@@ -358,13 +388,17 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
                 d.Lo = (int32_t)(ozhi - ozlo + 1);
                 d.yo0 = (int32_t)oylo;
                 d.Lyo = (int32_t)(oyhi - oylo + 1);
+                d.xo0 = (int32_t)oxlo;
+                d.Lxo = (int32_t)(oxhi - oxlo + 1);
             } else {
                 d.zo0 = 0;
                 d.Lo = 0;
                 d.yo0 = 0;
                 d.Lyo = 0;
+                d.xo0 = 0;
+                d.Lxo = 0;
             }
-            if (d.scanned && (d.Le > N || d.Lye > N || d.Lo > N || d.Lyo > N)) {
+            if (d.scanned && (d.Le > N || d.Lye > N || d.Lo > N || d.Lyo > N || d.Lxo > N)) {
                 int exp = -1;
                 bad_geom.compare_exchange_strong(exp, c);
             }
@@ -405,6 +439,7 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
     if (!only_one) {
         auto group = [&](const CfgDev &d) {
             if (!d.scanned) return 3;
+            if (fz) return d.Le <= N / 2 ? 0 : 1;  // the fused z kernel loads the window from plane 0
             if (!(d.ze0 >= 0 && d.ze0 + d.Le <= N / 2)) return 2;
             return (occ && d.Lo > N / 2) ? 1 : 0;
         };
@@ -421,6 +456,85 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
     const int64_t limit_c = (int64_t)(ctx->ws_limit / (size_t)ctx->ks->cbytes);
     int c = 0;
     int64_t ppt = 0;  // plane partial slots of the chunks before this one
+    while (c < ncfg && fz) {
+        Plan::Chunk ch{};
+        ch.c0 = c;
+        ch.off0 = P.fwd_off.size();
+        ch.z0 = P.zcfg.size();
+        int32_t ni = 0, nit = 0;
+        int nscan = 0, ma = 0;
+        int64_t wi = 0, nr = 0, nfw = 0;
+        int pp = 0;
+        bool zhalf = true;
+        while (c < ncfg) {
+            CfgDev &d = P.cfg[c];
+            const int local = c - ch.c0;
+            if (d.scanned) {
+                const int64_t iv = (int64_t)d.V[2] * NP;
+                if (nscan > 0 && (nscan >= ctx->chunk_cfgs || wi + iv > limit_c)) break;
+                const int ny = (d.V[1] + 63) / 64, W = (d.V[0] + 31) / 32;
+                d.off_fwd = 0;
+                d.off_inv = wi;
+                d.occ_slot0 = 0;
+                d.pp_base = (int32_t)(ppt + pp);
+                d.run_off = (int32_t)nr;
+                d.run_cap = occ ? (int32_t)run_cap[P.cfg_lig[d.global_cfg]] : 0;
+                d.free_off = (int32_t)nfw;
+                d.item_base = nit;
+                P.fwd_off.push_back(0);
+                P.inv_off.push_back(ni);
+                P.item_off.push_back(nit);
+                ni += d.V[2];
+                if (occ) {
+                    nit += d.V[2] * ny;
+                    nfw += (int64_t)d.V[2] * d.V[1] * W;
+                    nr += d.run_cap;
+                }
+                P.zcfg.push_back(local);
+                zhalf = zhalf && d.Le <= N / 2;
+                ma = std::max(ma, d.n_atoms);
+                wi += iv;
+                pp += d.V[2];
+                ++nscan;
+            } else {
+                d.off_fwd = d.off_inv = 0;
+                d.pp_base = (int32_t)(ppt + pp);
+                d.occ_slot0 = 0;
+                d.run_off = d.run_cap = d.free_off = 0;
+                d.item_base = nit;
+                P.fwd_off.push_back(0);
+                P.inv_off.push_back(ni);
+                P.item_off.push_back(nit);
+            }
+            ++c;
+        }
+        ch.c1 = c;
+        P.fwd_off.push_back(0);
+        P.inv_off.push_back(ni);
+        P.item_off.push_back(nit);
+        ch.nfwd = 0;
+        ch.ninv = ni;
+        ch.nz = P.zcfg.size() - ch.z0;
+        ch.ws_fwd = 0;
+        ch.ws_inv = wi;
+        ch.pp = pp;
+        ch.zhalf = zhalf ? 1 : 0;
+        ch.nitems = nit;
+        ch.nruns = nr;
+        ch.nfree = nfw;
+        ch.max_atoms = ma;
+        if (nr > INT32_MAX || nfw > INT32_MAX)
+            return set_err(ctx, FFTDG_E_INVALID, "scan: clash-test tables of one chunk exceed 2^31 entries");
+        P.max_inv = std::max(P.max_inv, wi);
+        P.max_runs = std::max(P.max_runs, nr);
+        P.max_free = std::max(P.max_free, nfw);
+        P.max_items = std::max<int64_t>(P.max_items, nit);
+        P.max_chunk_cfgs = std::max<int64_t>(P.max_chunk_cfgs, ch.c1 - ch.c0);
+        ppt += pp;
+        if (ppt > INT32_MAX) return set_err(ctx, FFTDG_E_INVALID, "scan: more than 2^31 valid z-translations in one batch");
+        P.total_pp = ppt;
+        P.chunks.push_back(ch);
+    }
     while (c < ncfg) {
         Plan::Chunk ch{};
         ch.c0 = c;
@@ -446,6 +560,7 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
                 const int local = c - ch.c0;
                 P.fwd_off.push_back(nf);
                 P.inv_off.push_back(ni);
+                P.item_off.push_back(0);
                 nf += e_items + (occ ? d.Lo : 0);
                 ni += d.V[2];
                 P.zcfg.push_back(local);
@@ -461,12 +576,14 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
                 d.occ_slot0 = 0;
                 P.fwd_off.push_back(nf);
                 P.inv_off.push_back(ni);
+                P.item_off.push_back(0);
             }
             ++c;
         }
         ch.c1 = c;
         P.fwd_off.push_back(nf);
         P.inv_off.push_back(ni);
+        P.item_off.push_back(0);
         ch.nfwd = nf;
         ch.ninv = ni;
         ch.nz = P.zcfg.size() - ch.z0;
@@ -511,7 +628,8 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     const size_t o_u = align256(o_cfg + sizeof(CfgDev) * P.cfg.size());
     const size_t o_fwd = align256(o_u + sizeof(int32_t) * P.U.size());
     const size_t o_inv = align256(o_fwd + sizeof(int32_t) * P.fwd_off.size());
-    const size_t o_z = align256(o_inv + sizeof(int32_t) * P.inv_off.size());
+    const size_t o_item = align256(o_inv + sizeof(int32_t) * P.inv_off.size());
+    const size_t o_z = align256(o_item + sizeof(int32_t) * P.item_off.size());
     const size_t o_gam = align256(o_z + sizeof(int32_t) * P.zcfg.size());
     const size_t o_thr = align256(o_gam + tsz * 3 * na);
     const size_t total = align256(o_thr + sizeof(double) * na);
@@ -523,6 +641,7 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     std::memcpy(h + o_u, P.U.data(), sizeof(int32_t) * P.U.size());
     std::memcpy(h + o_fwd, P.fwd_off.data(), sizeof(int32_t) * P.fwd_off.size());
     std::memcpy(h + o_inv, P.inv_off.data(), sizeof(int32_t) * P.inv_off.size());
+    std::memcpy(h + o_item, P.item_off.data(), sizeof(int32_t) * P.item_off.size());
     if (!P.zcfg.empty()) std::memcpy(h + o_z, P.zcfg.data(), sizeof(int32_t) * P.zcfg.size());
     if (g.precision == FFTDG_F32)
         fill_gamma<float>(b, (float *)(h + o_gam));
@@ -531,15 +650,22 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     double *thr = (double *)(h + o_thr);
     for (int i = 0; i < na; ++i) thr[i] = occ ? occ_threshold(g, b->sigma[i]) : 0.0;
     const size_t cb = (size_t)ctx->ks->cbytes;
-    if ((rc = reserve(ctx, ctx->ws_fwd, cb * (size_t)std::max<int64_t>(P.max_fwd, 1)))) return rc;
+    if (!P.fused && (rc = reserve(ctx, ctx->ws_fwd, cb * (size_t)std::max<int64_t>(P.max_fwd, 1)))) return rc;
+    if (P.fused && occ) {
+        if ((rc = reserve(ctx, ctx->runs, sizeof(uint32_t) * (size_t)std::max<int64_t>(P.max_runs, 1)))) return rc;
+        if ((rc = reserve(ctx, ctx->run_cnt, sizeof(int32_t) * (size_t)std::max<int64_t>(P.max_chunk_cfgs, 1)))) return rc;
+        if ((rc = reserve(ctx, ctx->fbits, sizeof(uint32_t) * (size_t)std::max<int64_t>(P.max_free, 1)))) return rc;
+        if ((rc = reserve(ctx, ctx->lives, (size_t)std::max<int64_t>(P.max_items, 1)))) return rc;
+    }
     // snapshots whose inverse planes share the workspace: the z kernel keeps
     // a configuration's forward spectra in registers across the group
     const int s_begin = snap_only >= 0 ? snap_only : 0;
     const int s_end = snap_only >= 0 ? snap_only + 1 : ctx->n_snap;
     const int64_t inv1 = std::max<int64_t>(P.max_inv, 1);
     const int64_t room = (int64_t)(ctx->ws_limit / cb) - P.max_fwd;
-    const int grp = (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)(s_end - s_begin), room / inv1,
-                                                                  (int64_t)ctx->snap_group}));
+    const int grp = P.fused ? 1
+                            : (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)(s_end - s_begin), room / inv1,
+                                                                           (int64_t)ctx->snap_group}));
     if ((rc = reserve(ctx, ctx->ws_inv, cb * (size_t)inv1 * grp))) return rc;
     // plane partials of the whole scan, one region per snapshot, merged into
     // configuration partials once per snapshot after the last chunk
@@ -553,6 +679,7 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     const int32_t *du = (const int32_t *)(d + o_u);
     const int32_t *dfwd = (const int32_t *)(d + o_fwd);
     const int32_t *dinv = (const int32_t *)(d + o_inv);
+    const int32_t *ditem = (const int32_t *)(d + o_item);
     const int32_t *dz = (const int32_t *)(d + o_z);
     const void *dgam = (const void *)(d + o_gam);
     const double *dthr = (const double *)(d + o_thr);
@@ -564,7 +691,58 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     // per-chunk data from the device tables, so a captured sequence stays
     // valid for any later scan with the same signature (launch shapes,
     // table layout, buffers, temperature).
+    const bool exporting = psi_out != nullptr || clash_out != nullptr;
+    // Fused path: ligand occupancy runs once per chunk; per snapshot the
+    // clash test on bits, the z pass (energy channels, inputs from per-atom
+    // factors) and the inverse xy on the planes holding a clash-free
+    // translation.
+    auto launch_fused = [&](hipStream_t st) -> int {
+    const FusedSet *fs = ctx->fs;
+    uint32_t *runs = (uint32_t *)ctx->runs.p;
+    int32_t *rcnt = (int32_t *)ctx->run_cnt.p;
+    uint32_t *fb = (uint32_t *)ctx->fbits.p;
+    uint8_t *lv = (uint8_t *)ctx->lives.p;
+    const double b_spec3 = 3.0 * (double)g.n_fft * ctx->ks->np * cb;
+    for (const Plan::Chunk &ch : P.chunks) {
+        const CfgDev *ccfg = dcfg + ch.c0;
+        const int nloc = ch.c1 - ch.c0;
+        if (occ)
+            HIPCHK(ctx, timed(ctx, FFTDG_K_RUNS, 4.0 * (double)ch.nruns, [&] {
+                       return fs->lig_runs(st, ccfg, dz + ch.z0, (int)ch.nz, du, dthr, runs, rcnt);
+                   }));
+        for (int s = s_begin; s < s_end; ++s) {
+            if (occ) {
+                const uint32_t *dil = (const uint32_t *)ctx->dil.p + (size_t)s * (size_t)fs->dil_words;
+                HIPCHK(ctx, timed(ctx, FFTDG_K_CLASH, 4.0 * (double)ch.nfree + (double)ch.nitems, [&] {
+                           return fs->clash(st, ditem + ch.off0, nloc, ch.nitems, ccfg, runs, rcnt, dil, fb, lv);
+                       }));
+            }
+            const char *rs = (const char *)ctx->rspec.p + spec_per_snap * s;
+            // planes written are counted on the device (those the inverse reads)
+            HIPCHK(ctx, timed(ctx, FFTDG_K_ZPROD, b_spec3, [&] {
+                       return fs->zpass(st, ch.zhalf != 0, occ && !exporting, ccfg, dz + ch.z0, (int)ch.nz,
+                                        ch.max_atoms, rs, ctx->tw.p, ctx->ws_inv.p, du, dgam, lv);
+                   }));
+            void *pp_s = (char *)ctx->pp.p + pp_snap * (size_t)(s - s_begin);
+            HIPCHK(ctx, timed(ctx, FFTDG_K_INV, pb * ch.pp, [&] {
+                       return fs->inv(st, occ, dinv + ch.off0, nloc, (int)ch.ninv, ccfg, ctx->ws_inv.p, beta,
+                                      ctx->tw.p, fb, lv, pp_s, psi_out, clash_out,
+                                      ctx->prof ? (unsigned int *)ctx->prof_cnt.p : nullptr);
+                   }));
+            if (ctx->prof) ctx->prof_fused = true;
+        }
+    }
+    if (out)
+        for (int s = s_begin; s < s_end; ++s) {
+            const void *pp_s = (const char *)ctx->pp.p + pp_snap * (size_t)(s - s_begin);
+            HIPCHK(ctx, timed(ctx, FFTDG_K_MERGE, pb * (double)P.total_pp + sizeof(fftdg_partial) * (double)ncfg, [&] {
+                       return ks->merge(st, dcfg, ncfg, pp_s, out + (size_t)s * ncfg);
+                   }));
+        }
+    return FFTDG_OK;
+    };
     auto launch_all = [&](hipStream_t st) -> int {
+    if (P.fused) return launch_fused(st);
     for (const Plan::Chunk &ch : P.chunks) {
         const CfgDev *ccfg = dcfg + ch.c0;
         // algorithmic bytes: forward planes written once (fwd), read once and
@@ -610,7 +788,10 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     };
     const bool graph_ok = ctx->use_graph && !ctx->prof && !psi_out && !clash_out && out;
     if (!graph_ok) return launch_all(ctx->stream);
-    std::vector<int64_t> sig = {(int64_t)(intptr_t)ks, occ, ctx->edirect, grp, s_begin, s_end,
+    std::vector<int64_t> sig = {(int64_t)(intptr_t)ks, occ, ctx->edirect, grp, s_begin, s_end, P.fused,
+                                (int64_t)(intptr_t)ctx->runs.p, (int64_t)(intptr_t)ctx->run_cnt.p,
+                                (int64_t)(intptr_t)ctx->fbits.p, (int64_t)(intptr_t)ctx->lives.p,
+                                (int64_t)(intptr_t)ctx->dil.p, (int64_t)o_item,
                                 (int64_t)(intptr_t)out, (int64_t)(intptr_t)ctx->tables.p,
                                 (int64_t)(intptr_t)ctx->ws_fwd.p, (int64_t)(intptr_t)ctx->ws_inv.p,
                                 (int64_t)(intptr_t)ctx->pp.p, (int64_t)(intptr_t)ctx->rspec.p,
@@ -621,7 +802,8 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     sig.push_back(bbits);
     for (const Plan::Chunk &ch : P.chunks)
         for (int64_t v : {(int64_t)ch.c0, (int64_t)ch.c1, (int64_t)ch.off0, (int64_t)ch.nfwd, (int64_t)ch.ninv,
-                          (int64_t)ch.z0, (int64_t)ch.nz, ch.ws_fwd, ch.ws_inv, (int64_t)ch.pp, (int64_t)ch.zhalf})
+                          (int64_t)ch.z0, (int64_t)ch.nz, ch.ws_fwd, ch.ws_inv, (int64_t)ch.pp, (int64_t)ch.zhalf,
+                          (int64_t)ch.nitems, ch.nruns, ch.nfree, (int64_t)ch.max_atoms})
             sig.push_back(v);
     if (!(ctx->graph_exec && sig == ctx->graph_sig)) {
         if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -707,6 +889,8 @@ int fftdg_create(fftdg_ctx **out, const fftdg_grid_desc *g, int device, void *hi
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
     c->ks = ks;
+    c->fs = fused_set(g->precision, g->n_fft);
+    c->fused = c->fs != nullptr;
     c->n_ch = g->clash_mode == FFTDG_OCC ? 4 : 3;
     if (hipSetDevice(device) != hipSuccess || hipEventCreateWithFlags(&c->staging_ev, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
@@ -749,7 +933,8 @@ void fftdg_destroy(fftdg_ctx *c) {
     (void)hipStreamSynchronize(c->stream);
     DevBuf *bufs[] = {&c->tw, &c->rspec, &c->rxy, &c->ws_fwd, &c->ws_inv, &c->pp, &c->tables,
                       &c->red_B, &c->red_res, &c->red_off, &c->red_W, &c->prof_cnt, &c->tune_out,
-                      &c->sir_psi, &c->sir_clash, &c->sir_u, &c->sir_lin, &c->sir_psi_out};
+                      &c->sir_psi, &c->sir_clash, &c->sir_u, &c->sir_lin, &c->sir_psi_out,
+                      &c->dil, &c->runs, &c->run_cnt, &c->fbits, &c->lives};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->pinned) (void)hipHostFree(c->pinned);
@@ -819,6 +1004,15 @@ int fftdg_set_receptors(fftdg_ctx *ctx, int32_t n_snap, const void *grids, const
                                                is_occ ? occ + s * n3 : nullptr, g.n_rec, ctx->n_ch, ctx->tw.p,
                                                ctx->rxy.p, (char *)ctx->rspec.p + s * per_snap);
                }));
+    }
+    if (is_occ && ctx->fs) {
+        // bit rows of the clash test (fused path), one table per snapshot
+        const size_t dw = (size_t)ctx->fs->dil_words;
+        if ((rc = reserve(ctx, ctx->dil, sizeof(uint32_t) * dw * n_snap))) return rc;
+        for (int s = 0; s < n_snap; ++s)
+            HIPCHK(ctx, timed(ctx, FFTDG_K_SPECTRA, (double)n3 + 4.0 * (double)dw, [&] {
+                       return ctx->fs->rec_dilate(ctx->stream, occ + s * n3, g.n_rec, (uint32_t *)ctx->dil.p + s * dw);
+                   }));
     }
     ctx->n_snap = n_snap;
     ctx->W = W;
@@ -931,6 +1125,7 @@ int fftdg_profile(fftdg_ctx *ctx, int enable) {
         ctx->ev_pool.push_back(r.b);
     }
     ctx->recs.clear();
+    ctx->prof_fused = false;
     for (int k = 0; k < FFTDG_N_KERNELS; ++k) {
         ctx->prof_ms[k] = 0.0;
         ctx->prof_n[k] = 0;
@@ -968,6 +1163,8 @@ int fftdg_profile_read(fftdg_ctx *ctx, int32_t k, double *ms, int64_t *n, double
         const unsigned int zero = 0;
         HIPCHK(ctx, hipMemcpy(ctx->prof_cnt.p, &zero, sizeof(zero), hipMemcpyHostToDevice));
         ctx->prof_bytes[FFTDG_K_INV] += (double)cnt * ctx->ks->np * ctx->ks->cbytes;
+        if (ctx->prof_fused) ctx->prof_bytes[FFTDG_K_ZPROD] += (double)cnt * ctx->ks->np * ctx->ks->cbytes;
+        ctx->prof_fused = false;
     }
     *ms = ctx->prof_ms[k];
     *n = ctx->prof_n[k];
@@ -981,6 +1178,7 @@ int fftdg_get_tuning(const fftdg_ctx *ctx, fftdg_tuning *t) {
     t->energy_xy_direct = ctx->edirect;
     t->snapshots_per_pass = ctx->snap_group;
     t->use_graph = ctx->use_graph ? 1 : 0;
+    t->fused = ctx->fused ? 1 : 0;
     return FFTDG_OK;
 }
 
@@ -996,8 +1194,11 @@ int fftdg_set_tuning(fftdg_ctx *ctx, const fftdg_tuning *t) {
     ctx->chunk_cfgs = t->configs_per_chunk;
     ctx->edirect = t->energy_xy_direct;
     if (t->use_graph != 0 && t->use_graph != 1) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: use_graph must be 0 or 1");
+    if (t->fused != 0 && t->fused != 1) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: fused must be 0 or 1");
+    if (t->fused && !ctx->fs) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: the fused path needs n_fft <= 128");
     ctx->snap_group = t->snapshots_per_pass;
     ctx->use_graph = t->use_graph != 0;
+    ctx->fused = t->fused != 0;
     return FFTDG_OK;
 }
 
@@ -1070,17 +1271,21 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
     fftdg_batch bs = *b;
     bs.cfg_select = sel.data();
     if ((rc = reserve(ctx, ctx->tune_out, sizeof(fftdg_partial) * (size_t)ncfg * ctx->n_snap))) return rc;
-    const fftdg_tuning keep = {ctx->chunk_cfgs, ctx->edirect, ctx->snap_group, ctx->use_graph ? 1 : 0};
+    const fftdg_tuning keep = {ctx->chunk_cfgs, ctx->edirect, ctx->snap_group, ctx->use_graph ? 1 : 0,
+                               ctx->fused ? 1 : 0};
     const bool prof = ctx->prof;
     ctx->prof = false;
     std::vector<fftdg_tuning> cand;
     std::vector<int> passes = {1};
     if (ctx->n_snap > 1) passes.push_back(ctx->n_snap);
-    for (int chunk : {64, 128, 256, 512})
+    for (int chunk : {64, 128, 256, 512}) {
+        if (ctx->fs)
+            for (int gr : {0, 1}) cand.push_back(fftdg_tuning{chunk, ctx->edirect, 1, gr, 1});
         for (int ed : {0, 1, 2})
             for (int sp : passes)
                 for (int gr : {0, 1})
-                    if (ed != 1 || ctx->g.n_fft <= 128) cand.push_back(fftdg_tuning{chunk, ed, sp, gr});
+                    if (ed != 1 || ctx->g.n_fft <= 128) cand.push_back(fftdg_tuning{chunk, ed, sp, gr, 0});
+    }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(ctx, hipEventCreate(&e0));
     HIPCHK(ctx, hipEventCreate(&e1));
@@ -1092,6 +1297,7 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
         ctx->edirect = t.energy_xy_direct;
         ctx->snap_group = t.snapshots_per_pass;
         ctx->use_graph = t.use_graph != 0;
+        ctx->fused = t.fused != 0;
         float tmin = INFINITY;
         for (int rep = 0; rep < 5 && !err; ++rep) {  // a warm-up run, then the fastest of four
             Plan P;
@@ -1118,6 +1324,7 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
         ctx->edirect = keep.energy_xy_direct;
         ctx->snap_group = keep.snapshots_per_pass;
         ctx->use_graph = keep.use_graph != 0;
+        ctx->fused = keep.fused != 0;
         if (err == FFTDG_E_DEVICE && ctx->err.empty()) ctx->err = "autotune: HIP event error";
         return err;
     }
@@ -1125,6 +1332,7 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
     ctx->edirect = bt.energy_xy_direct;
     ctx->snap_group = bt.snapshots_per_pass;
     ctx->use_graph = bt.use_graph != 0;
+    ctx->fused = bt.fused != 0;
     if (out) *out = bt;
     if (ms_host) *ms_host = best / ((double)nsel * ctx->n_snap);
     return FFTDG_OK;

@@ -21,6 +21,12 @@ struct CfgDev {
     int32_t pp_base;     // first plane-partial slot (one per valid z translation)
     int32_t scanned;     // 1 if the configuration is scanned in this call
     int32_t occ_slot0;   // forward-plane slot of the first occupancy plane
+    int32_t xo0, Lxo;    // occupancy channel: first column (true x) and count
+    // fused path (clash test on bits):
+    int32_t run_off;     // first slot of its occupancy runs in the chunk's run buffer
+    int32_t run_cap;     // slots reserved for them (an upper bound on the count)
+    int32_t free_off;    // first word of its free-translation bits in the chunk
+    int32_t item_base;   // first (tz, 64-row group) item of its clash test in the chunk
     int32_t pad0;
     int64_t off_fwd;     // complex-element offset of its forward planes
     int64_t off_inv;     // complex-element offset of its inverse planes

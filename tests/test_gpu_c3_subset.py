@@ -1,7 +1,7 @@
 """The batched workload (141 ligands of 8-40 atoms, 10 jittered receptor
 snapshots, 128^3 FFT; configurations at a tenth of 200-2000 per ligand)
-scanned whole on the GPU in one pass, in the schedule the autotuner picks
-for it (chunks of 256, direct energy planes, one snapshot per z pass), and
+scanned whole on the GPU in one pass on the fused path (chunks of 256: the
+clash test on bits, energy channels through the FFT), and
 checked against the FP64 oracle on a stratified subset of snapshot 0:
   - 6 ligands (fewest atoms, most atoms, 4 seeded picks) x all their
     configurations: partials of Eq. 2 per configuration (counts bit-exact),
@@ -32,7 +32,7 @@ def test_batched_workload_stratified_subset():
     w = synth.config3(cfg_scale=0.1)
     rng = np.random.default_rng(20171)
     ctx = fd.FFTDG.from_workload(w)
-    ctx.set_tuning(configs_per_chunk=256, energy_xy_direct=2, snapshots_per_pass=1)
+    ctx.set_tuning(configs_per_chunk=256, fused=1)
     gs, os_ = [], []
     for s in range(w.receptor.n_snap):
         g, o = ctx.receptor_grids(w.receptor.xyz[s], w.receptor.q, w.receptor.sigma, w.receptor.eps)

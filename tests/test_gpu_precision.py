@@ -19,16 +19,16 @@ GOLD = os.path.join(os.path.dirname(__file__), "golden", "c2_oracle.json")
 
 
 @pytest.mark.parametrize("mode,tol", [("occ", 0.01), ("cap", 0.01)])
-@pytest.mark.parametrize("energy_xy_direct", [0, 2])
-def test_full_c2_fp32_against_fp64_oracle(mode, tol, energy_xy_direct):
+@pytest.mark.parametrize("fused,energy_xy_direct", [(1, 0), (0, 0), (0, 2)])
+def test_full_c2_fp32_against_fp64_oracle(mode, tol, fused, energy_xy_direct):
     import torch
     import paper_1708_07045_amd as fd
     ref = json.load(open(GOLD))[mode]
-    print(f"precision study: c2 {mode} energy_xy_direct={energy_xy_direct}", flush=True)
+    print(f"precision study: c2 {mode} fused={fused} energy_xy_direct={energy_xy_direct}", flush=True)
     w = synth.config2()
     w.clash_mode = mode
     ctx = fd.FFTDG.from_workload(w)
-    ctx.set_tuning(energy_xy_direct=energy_xy_direct, configs_per_chunk=512)
+    ctx.set_tuning(energy_xy_direct=energy_xy_direct, configs_per_chunk=512, fused=fused)
     g, o = ctx.receptor_grids(w.receptor.xyz[0], w.receptor.q, w.receptor.sigma, w.receptor.eps)
     ctx.set_receptors(g[None].contiguous(), o[None].contiguous() if o is not None else None, w.receptor.weights)
     b = fd.Batch(w.ligands)
