@@ -368,6 +368,9 @@ def main():
     ap.add_argument("--chunk", type=int, default=0, help="configurations per chunk (0 = library default)")
     ap.add_argument("--energy-direct", type=int, default=-1, help="energy xy transforms: 0 FFT pass, 1 in the z kernel, 2 direct in the forward pass (default: autotuned)")
     ap.add_argument("--snap-pass", type=int, default=0, help="snapshots per z pass (0 = library default)")
+    ap.add_argument("--fused", type=int, default=-1,
+                    help="0: plane path; 1: fused path, energy planes from the forward pass; 2: fused path, "
+                         "z inputs formed in the z kernel (default: autotuned)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c6"],
                     help="c2: the 8000-configuration T4L-sized scan (the metric's workload); "
                          "c3: 141 ligands x 10 receptor snapshots (batched); "
@@ -426,6 +429,8 @@ def main():
         ctx.set_tuning(energy_xy_direct=args.energy_direct)
     if args.snap_pass:
         ctx.set_tuning(snapshots_per_pass=args.snap_pass)
+    if args.fused in (0, 1, 2):
+        ctx.set_tuning(fused=args.fused)
     gl, ol = [], []
     for sn in range(n_snap):
         g, o = ctx.receptor_grids(w.receptor.xyz[sn], w.receptor.q, w.receptor.sigma, w.receptor.eps)
@@ -438,7 +443,8 @@ def main():
     out = ctx.alloc_partials(batch)
     torch.cuda.synchronize()
     autotuned = None
-    if not args.no_autotune and not (args.chunk or args.energy_direct in (0, 1, 2) or args.snap_pass):
+    if not args.no_autotune and not (args.chunk or args.energy_direct in (0, 1, 2) or args.snap_pass or
+                                     args.fused in (0, 1, 2)):
         t0 = time.perf_counter()
         # the T4L-sized workload is tuned on all of its 8000 configurations
         # (a small sample leaves chunk sizes within noise of each other)

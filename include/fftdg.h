@@ -316,18 +316,20 @@ int fftdg_pair_energies(int device, void *hip_stream, int32_t n_rec_atoms, const
  *                      are unchanged (the new placement tables are uploaded
  *                      first); not used while profiling or exporting
  *                      energies.  Default 0;
- *   fused              1 (default where available: n_fft <= 128): only the
- *                      three energy channels go through the FFT, their z
- *                      inputs formed inside the z-pencil kernel from the
- *                      per-atom factors of the trilinear stencil's DFT (no
- *                      forward planes in HBM); in OCC mode the clash test of
- *                      Eq. 10 is made exactly on bits (ligand occupancy runs
- *                      against OR-dilated receptor occupancy rows) before the
- *                      z pass, and only z-translations with a clash-free
- *                      translation are stored and inverse-transformed.
- *                      energy_xy_direct and snapshots_per_pass are then not
- *                      used.  0: the occupancy channel as a fourth FFT
- *                      channel thresholded at 1/2 (the paper's formulation). */
+ *   fused              1 or 2 (1 is the default where available: n_fft <=
+ *                      128): only the three energy channels go through the
+ *                      FFT; in OCC mode the clash test of Eq. 10 is made
+ *                      exactly on bits (ligand occupancy runs against
+ *                      OR-dilated receptor occupancy rows) before the z pass,
+ *                      and only z-translations with a clash-free translation
+ *                      are stored and inverse-transformed.  1: the energy
+ *                      planes' x/y transforms come from the direct per-atom
+ *                      forward pass through device memory; 2: the z-pencil
+ *                      kernel forms its inputs itself from the per-atom
+ *                      factors (no forward planes).  energy_xy_direct and
+ *                      snapshots_per_pass are then not used.  0: the
+ *                      occupancy channel as a fourth FFT channel thresholded
+ *                      at 1/2 (the paper's formulation). */
 typedef struct {
     int32_t configs_per_chunk;
     int32_t energy_xy_direct;
@@ -339,7 +341,7 @@ int fftdg_get_tuning(const fftdg_ctx *ctx, fftdg_tuning *out);
 int fftdg_set_tuning(fftdg_ctx *ctx, const fftdg_tuning *t);
 
 /* Autotuner: times the candidate schedules (configurations per chunk in
- * {64, 128, 256, 512}, use_graph in {0, 1}, and fused = 1 where available or
+ * {64, 128, 256, 512}, use_graph in {0, 1}, and fused in {1, 2} where available or
  * fused = 0 with energy_xy_direct in {0, 1, 2} and snapshots_per_pass in
  * {1, n_snap} when there are several snapshots) with
  * HIP events, each by the fastest of four runs after a warm-up, on an evenly

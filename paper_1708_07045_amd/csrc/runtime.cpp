@@ -41,6 +41,8 @@ struct fftdg_ctx {
     int n_ch = 3;  // receptor/ligand channels: 3 energy (+1 occupancy)
     DevBuf tw, rspec, rxy, ws_fwd, ws_inv, pp, tables, red_B, red_res, red_off, red_W;
     DevBuf dil, runs, run_cnt, fbits, lives;  // fused path: receptor bit rows, ligand runs, clash results
+    DevBuf zat, zbt;                          // fused path: sorted atoms and plane starts per configuration
+    DevBuf surv, scnt;                        // fused path: undecided rows of the clash test and their counts
     DevBuf sir_psi, sir_clash, sir_u, sir_lin, sir_psi_out;  // pose resampling
     int n_snap = 0;
     std::vector<double> W;
@@ -52,7 +54,7 @@ struct fftdg_ctx {
     int edirect = 0;  // energy xy transforms: 0 FFT pass, 1 inside the z kernel, 2 direct in the forward pass
     int snap_group = 1;  // snapshots per z launch (limited by workspace)
     bool use_graph = false;
-    bool fused = false;  // fused path selected (tuning)
+    int fused = 0;  // 0 plane path; fused path with energy planes from the forward pass (1) or built in the z kernel (2)
     hipStream_t cap_stream = nullptr;   // capture only; graphs run on `stream`
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -228,15 +230,18 @@ struct Plan {
         int zhalf;                // 1: every scanned configuration's energy planes lie in [0, n_fft/2); 2: and some occupancy window is longer than n_fft/2
         // fused path
         int nitems;               // clash-test items (tz, 64-row group)
+        int nitems2;              // phase-2 items (64-row slices of the undecided-row lists)
+        int64_t nsurv;            // undecided-row list slots
         int64_t nruns, nfree;     // run slots, free-bit words
         int max_atoms;            // most atoms of a scanned configuration
     };
     std::vector<Chunk> chunks;
-    std::vector<int32_t> fwd_off, inv_off, item_off;
+    std::vector<int32_t> fwd_off, inv_off, item_off, item2_off;
     std::vector<int32_t> zcfg;
-    bool fused = false;  // planned for the fused path
+    bool fused = false;         // planned for the fused path
+    bool fused_planes = false;  // ... with energy planes written by the forward pass
     int64_t max_fwd = 0, max_inv = 0;
-    int64_t max_runs = 0, max_free = 0, max_items = 0, max_chunk_cfgs = 0;
+    int64_t max_runs = 0, max_free = 0, max_items = 0, max_chunk_cfgs = 0, max_surv = 0;
     int64_t total_pp = 0;  // plane partial slots of the whole plan (per snapshot)
 };
 
@@ -312,19 +317,23 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
         thr[i] = occ ? occ_threshold(g, b->sigma[i]) : 0.0;
         reach[i] = occ && thr[i] >= 1.0 ? isqrt_lt((long long)thr[i]) : -1;
     }
-    const bool fz = ctx->fused && ctx->fs != nullptr;
+    const bool fz = ctx->fused != 0 && ctx->fs != nullptr;
+    const bool fzp = fz && ctx->fused == 1;
     P.fused = fz;
-    // fused path: slots for a configuration's occupancy runs, at most one per
-    // atom chord plus one per (atom, row of its ball) (union segments never
-    // outnumber the balls meeting the row)
+    P.fused_planes = fzp;
+    // fused path: slots for a configuration's occupancy runs.  An atom's ball
+    // meets at most r = 2 floor(reach / 2^16) + 2 rows and columns of each
+    // axis; runs are written in pieces of at most 63 points, and the pieces
+    // of a row's union never outnumber those of the balls meeting it, so per
+    // atom (1 chord + r^2 rows) x ceil(r / 63) pieces bound the count
     std::vector<int64_t> run_cap(b->n_lig, 0);
     if (fz && occ)
         for (int l = 0; l < b->n_lig; ++l) {
-            int64_t cap = b->atom_off[l + 1] - b->atom_off[l];
+            int64_t cap = 0;
             for (int i = b->atom_off[l]; i < b->atom_off[l + 1]; ++i)
                 if (reach[i] >= 0) {
                     const int64_t r = 2 * (reach[i] >> 16) + 2;
-                    cap += r * r;
+                    cap += (1 + r * r) * ((r + 62) / 63);
                 }
             run_cap[l] = cap;
         }
@@ -461,9 +470,9 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
         ch.c0 = c;
         ch.off0 = P.fwd_off.size();
         ch.z0 = P.zcfg.size();
-        int32_t ni = 0, nit = 0;
+        int32_t ni = 0, nit = 0, nit2 = 0, nf = 0;
         int nscan = 0, ma = 0;
-        int64_t wi = 0, nr = 0, nfw = 0;
+        int64_t wi = 0, wf = 0, nr = 0, nfw = 0, nsv = 0;
         int pp = 0;
         bool zhalf = true;
         while (c < ncfg) {
@@ -471,9 +480,10 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
             const int local = c - ch.c0;
             if (d.scanned) {
                 const int64_t iv = (int64_t)d.V[2] * NP;
-                if (nscan > 0 && (nscan >= ctx->chunk_cfgs || wi + iv > limit_c)) break;
+                const int64_t f = fzp ? (int64_t)3 * d.Le * NP : 0;
+                if (nscan > 0 && (nscan >= ctx->chunk_cfgs || wi + iv + wf + f > limit_c)) break;
                 const int ny = (d.V[1] + 63) / 64, W = (d.V[0] + 31) / 32;
-                d.off_fwd = 0;
+                d.off_fwd = wf;
                 d.off_inv = wi;
                 d.occ_slot0 = 0;
                 d.pp_base = (int32_t)(ppt + pp);
@@ -481,13 +491,21 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
                 d.run_cap = occ ? (int32_t)run_cap[P.cfg_lig[d.global_cfg]] : 0;
                 d.free_off = (int32_t)nfw;
                 d.item_base = nit;
-                P.fwd_off.push_back(0);
+                d.surv_off = (int32_t)nsv;
+                P.fwd_off.push_back(nf);
                 P.inv_off.push_back(ni);
                 P.item_off.push_back(nit);
+                P.item2_off.push_back(nit2);
                 ni += d.V[2];
+                if (fzp) {
+                    nf += d.Le;  // one forward item per energy plane (all three channels)
+                    wf += f;
+                }
                 if (occ) {
                     nit += d.V[2] * ny;
+                    nit2 += (d.V[2] * d.V[1] + 63) / 64;
                     nfw += (int64_t)d.V[2] * d.V[1] * W;
+                    nsv += (int64_t)d.V[2] * d.V[1];
                     nr += d.run_cap;
                 }
                 P.zcfg.push_back(local);
@@ -500,35 +518,41 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
                 d.off_fwd = d.off_inv = 0;
                 d.pp_base = (int32_t)(ppt + pp);
                 d.occ_slot0 = 0;
-                d.run_off = d.run_cap = d.free_off = 0;
+                d.run_off = d.run_cap = d.free_off = d.surv_off = 0;
                 d.item_base = nit;
-                P.fwd_off.push_back(0);
+                P.fwd_off.push_back(nf);
                 P.inv_off.push_back(ni);
                 P.item_off.push_back(nit);
+                P.item2_off.push_back(nit2);
             }
             ++c;
         }
         ch.c1 = c;
-        P.fwd_off.push_back(0);
+        P.fwd_off.push_back(nf);
         P.inv_off.push_back(ni);
         P.item_off.push_back(nit);
-        ch.nfwd = 0;
+        P.item2_off.push_back(nit2);
+        ch.nfwd = nf;
         ch.ninv = ni;
         ch.nz = P.zcfg.size() - ch.z0;
-        ch.ws_fwd = 0;
+        ch.ws_fwd = wf;
         ch.ws_inv = wi;
         ch.pp = pp;
         ch.zhalf = zhalf ? 1 : 0;
         ch.nitems = nit;
+        ch.nitems2 = nit2;
+        ch.nsurv = nsv;
         ch.nruns = nr;
         ch.nfree = nfw;
         ch.max_atoms = ma;
-        if (nr > INT32_MAX || nfw > INT32_MAX)
+        if (nr > INT32_MAX || nfw > INT32_MAX || nsv > INT32_MAX)
             return set_err(ctx, FFTDG_E_INVALID, "scan: clash-test tables of one chunk exceed 2^31 entries");
         P.max_inv = std::max(P.max_inv, wi);
+        P.max_fwd = std::max(P.max_fwd, wf);
         P.max_runs = std::max(P.max_runs, nr);
         P.max_free = std::max(P.max_free, nfw);
         P.max_items = std::max<int64_t>(P.max_items, nit);
+        P.max_surv = std::max(P.max_surv, nsv);
         P.max_chunk_cfgs = std::max<int64_t>(P.max_chunk_cfgs, ch.c1 - ch.c0);
         ppt += pp;
         if (ppt > INT32_MAX) return set_err(ctx, FFTDG_E_INVALID, "scan: more than 2^31 valid z-translations in one batch");
@@ -561,6 +585,7 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
                 P.fwd_off.push_back(nf);
                 P.inv_off.push_back(ni);
                 P.item_off.push_back(0);
+                P.item2_off.push_back(0);
                 nf += e_items + (occ ? d.Lo : 0);
                 ni += d.V[2];
                 P.zcfg.push_back(local);
@@ -577,6 +602,7 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
                 P.fwd_off.push_back(nf);
                 P.inv_off.push_back(ni);
                 P.item_off.push_back(0);
+                P.item2_off.push_back(0);
             }
             ++c;
         }
@@ -584,6 +610,7 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
         P.fwd_off.push_back(nf);
         P.inv_off.push_back(ni);
         P.item_off.push_back(0);
+        P.item2_off.push_back(0);
         ch.nfwd = nf;
         ch.ninv = ni;
         ch.nz = P.zcfg.size() - ch.z0;
@@ -629,7 +656,8 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     const size_t o_fwd = align256(o_u + sizeof(int32_t) * P.U.size());
     const size_t o_inv = align256(o_fwd + sizeof(int32_t) * P.fwd_off.size());
     const size_t o_item = align256(o_inv + sizeof(int32_t) * P.inv_off.size());
-    const size_t o_z = align256(o_item + sizeof(int32_t) * P.item_off.size());
+    const size_t o_item2 = align256(o_item + sizeof(int32_t) * P.item_off.size());
+    const size_t o_z = align256(o_item2 + sizeof(int32_t) * P.item2_off.size());
     const size_t o_gam = align256(o_z + sizeof(int32_t) * P.zcfg.size());
     const size_t o_thr = align256(o_gam + tsz * 3 * na);
     const size_t total = align256(o_thr + sizeof(double) * na);
@@ -642,6 +670,7 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     std::memcpy(h + o_fwd, P.fwd_off.data(), sizeof(int32_t) * P.fwd_off.size());
     std::memcpy(h + o_inv, P.inv_off.data(), sizeof(int32_t) * P.inv_off.size());
     std::memcpy(h + o_item, P.item_off.data(), sizeof(int32_t) * P.item_off.size());
+    std::memcpy(h + o_item2, P.item2_off.data(), sizeof(int32_t) * P.item2_off.size());
     if (!P.zcfg.empty()) std::memcpy(h + o_z, P.zcfg.data(), sizeof(int32_t) * P.zcfg.size());
     if (g.precision == FFTDG_F32)
         fill_gamma<float>(b, (float *)(h + o_gam));
@@ -650,12 +679,25 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     double *thr = (double *)(h + o_thr);
     for (int i = 0; i < na; ++i) thr[i] = occ ? occ_threshold(g, b->sigma[i]) : 0.0;
     const size_t cb = (size_t)ctx->ks->cbytes;
-    if (!P.fused && (rc = reserve(ctx, ctx->ws_fwd, cb * (size_t)std::max<int64_t>(P.max_fwd, 1)))) return rc;
+    if ((!P.fused || P.fused_planes) && (rc = reserve(ctx, ctx->ws_fwd, cb * (size_t)std::max<int64_t>(P.max_fwd, 1))))
+        return rc;
+    int64_t max_nz_atoms = 1;
+    if (P.fused) {
+        int64_t nzmax = 1;
+        for (const Plan::Chunk &ch : P.chunks) {
+            nzmax = std::max<int64_t>(nzmax, (int64_t)ch.nz);
+            max_nz_atoms = std::max<int64_t>(max_nz_atoms, (int64_t)ch.nz * std::max(ch.max_atoms, 1));
+        }
+        if ((rc = reserve(ctx, ctx->zat, ctx->fs->zat_bytes * (size_t)max_nz_atoms))) return rc;
+        if ((rc = reserve(ctx, ctx->zbt, sizeof(int32_t) * (size_t)nzmax * (g.n_fft + 2)))) return rc;
+    }
     if (P.fused && occ) {
-        if ((rc = reserve(ctx, ctx->runs, sizeof(uint32_t) * (size_t)std::max<int64_t>(P.max_runs, 1)))) return rc;
+        if ((rc = reserve(ctx, ctx->runs, 2 * sizeof(uint32_t) * (size_t)std::max<int64_t>(P.max_runs, 1)))) return rc;
         if ((rc = reserve(ctx, ctx->run_cnt, sizeof(int32_t) * (size_t)std::max<int64_t>(P.max_chunk_cfgs, 1)))) return rc;
         if ((rc = reserve(ctx, ctx->fbits, sizeof(uint32_t) * (size_t)std::max<int64_t>(P.max_free, 1)))) return rc;
         if ((rc = reserve(ctx, ctx->lives, (size_t)std::max<int64_t>(P.max_items, 1)))) return rc;
+        if ((rc = reserve(ctx, ctx->surv, sizeof(uint32_t) * (size_t)std::max<int64_t>(P.max_surv, 1)))) return rc;
+        if ((rc = reserve(ctx, ctx->scnt, sizeof(int32_t) * (size_t)std::max<int64_t>(P.max_chunk_cfgs, 1)))) return rc;
     }
     // snapshots whose inverse planes share the workspace: the z kernel keeps
     // a configuration's forward spectra in registers across the group
@@ -680,6 +722,7 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     const int32_t *dfwd = (const int32_t *)(d + o_fwd);
     const int32_t *dinv = (const int32_t *)(d + o_inv);
     const int32_t *ditem = (const int32_t *)(d + o_item);
+    const int32_t *ditem2 = (const int32_t *)(d + o_item2);
     const int32_t *dz = (const int32_t *)(d + o_z);
     const void *dgam = (const void *)(d + o_gam);
     const double *dthr = (const double *)(d + o_thr);
@@ -707,21 +750,37 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
         const CfgDev *ccfg = dcfg + ch.c0;
         const int nloc = ch.c1 - ch.c0;
         if (occ)
-            HIPCHK(ctx, timed(ctx, FFTDG_K_RUNS, 4.0 * (double)ch.nruns, [&] {
+            HIPCHK(ctx, timed(ctx, FFTDG_K_RUNS, 8.0 * (double)ch.nruns, [&] {
                        return fs->lig_runs(st, ccfg, dz + ch.z0, (int)ch.nz, du, dthr, runs, rcnt);
+                   }));
+        if (P.fused_planes)
+            HIPCHK(ctx, timed(ctx, FFTDG_K_FWD, (double)ch.ws_fwd * cb, [&] {
+                       return ks->fwd(st, true, dfwd + ch.off0, nloc, (int)ch.nfwd, ccfg, du, dgam, dthr, ctx->tw.p,
+                                      ctx->ws_fwd.p);
+                   }));
+        else
+            HIPCHK(ctx, timed(ctx, FFTDG_K_RUNS, (double)ch.nz * ch.max_atoms * fs->zat_bytes, [&] {
+                       return fs->zprep(st, ccfg, dz + ch.z0, (int)ch.nz, std::max(ch.max_atoms, 1), du, dgam,
+                                        ctx->zat.p, (int32_t *)ctx->zbt.p);
                    }));
         for (int s = s_begin; s < s_end; ++s) {
             if (occ) {
                 const uint32_t *dil = (const uint32_t *)ctx->dil.p + (size_t)s * (size_t)fs->dil_words;
                 HIPCHK(ctx, timed(ctx, FFTDG_K_CLASH, 4.0 * (double)ch.nfree + (double)ch.nitems, [&] {
-                           return fs->clash(st, ditem + ch.off0, nloc, ch.nitems, ccfg, runs, rcnt, dil, fb, lv);
+                           return fs->clash(st, ditem + ch.off0, ditem2 + ch.off0, nloc, ch.nitems, ch.nitems2, ccfg,
+                                            runs, rcnt, dil, fb, lv, (uint32_t *)ctx->surv.p,
+                                            (int32_t *)ctx->scnt.p);
                        }));
             }
             const char *rs = (const char *)ctx->rspec.p + spec_per_snap * s;
             // planes written are counted on the device (those the inverse reads)
-            HIPCHK(ctx, timed(ctx, FFTDG_K_ZPROD, b_spec3, [&] {
+            HIPCHK(ctx, timed(ctx, FFTDG_K_ZPROD, b_spec3 + (P.fused_planes ? (double)ch.ws_fwd * cb : 0.0), [&] {
+                       if (P.fused_planes)
+                           return fs->zplanes(st, ch.zhalf != 0, occ && !exporting, ccfg, dz + ch.z0, (int)ch.nz,
+                                              ctx->ws_fwd.p, rs, ctx->tw.p, ctx->ws_inv.p, lv);
                        return fs->zpass(st, ch.zhalf != 0, occ && !exporting, ccfg, dz + ch.z0, (int)ch.nz,
-                                        ch.max_atoms, rs, ctx->tw.p, ctx->ws_inv.p, du, dgam, lv);
+                                        std::max(ch.max_atoms, 1), ctx->zat.p, (const int32_t *)ctx->zbt.p, rs,
+                                        ctx->tw.p, ctx->ws_inv.p, lv);
                    }));
             void *pp_s = (char *)ctx->pp.p + pp_snap * (size_t)(s - s_begin);
             HIPCHK(ctx, timed(ctx, FFTDG_K_INV, pb * ch.pp, [&] {
@@ -788,10 +847,12 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     };
     const bool graph_ok = ctx->use_graph && !ctx->prof && !psi_out && !clash_out && out;
     if (!graph_ok) return launch_all(ctx->stream);
-    std::vector<int64_t> sig = {(int64_t)(intptr_t)ks, occ, ctx->edirect, grp, s_begin, s_end, P.fused,
+    std::vector<int64_t> sig = {(int64_t)(intptr_t)ks, occ, ctx->edirect, grp, s_begin, s_end, P.fused, P.fused_planes,
                                 (int64_t)(intptr_t)ctx->runs.p, (int64_t)(intptr_t)ctx->run_cnt.p,
                                 (int64_t)(intptr_t)ctx->fbits.p, (int64_t)(intptr_t)ctx->lives.p,
-                                (int64_t)(intptr_t)ctx->dil.p, (int64_t)o_item,
+                                (int64_t)(intptr_t)ctx->dil.p, (int64_t)o_item, (int64_t)(intptr_t)ctx->zat.p,
+                                (int64_t)(intptr_t)ctx->zbt.p, (int64_t)(intptr_t)ctx->surv.p,
+                                (int64_t)(intptr_t)ctx->scnt.p, (int64_t)o_item2,
                                 (int64_t)(intptr_t)out, (int64_t)(intptr_t)ctx->tables.p,
                                 (int64_t)(intptr_t)ctx->ws_fwd.p, (int64_t)(intptr_t)ctx->ws_inv.p,
                                 (int64_t)(intptr_t)ctx->pp.p, (int64_t)(intptr_t)ctx->rspec.p,
@@ -803,7 +864,8 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     for (const Plan::Chunk &ch : P.chunks)
         for (int64_t v : {(int64_t)ch.c0, (int64_t)ch.c1, (int64_t)ch.off0, (int64_t)ch.nfwd, (int64_t)ch.ninv,
                           (int64_t)ch.z0, (int64_t)ch.nz, ch.ws_fwd, ch.ws_inv, (int64_t)ch.pp, (int64_t)ch.zhalf,
-                          (int64_t)ch.nitems, ch.nruns, ch.nfree, (int64_t)ch.max_atoms})
+                          (int64_t)ch.nitems, (int64_t)ch.nitems2, ch.nsurv, ch.nruns, ch.nfree,
+                          (int64_t)ch.max_atoms})
             sig.push_back(v);
     if (!(ctx->graph_exec && sig == ctx->graph_sig)) {
         if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
@@ -890,7 +952,7 @@ int fftdg_create(fftdg_ctx **out, const fftdg_grid_desc *g, int device, void *hi
     c->stream = (hipStream_t)hip_stream;
     c->ks = ks;
     c->fs = fused_set(g->precision, g->n_fft);
-    c->fused = c->fs != nullptr;
+    c->fused = c->fs != nullptr ? 1 : 0;
     c->n_ch = g->clash_mode == FFTDG_OCC ? 4 : 3;
     if (hipSetDevice(device) != hipSuccess || hipEventCreateWithFlags(&c->staging_ev, hipEventDisableTiming) != hipSuccess) {
         (void)hipGetLastError();
@@ -934,7 +996,8 @@ void fftdg_destroy(fftdg_ctx *c) {
     DevBuf *bufs[] = {&c->tw, &c->rspec, &c->rxy, &c->ws_fwd, &c->ws_inv, &c->pp, &c->tables,
                       &c->red_B, &c->red_res, &c->red_off, &c->red_W, &c->prof_cnt, &c->tune_out,
                       &c->sir_psi, &c->sir_clash, &c->sir_u, &c->sir_lin, &c->sir_psi_out,
-                      &c->dil, &c->runs, &c->run_cnt, &c->fbits, &c->lives};
+                      &c->dil, &c->runs, &c->run_cnt, &c->fbits, &c->lives, &c->zat, &c->zbt, &c->surv,
+                      &c->scnt};
     for (DevBuf *b : bufs)
         if (b->p) (void)hipFree(b->p);
     if (c->pinned) (void)hipHostFree(c->pinned);
@@ -1178,7 +1241,7 @@ int fftdg_get_tuning(const fftdg_ctx *ctx, fftdg_tuning *t) {
     t->energy_xy_direct = ctx->edirect;
     t->snapshots_per_pass = ctx->snap_group;
     t->use_graph = ctx->use_graph ? 1 : 0;
-    t->fused = ctx->fused ? 1 : 0;
+    t->fused = ctx->fused;
     return FFTDG_OK;
 }
 
@@ -1194,11 +1257,11 @@ int fftdg_set_tuning(fftdg_ctx *ctx, const fftdg_tuning *t) {
     ctx->chunk_cfgs = t->configs_per_chunk;
     ctx->edirect = t->energy_xy_direct;
     if (t->use_graph != 0 && t->use_graph != 1) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: use_graph must be 0 or 1");
-    if (t->fused != 0 && t->fused != 1) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: fused must be 0 or 1");
+    if (t->fused < 0 || t->fused > 2) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: fused must be 0, 1 or 2");
     if (t->fused && !ctx->fs) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: the fused path needs n_fft <= 128");
     ctx->snap_group = t->snapshots_per_pass;
     ctx->use_graph = t->use_graph != 0;
-    ctx->fused = t->fused != 0;
+    ctx->fused = t->fused;
     return FFTDG_OK;
 }
 
@@ -1272,7 +1335,7 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
     bs.cfg_select = sel.data();
     if ((rc = reserve(ctx, ctx->tune_out, sizeof(fftdg_partial) * (size_t)ncfg * ctx->n_snap))) return rc;
     const fftdg_tuning keep = {ctx->chunk_cfgs, ctx->edirect, ctx->snap_group, ctx->use_graph ? 1 : 0,
-                               ctx->fused ? 1 : 0};
+                               ctx->fused};
     const bool prof = ctx->prof;
     ctx->prof = false;
     std::vector<fftdg_tuning> cand;
@@ -1280,7 +1343,8 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
     if (ctx->n_snap > 1) passes.push_back(ctx->n_snap);
     for (int chunk : {64, 128, 256, 512}) {
         if (ctx->fs)
-            for (int gr : {0, 1}) cand.push_back(fftdg_tuning{chunk, ctx->edirect, 1, gr, 1});
+            for (int fu : {1, 2})
+                for (int gr : {0, 1}) cand.push_back(fftdg_tuning{chunk, ctx->edirect, 1, gr, fu});
         for (int ed : {0, 1, 2})
             for (int sp : passes)
                 for (int gr : {0, 1})
@@ -1297,7 +1361,7 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
         ctx->edirect = t.energy_xy_direct;
         ctx->snap_group = t.snapshots_per_pass;
         ctx->use_graph = t.use_graph != 0;
-        ctx->fused = t.fused != 0;
+        ctx->fused = t.fused;
         float tmin = INFINITY;
         for (int rep = 0; rep < 5 && !err; ++rep) {  // a warm-up run, then the fastest of four
             Plan P;
@@ -1324,7 +1388,7 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
         ctx->edirect = keep.energy_xy_direct;
         ctx->snap_group = keep.snapshots_per_pass;
         ctx->use_graph = keep.use_graph != 0;
-        ctx->fused = keep.fused != 0;
+        ctx->fused = keep.fused;
         if (err == FFTDG_E_DEVICE && ctx->err.empty()) ctx->err = "autotune: HIP event error";
         return err;
     }
@@ -1332,7 +1396,7 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
     ctx->edirect = bt.energy_xy_direct;
     ctx->snap_group = bt.snapshots_per_pass;
     ctx->use_graph = bt.use_graph != 0;
-    ctx->fused = bt.fused != 0;
+    ctx->fused = bt.fused;
     if (out) *out = bt;
     if (ms_host) *ms_host = best / ((double)nsel * ctx->n_snap);
     return FFTDG_OK;

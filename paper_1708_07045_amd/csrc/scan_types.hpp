@@ -27,7 +27,7 @@ struct CfgDev {
     int32_t run_cap;     // slots reserved for them (an upper bound on the count)
     int32_t free_off;    // first word of its free-translation bits in the chunk
     int32_t item_base;   // first (tz, 64-row group) item of its clash test in the chunk
-    int32_t pad0;
+    int32_t surv_off;    // first slot of its list of undecided rows (Vz * Vy slots)
     int64_t off_fwd;     // complex-element offset of its forward planes
     int64_t off_inv;     // complex-element offset of its inverse planes
 };

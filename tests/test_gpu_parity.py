@@ -133,11 +133,13 @@ def test_energy_c2_fp32_occ(edirect):
     _energy_parity(w, [0, 13, 27, 40, 66, 95], "f32", TOL_F32, energy_xy_direct=edirect)
 
 
-def test_energy_c2_fp32_occ_fused():
-    """Fused path: energies from the per-atom z inputs, clash masks from the
-    bitwise test, against the oracle's direct sums and exact overlap test."""
+@pytest.mark.parametrize("fused", [1, 2])
+def test_energy_c2_fp32_occ_fused(fused):
+    """Fused path (energy planes from the forward pass, or z inputs formed
+    in the z kernel): energies and the clash masks of the bitwise test
+    against the oracle's direct sums and exact overlap test."""
     w = synth.config2(n_rot=12, n_conf=8)
-    _energy_parity(w, [0, 5, 13, 27, 40, 66, 81, 95], "f32", TOL_F32, fused=1)
+    _energy_parity(w, [0, 5, 13, 27, 40, 66, 81, 95], "f32", TOL_F32, fused=fused)
 
 
 def test_energy_c2_fp32_cap_and_fp64_n64():
@@ -148,10 +150,12 @@ def test_energy_c2_fp32_cap_and_fp64_n64():
     for prec, tol in [("f32", TOL_F32), ("f64", TOL_F64)]:
         for ed in (1, 0, 2):
             _energy_parity(w, [0, 3, 5], prec, tol, energy_xy_direct=ed)
-        _energy_parity(w, [0, 3, 5], prec, tol, fused=1)
+        for fu in (1, 2):
+            _energy_parity(w, [0, 3, 5], prec, tol, fused=fu)
     w.clash_mode = "cap"
     _energy_parity(w, [1, 6], "f32", 2e-5)
-    _energy_parity(w, [1, 6], "f32", 2e-5, fused=1)
+    for fu in (1, 2):
+        _energy_parity(w, [1, 6], "f32", 2e-5, fused=fu)
 
 
 @pytest.mark.parametrize("n_fft,h,prec", [(32, 0.8, "f32"), (64, 0.4, "f32"), (32, 0.8, "f64")])
@@ -170,7 +174,8 @@ def test_direct_energy_many_atoms_per_plane(n_fft, h, prec):
     assert len(set(np.floor(u[:, 2]).astype(int).tolist())) <= 2
     for ed in (0, 2):
         _energy_parity(w, [0, 1, 2], prec, TOL_F32 if prec == "f32" else TOL_F64, energy_xy_direct=ed)
-    _energy_parity(w, [0, 1, 2], prec, TOL_F32 if prec == "f32" else TOL_F64, fused=1)
+    for fu in (1, 2):
+        _energy_parity(w, [0, 1, 2], prec, TOL_F32 if prec == "f32" else TOL_F64, fused=fu)
 
 
 def test_single_point_charge_gpu():
@@ -259,9 +264,9 @@ def test_scan_c1_fp64(edirect):
     _scan_parity(synth.config1(), "f64", 1e-8, energy_xy_direct=edirect)
 
 
-@pytest.mark.parametrize("chunk", [256, 7])
-def test_scan_c1_fp64_fused(chunk):
-    _scan_parity(synth.config1(), "f64", 1e-8, fused=1, configs_per_chunk=chunk)
+@pytest.mark.parametrize("fused,chunk", [(1, 256), (1, 7), (2, 256), (2, 7)])
+def test_scan_c1_fp64_fused(fused, chunk):
+    _scan_parity(synth.config1(), "f64", 1e-8, fused=fused, configs_per_chunk=chunk)
 
 
 @pytest.mark.parametrize("edirect,chunk", [(1, 256), (0, 256), (1, 7), (2, 256), (2, 7)])
@@ -270,10 +275,10 @@ def test_scan_c2_subset_fp32(edirect, chunk):
     _scan_parity(w, "f32", 0.01, energy_xy_direct=edirect, configs_per_chunk=chunk)
 
 
-@pytest.mark.parametrize("chunk,graph", [(256, 0), (7, 0), (32, 1)])
-def test_scan_c2_subset_fp32_fused(chunk, graph):
+@pytest.mark.parametrize("fused,chunk,graph", [(1, 256, 0), (1, 7, 0), (1, 32, 1), (2, 256, 0), (2, 7, 0), (2, 32, 1)])
+def test_scan_c2_subset_fp32_fused(fused, chunk, graph):
     w = synth.subset(synth.config2(), 96, stride=83)
-    _scan_parity(w, "f32", 0.01, fused=1, configs_per_chunk=chunk, use_graph=graph)
+    _scan_parity(w, "f32", 0.01, fused=fused, configs_per_chunk=chunk, use_graph=graph)
 
 
 @pytest.mark.parametrize("snap_pass,chunk,edirect", [(16, 256, 0), (1, 256, 0), (2, 5, 0), (1, 64, 2), (16, 9, 2)])
@@ -287,12 +292,12 @@ def test_scan_batched_uneven_ligands_three_snapshots(snap_pass, chunk, edirect):
     assert P.shape[0] == 3
 
 
-@pytest.mark.parametrize("chunk", [256, 5])
-def test_scan_batched_uneven_ligands_three_snapshots_fused(chunk):
+@pytest.mark.parametrize("fused,chunk", [(1, 256), (1, 5), (2, 256), (2, 5)])
+def test_scan_batched_uneven_ligands_three_snapshots_fused(fused, chunk):
     """The ragged three-snapshot batch on the fused path: one occupancy-run
     pass per chunk, the clash test, z pass and inverse per snapshot."""
     w = synth.config3(n_ligands=5, n_snap=3, cfg_scale=0.02)
-    P, B, res = _scan_parity(w, "f32", 0.01, fused=1, configs_per_chunk=chunk)
+    P, B, res = _scan_parity(w, "f32", 0.01, fused=fused, configs_per_chunk=chunk)
     assert P.shape[0] == 3
 
 

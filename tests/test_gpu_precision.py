@@ -19,7 +19,7 @@ GOLD = os.path.join(os.path.dirname(__file__), "golden", "c2_oracle.json")
 
 
 @pytest.mark.parametrize("mode,tol", [("occ", 0.01), ("cap", 0.01)])
-@pytest.mark.parametrize("fused,energy_xy_direct", [(1, 0), (0, 0), (0, 2)])
+@pytest.mark.parametrize("fused,energy_xy_direct", [(1, 0), (2, 0), (0, 0), (0, 2)])
 def test_full_c2_fp32_against_fp64_oracle(mode, tol, fused, energy_xy_direct):
     import torch
     import paper_1708_07045_amd as fd
