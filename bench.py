@@ -23,26 +23,45 @@ sys.path.insert(0, ROOT)
 
 METRIC = "ligand configs/sec (FFT scan) + configs needed for BPMF ±0.1 kcal/mol, MLP vs plain"
 HBM_PEAK_GBS = 8000.0
-# FP32 vector peak with one FMA per lane per cycle: 256 CUs x 4 SIMDs x 16
-# lanes x 2 flops x 2.4 GHz.  The packed-FP32 forms that would double it are
-# kept out of the build, so this is the attainable arithmetic peak.
-VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-VALU_FP32_PACKED_PEAK_TFLOPS = 2 * VALU_FP32_PEAK_TFLOPS
+# FP32 vector peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x
+# 2 (packed FP32, two FMAs per lane per cycle) x 2.4 GHz = 157.3 TFLOP/s.
+# This build keeps packed-FP32 instructions out of its kernels, so half of
+# it, 78.6 TFLOP/s, is the rate its instructions can issue at.
+VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2 * 2.4e9 / 1e12
+VALU_FP32_NONPACKED_TFLOPS = VALU_FP32_PEAK_TFLOPS / 2
 
 
-def zpass_flops(n_fft: int, occ: bool, n_cfg: int, n_snap: int, snap_pass: int) -> float:
+def zpass_flops(n_fft: int, n_in: int, n_out: int, occ_product: bool, n_cfg: int, n_snap: int,
+                snap_pass: int) -> float:
     """Algorithmic flops of the z pass for n_cfg configurations x n_snap
     snapshots: over the N (N/2 + 1) pencils, 5 N log2 N per complex length-N
-    transform (n_in = 3 (+1 occupancy) forward, once per pass of snap_pass
-    snapshots; n_out = 1 (+1) inverse per snapshot) and per spectral point 8
-    flops per energy channel's R * conj(L) multiply-add (3 channels) plus 6
-    for the occupancy product."""
+    transform (n_in forward, once per pass of snap_pass snapshots; n_out
+    inverse per snapshot) and per spectral point 8 flops per energy
+    channel's R * conj(L) multiply-add (3 channels), plus 6 for the
+    occupancy product on the plane path."""
     N = n_fft
     pencils = N * (N // 2 + 1)
     t = 5.0 * N * math.log2(N)
-    n_in, n_out = (4, 2) if occ else (3, 1)
     passes = -(-n_snap // max(1, snap_pass))
-    return float(n_cfg) * pencils * (n_in * t * passes + n_snap * (n_out * t + N * (24 + (6 if occ else 0))))
+    return float(n_cfg) * pencils * (n_in * t * passes + n_snap * (n_out * t + N * (24 + (6 if occ_product else 0))))
+
+
+def s8d_bytes_per_cfg(P, n_fft: int, occ: bool, B_rc: int) -> float:
+    """Algorithmic bytes per configuration of the scan as the survey's
+    measurement section defines them (what the method must move when a 3D FFT
+    does not fit one CU's LDS): 16 N (N/2 + 1) (n_in L_z + n_out V_z) + 8 S_h
+    n_rc / B_rc, with n_in = n_rc = 4, n_out = 2 in occupancy mode (3, 1 in
+    cap mode), L_z = B_z + 1 and V_z from this workload's placements, S_h =
+    N^2 (N/2 + 1) and B_rc configurations per receptor read.  Evaluated over
+    the scanned configurations: the mean of the per-configuration figure."""
+    import numpy as np
+    N = n_fft
+    nh = N * (N // 2 + 1)
+    n_in, n_out = (4, 2) if occ else (3, 1)
+    box_z = np.asarray(P["box_z"], dtype=np.float64)
+    vz = np.asarray(P["V_z"], dtype=np.float64)
+    per = 16.0 * nh * (n_in * (box_z + 1.0) + n_out * vz) + 8.0 * N * nh * n_in / max(1, B_rc)
+    return float(per.mean())
 
 
 def log(*a):
@@ -50,7 +69,8 @@ def log(*a):
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "zprod_t4l_8000cfg_hbm_traffic.md")
-KERNEL_SOURCES = ["scan_kernels.hip", "fft_device.hpp", "scan_types.hpp", "kernels.hpp"]
+KERNEL_SOURCES = ["scan_kernels.hip", "fused_kernels.hip", "fft_device.hpp", "scan_types.hpp", "kernels.hpp",
+                  "scan_common.hpp", "fused.hpp"]
 
 
 def kernel_source_digest() -> str:
@@ -79,7 +99,9 @@ def recorded_traffic(tuning: dict):
         # (about 1 % of its bytes at 128 configurations per chunk, less above)
         if rec["kernel_source_sha256"] != kernel_source_digest():
             return None
-        if int(rec["energy_xy_direct"]) != tuning["energy_xy_direct"] or tuning["configs_per_chunk"] < 128:
+        if int(rec.get("fused", 0)) != tuning.get("fused", 0) or tuning["configs_per_chunk"] < 128:
+            return None
+        if tuning.get("fused", 0) == 0 and int(rec["energy_xy_direct"]) != tuning["energy_xy_direct"]:
             return None
         return float(rec["hbm_bytes_per_cfg"])
     except (KeyError, ValueError):
@@ -182,6 +204,7 @@ def cpu_fft_baseline(w, budget_s: float):
     fft_cpu.scan(w, spec, 0, sel)
     dt = time.perf_counter() - t0
     return {"value": n / dt, "unit": "configs/s", "cores": fft_cpu._workers(), "kind": "fft_cpu",
+            "cpu_model": cpu_model(),
             "sample": f"{n} of {n_all} configurations (evenly strided), FP64 scipy.fft (pocketfft) rfftn/irfftn "
                       f"of the {w.n_fft}^3 grids, 4 forward + 2 inverse transforms per configuration, {dt:.1f} s"}
 
@@ -196,6 +219,31 @@ PAPER_CPU_TIMES = {
     "configs_per_s_if_1000_configs": {"16A_0.25A": 1000 / 139.0, "16A_0.125A": 1000 / 1706.0,
                                       "62A_0.25A": 1000 / 25390.0},
 }
+
+
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def oracle_c1_rate():
+    """The oracle over the whole tiny FP64 workload (300-atom receptor, 32^3
+    grid, one 12-atom ligand x 100 rotations, cap mode): configurations/s."""
+    import oracle
+    from workload import synth
+    w = synth.config1()
+    go, oo = oracle.receptor_grids(w)
+    t0 = time.perf_counter()
+    oracle.scan(w, go, oo)
+    dt = time.perf_counter() - t0
+    return {"value": w.ligands[0].n_cfg / dt, "unit": "configs/s", "sample": "all 100 configurations",
+            "seconds": dt}
 
 
 def cpu_baseline(w, budget_s: float):
@@ -219,8 +267,66 @@ def cpu_baseline(w, budget_s: float):
     dt = time.perf_counter() - t0
     threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or len(os.sched_getaffinity(0))
     return {"value": len(sel) / dt, "unit": "configs/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(),
             "sample": f"{len(sel)} of {n_all} configurations (evenly strided), FP64 direct trilinear sum "
-                      f"+ exact clash test + partials, OpenMP over configurations, {dt:.1f} s"}
+                      f"+ exact clash test + partials, OpenMP over configurations, {dt:.1f} s",
+            "tiny_workload": oracle_c1_rate()}
+
+
+def batched_timing(reps: int = 3):
+    """The whole batched workload (141 ligands of 8-40 atoms, 200-2000
+    configurations each, 10 jittered receptor snapshots, 128^3 FFT) scanned
+    exhaustively under the autotuned schedule: the median of `reps` scans
+    timed with HIP events on the library's stream (receptor spectra built
+    beforehand), the per-kernel table of one more, profiled, scan, and the
+    survey's per-configuration bytes at that rate."""
+    import numpy as np
+    import torch
+    import paper_1708_07045_amd as fd
+    from workload import synth
+    w = synth.config3(cfg_scale=1.0)
+    S = w.receptor.n_snap
+    ctx = fd.FFTDG.from_workload(w)
+    gl, ol = [], []
+    for sn in range(S):
+        g, o = ctx.receptor_grids(w.receptor.xyz[sn], w.receptor.q, w.receptor.sigma, w.receptor.eps)
+        gl.append(g)
+        ol.append(o)
+    ctx.set_receptors(torch.stack(gl).contiguous(), torch.stack(ol).contiguous(), w.receptor.weights)
+    del gl, ol
+    b = fd.Batch(w.ligands)
+    log(f"batched timing: {len(w.ligands)} ligands, {b.n_cfg} configurations x {S} snapshots")
+    tun, _ = ctx.autotune(b, w.T, max_cfgs=2048)
+    out = ctx.alloc_partials(b)
+    ctx.scan(b, w.T, out)
+    torch.cuda.synchronize()
+    ms = []
+    for r in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        ctx.scan(b, w.T, out)
+        e1.record()
+        torch.cuda.synchronize()
+        ms.append(e0.elapsed_time(e1))
+        log(f"batched scan {r + 1}/{reps}: {ms[-1]:.0f} ms")
+    ctx.profile(True)
+    ctx.scan(b, w.T, out)
+    prof = ctx.profile_read()
+    ctx.profile(False)
+    med = float(np.median(ms))
+    scans = b.n_cfg * S
+    boxes = ctx.boxes(b)
+    s8d = s8d_bytes_per_cfg({"box_z": boxes[:, 2], "V_z": np.maximum(w.n_rec - boxes[:, 2], 0)}, w.n_fft,
+                            w.clash_mode == "occ", tun["configs_per_chunk"])
+    rate = scans / (med / 1e3)
+    B, res = ctx.reduce(b, out, w.T)
+    return {"workload": f"batched: {len(w.ligands)} ligands of 8-40 atoms, {b.n_cfg} configurations, {S} jittered "
+                        f"receptor snapshots, {w.n_rec}^3 grid in a {w.n_fft}^3 FFT, occupancy clash mode",
+            "tuning": tun, "scan_ms": ms, "scan_ms_median": med, "scans_per_s": rate,
+            "configs_per_s": b.n_cfg / (med / 1e3),
+            "kernels_ms": {k: v[0] for k, v in prof.items() if v[1] > 0},
+            "s8d_bytes_per_scan": s8d, "s8d_GBps": s8d * rate / 1e9, "s8d_frac_of_peak": s8d * rate / 1e9 / HBM_PEAK_GBS,
+            "dG_mean_kcal_mol": float(np.mean(res["dG"]))}
 
 
 def configs_needed(args):
@@ -242,9 +348,8 @@ def configs_needed(args):
     S = w.receptor.n_snap
     log(f"configs needed: {len(w.ligands)} ligands, {b.n_cfg} configurations x {S} snapshots")
     ctx_f = prop.make_context(w)
-    # coarse pre-scan at twice the spacing against every snapshot (with
-    # --is-coarse-first-snapshot: the first one only, ten times cheaper, but
-    # its ranking does not carry over to the other jittered snapshots)
+    # coarse pre-scan at twice the spacing: against one receptor at the
+    # snapshots' mean coordinates (default), every snapshot, or the first
     ctx_c = prop.make_context(w, prop.coarse_desc(w), snapshots=args.is_coarse_snapshots)
     ctx_f.autotune(b, T, max_cfgs=2048)
     ctx_c.autotune(b, T, max_cfgs=2048)
@@ -268,9 +373,10 @@ def configs_needed(args):
     Xc = X[:, :fd.N_FEATURES].contiguous()
     t, wt = prop.targets(ctx_f, b, part_f)
     nets, t_train = {}, {}
-    for name, xin in (("net_scan", X), ("net_cfg", Xc)):
-        net = fd.Network(int(xin.shape[1]), 256, 512)
-        net.set_params(prop.init_params(int(xin.shape[1]), 256))
+    # net_scan: residual form (coarse relative log weight through the skip);
+    # net_cfg: configuration descriptors only
+    for name, xin, resid in (("net_scan", X, True), ("net_cfg", Xc, False)):
+        net = prop.make_network(int(xin.shape[1]), 256, residual=resid)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         hist = prop.train(net, xin, t, wt, rows, epochs=args.is_epochs)
@@ -335,6 +441,7 @@ def configs_needed(args):
     dB = est["B"] - Bref
     ddg = est["res"]["dG"] - dref
     n_is = int(est["n_scanned"].sum())
+    fin = np.isfinite(dB)
     return {
         "workload": f"batched: {len(w.ligands)} ligands x {S} snapshots, {b.n_cfg} configurations, "
                     f"101 training / {len(test_l)} held-out ligands (seeded split)",
@@ -342,7 +449,7 @@ def configs_needed(args):
                      "cost = distinct fine-scanned configurations (+ coarse pre-scan at its cost ratio)",
         "replicates": args.is_reps,
         "coarse_cost_ratio": rho,
-        "coarse_snapshots": w.receptor.n_snap if args.is_coarse_snapshots is None else len(args.is_coarse_snapshots),
+        "coarse_receptors": args.is_coarse,
         "mixture_alpha": alpha,
         "mixture_tau_nats": tau_of,
         "train_seconds": t_train,
@@ -350,9 +457,13 @@ def configs_needed(args):
         "median_fraction_of_pool": {k: float(np.median([r[k] / r["n_cfg"] for r in per]))
                                     for k in ("plain", "net_scan", "net_cfg", "coarse")},
         "is_run_10pct": {"configs_scanned": n_is, "configs_total": int(bt.n_cfg),
+                         "cost_fine_equivalents": n_is + rho * bt.n_cfg,
                          "fallback_ligands": int(est["fallback"].sum()),
-                         "rms_dB_kcal_mol": float(np.sqrt(np.mean(dB[np.isfinite(dB)] ** 2))),
-                         "max_abs_dB_kcal_mol": float(np.max(np.abs(dB[np.isfinite(dB)]))),
+                         "fallback_rule": "predicted weight outside the exact stratum > 0.5 (decided before the draw)",
+                         "max_sampled_share": float(np.max(est["share"])),
+                         "rms_dB_kcal_mol": float(np.sqrt(np.mean(dB[fin] ** 2))),
+                         "max_abs_dB_kcal_mol": float(np.max(np.abs(dB[fin]))),
+                         "n_infinite_dB": int(np.count_nonzero(~fin)),
                          "rms_ddG_kcal_mol": float(np.sqrt(np.mean(ddg ** 2))),
                          "seconds_is_path_fine_only": t_is,
                          "seconds_exhaustive_fine_same_ligands": t_f * bt.n_cfg / b.n_cfg},
@@ -381,6 +492,7 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0, help="seconds of oracle work for cpu_baseline")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-is", action="store_true", help="skip the configurations-needed measurement")
+    ap.add_argument("--no-batched", action="store_true", help="skip the timed batched (141-ligand) scan")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the pose-resampling and grid-spacing measurements after the timed steps "
                          "(for profiler runs that should hold the timed kernels only)")
@@ -391,10 +503,11 @@ def main():
     ap.add_argument("--is-epochs", type=int, default=20)
     ap.add_argument("--is-tune-ligands", type=int, default=12)
     ap.add_argument("--is-detail", default="", help="write per-ligand configurations-needed results here (JSON)")
-    ap.add_argument("--is-coarse-first-snapshot", action="store_true",
-                    help="coarse pre-scan against the first snapshot only")
+    ap.add_argument("--is-coarse", default="mean", choices=["mean", "all", "first"],
+                    help="coarse pre-scan receptors: one at the snapshots' mean coordinates, every snapshot, "
+                         "or the first snapshot")
     args = ap.parse_args()
-    args.is_coarse_snapshots = [0] if args.is_coarse_first_snapshot else None
+    args.is_coarse_snapshots = {"mean": "mean", "all": None, "first": [0]}[args.is_coarse]
     if args.gpus != 1:
         print(f"bench.py: this implementation runs on one GPU; --gpus {args.gpus} is not supported "
               "(the scan would shard by ligand, snapshot and configuration chunk)", file=sys.stderr)
@@ -467,28 +580,46 @@ def main():
     for i in range(args.warmup):
         step()
         log(f"warmup step {i + 1}/{args.warmup} done")
+    # Timed steps with profiling off: the schedule as tuned (a captured
+    # graph replays when the autotuner chose one).  Each step ends in the
+    # reduce, which synchronizes, so per-step host times are step times.
     torch.cuda.synchronize()
-    ctx.profile(True)
+    step_ms = []
     t0 = time.perf_counter()
     for i in range(args.steps):
+        ts = time.perf_counter()
         step()
+        step_ms.append((time.perf_counter() - ts) * 1e3)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    log(f"timed {args.steps} steps in {t1 - t0:.3f}s")
+    # Separate profiled steps for the per-kernel table: HIP events around
+    # every launch on the library's stream (graphs are not replayed while
+    # profiling, so these steps run the same kernels eagerly).
+    n_prof = max(2, min(args.steps, 5))
+    ctx.profile(True)
+    tp0 = time.perf_counter()
+    for i in range(n_prof):
+        step()
+    torch.cuda.synchronize()
+    tp1 = time.perf_counter()
     prof = ctx.profile_read()
     ctx.profile(False)
-    log(f"timed {args.steps} steps in {t1 - t0:.3f}s")
+    log(f"profiled {n_prof} more steps in {tp1 - tp0:.3f}s")
 
     ms_step = (t1 - t0) * 1e3 / args.steps
     n_cfg = batch.n_cfg
     cfg_s = n_cfg / (ms_step / 1e3)
     P = ctx.partials_numpy(out, n_snap, n_cfg)[0]
     n_valid = int(P["n_valid"].sum())
+    tun = ctx.get_tuning()
+    fused = tun.get("fused", 0) != 0
 
     kernels = {}
     for name, (ms, n, b) in prof.items():
         if n == 0:
             continue
-        kernels[name] = {"ms_per_step": ms / args.steps, "launches_per_step": n / args.steps,
+        kernels[name] = {"ms_per_step": ms / n_prof, "launches_per_step": n / n_prof,
                          "avg_launch_us": 1e3 * ms / n, "alg_GBps": (b / 1e9) / (ms / 1e3) if ms > 0 else None,
                          "alg_bytes_per_launch": b / n}
     dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
@@ -496,23 +627,26 @@ def main():
     achieved = kd["alg_GBps"]
     traffic = None
     if dom == "zprod" and args.workload == "c2":
-        per_cfg = recorded_traffic(ctx.get_tuning())
+        per_cfg = recorded_traffic(tun)
         if per_cfg is not None:
-            traffic = per_cfg * n_cfg * args.steps / prof["zprod"][1]   # bytes per launch
+            traffic = per_cfg * n_cfg * n_prof / prof["zprod"][1]   # bytes per launch
     hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
            "copy_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps,
            "alg_bytes_per_launch": kd["alg_bytes_per_launch"]}
     if dom == "zprod":
-        # the z pass is bound by vector-ALU issue (its HBM traffic runs at a
-        # third of peak while the VALU is ~70 % busy): rate its algorithmic flops
-        tun = ctx.get_tuning()
-        fl = zpass_flops(w.n_fft, w.clash_mode == "occ", n_cfg, n_snap,
-                         tun["snapshots_per_pass"] if tun["snapshots_per_pass"] > 0 else 1)
-        fl_launch = fl * args.steps / prof["zprod"][1]
+        # the z pass is bound by vector-ALU issue (VALU busy 0.9 and more in
+        # the counter runs): rate its algorithmic flops against the FP32
+        # vector peak; its HBM view is the sub-object
+        occ = w.clash_mode == "occ"
+        n_in, n_out = (3, 1) if (fused or not occ) else (4, 2)
+        fl = zpass_flops(w.n_fft, n_in, n_out, occ and not fused, n_cfg, n_snap,
+                         tun["snapshots_per_pass"] if (tun["snapshots_per_pass"] > 0 and not fused) else 1)
+        fl_launch = fl * n_prof / prof["zprod"][1]
         tf = fl_launch / (kd["avg_launch_us"] * 1e-6) / 1e12
         roof = {"bound": "alu", "kernel": dom, "achieved": tf, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": tf / VALU_FP32_PEAK_TFLOPS, "traffic": traffic,
-                "peak_packed_fp32": VALU_FP32_PACKED_PEAK_TFLOPS, "frac_of_packed_peak": tf / VALU_FP32_PACKED_PEAK_TFLOPS,
+                "peak_nonpacked_fp32": VALU_FP32_NONPACKED_TFLOPS,
+                "frac_of_nonpacked": tf / VALU_FP32_NONPACKED_TFLOPS,
                 "avg_launch_us": kd["avg_launch_us"], "alg_flops_per_launch": fl_launch, "hbm": hbm}
     else:
         roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -520,7 +654,11 @@ def main():
                 "copy_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps,
                 "avg_launch_us": kd["avg_launch_us"], "alg_bytes_per_launch": kd["alg_bytes_per_launch"]}
     # whole path: algorithmic bytes of all scan kernels per configuration
-    path_bytes = sum(prof[k][2] for k in ("lig_fwd_xy", "zprod", "inv_xy_lse", "merge")) / args.steps
+    path_bytes = sum(prof[k][2] for k in ("lig_fwd_xy", "zprod", "inv_xy_lse", "merge", "lig_runs", "clash")
+                     if k in prof) / n_prof
+    boxes = ctx.boxes(batch)
+    s8d = s8d_bytes_per_cfg({"box_z": boxes[:, 2], "V_z": np.maximum(w.n_rec - boxes[:, 2], 0)}, w.n_fft,
+                            w.clash_mode == "occ", tun["configs_per_chunk"])
     rec = {
         "metric": METRIC,
         "value": cfg_s,
@@ -529,6 +667,9 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": ms_step,
+        "ms_per_step_median": float(np.median(step_ms)),
+        "ms_per_step_min": float(np.min(step_ms)),
+        "profiled_ms_per_step": (tp1 - tp0) * 1e3 / n_prof,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -552,6 +693,9 @@ def main():
         "path_alg_GBps": path_bytes / (ms_step / 1e3) / 1e9,
         "path_frac_of_peak": path_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
         "path_frac_of_copy": path_bytes / (ms_step / 1e3) / 1e9 / copy_gbps,
+        "s8d_bytes_per_cfg": s8d,
+        "s8d_GBps": s8d * cfg_s * n_snap / 1e9,
+        "s8d_frac_of_peak": s8d * cfg_s * n_snap / 1e9 / HBM_PEAK_GBS,
         "roofline": roof,
         "kernels": kernels,
         "precision": precision_vs_oracle(args, result),
@@ -575,9 +719,13 @@ def main():
         rec["paper_cpu_times"] = PAPER_CPU_TIMES
     else:
         rec["cpu_baseline"] = None
-    if args.workload == "c2" and not args.no_is:
+    if args.workload == "c2" and not (args.no_is and args.no_batched):
         del ctx, out, grids, occ
         torch.cuda.empty_cache()
+    if args.workload == "c2" and not args.no_batched:
+        rec["batched"] = batched_timing()
+        torch.cuda.empty_cache()
+    if args.workload == "c2" and not args.no_is:
         cn = configs_needed(args)
         rec["configs_needed"] = {k: v for k, v in cn.items() if k != "per_ligand"}
         rec["configs_needed_median_plain_over_learned"] = cn["median_plain_over"]["net_scan"]

@@ -432,6 +432,12 @@ int64_t fftdg_mlp_num_params(const fftdg_mlp *m);
 /* host <-> device parameters (synchronizes; set also resets Adam) */
 int fftdg_mlp_set_params(fftdg_mlp *m, const float *params_host, int64_t n);
 int fftdg_mlp_get_params(fftdg_mlp *m, float *params_host, int64_t n);
+/* Skip connection (the proposal's residual form): with col >= 0 the output
+ * becomes net(x) + scale * x[col], in forward, gradients and training alike
+ * (the term has no parameters: the network is trained on the residual
+ * t - scale * x[col]).  col = -1 removes it (the default).  E_INVALID if col
+ * is outside [-1, n_in) or scale is not finite. */
+int fftdg_mlp_set_skip(fftdg_mlp *m, int32_t col, float scale);
 /* y_dev[i] = net(x_dev[i]) for i < n (device arrays, x [n][n_in]) */
 int fftdg_mlp_forward(fftdg_mlp *m, const float *x_dev, int32_t n, float *y_dev);
 /* gradient of the loss over the rows idx_dev[0..B-1] (NULL = rows 0..B-1)

@@ -2,8 +2,9 @@
 (test infrastructure only; independent of the GPU kernels).
 
 Network: inputs x (n_in) -> 3 hidden layers of `width` units with SiLU
-(silu(z) = z / (1 + exp(-z))) -> 1 linear output.  Loss: weighted mean
-squared error  L = sum_i w_i (y_i - t_i)^2 / sum_i w_i.
+(silu(z) = z / (1 + exp(-z))) -> 1 linear output, optionally plus a skip
+term scale * x[col] (skip = (col, scale)).  Loss: weighted mean squared
+error  L = sum_i w_i (y_i - t_i)^2 / sum_i w_i.
 
 Flat parameter layout (shared interface with the library, row-major):
   W1 [width][n_in], b1 [width], W2 [width][width], b2 [width],
@@ -45,9 +46,10 @@ def dsilu(z):
     return s * (1.0 + z * (1.0 - s))
 
 
-def forward(p, X, n_in, width, keep=False):
+def forward(p, X, n_in, width, keep=False, skip=None):
     layers = unpack(p, n_in, width)
     H = np.asarray(X, dtype=np.float64)
+    sk = 0.0 if skip is None else skip[1] * H[:, skip[0]]
     cache = [H]
     Zs = []
     for l, (W, b) in enumerate(layers):
@@ -57,20 +59,20 @@ def forward(p, X, n_in, width, keep=False):
             H = silu(Z)
             cache.append(H)
         else:
-            y = Z[:, 0]
+            y = Z[:, 0] + sk
     return (y, cache, Zs) if keep else y
 
 
-def loss(p, X, t, w, n_in, width):
-    y = forward(p, X, n_in, width)
+def loss(p, X, t, w, n_in, width, skip=None):
+    y = forward(p, X, n_in, width, skip=skip)
     w = np.asarray(w, dtype=np.float64)
     return float(np.sum(w * (y - t) ** 2) / np.sum(w))
 
 
-def grad(p, X, t, w, n_in, width):
+def grad(p, X, t, w, n_in, width, skip=None):
     """Manual backward pass; returns (loss, flat gradient)."""
     layers = unpack(p, n_in, width)
-    y, cache, Zs = forward(p, X, n_in, width, keep=True)
+    y, cache, Zs = forward(p, X, n_in, width, keep=True, skip=skip)
     w = np.asarray(w, dtype=np.float64)
     t = np.asarray(t, dtype=np.float64)
     sw = np.sum(w)

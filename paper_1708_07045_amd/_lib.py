@@ -59,7 +59,7 @@ EXPORTS = ["fftdg_version", "fftdg_status_string", "fftdg_create", "fftdg_destro
            "fftdg_energy_grid", "fftdg_place", "fftdg_reduce", "fftdg_profile", "fftdg_profile_read",
            "fftdg_get_tuning", "fftdg_set_tuning", "fftdg_autotune", "fftdg_config_features",
            "fftdg_mlp_create", "fftdg_mlp_destroy", "fftdg_mlp_last_error", "fftdg_mlp_num_params",
-           "fftdg_mlp_set_params", "fftdg_mlp_get_params", "fftdg_mlp_forward", "fftdg_mlp_grad",
+           "fftdg_mlp_set_params", "fftdg_mlp_get_params", "fftdg_mlp_set_skip", "fftdg_mlp_forward", "fftdg_mlp_grad",
            "fftdg_mlp_train_step", "fftdg_proposal_sample", "fftdg_scan_features", "fftdg_is_plan", "fftdg_sample_poses",
            "fftdg_grids_build", "fftdg_grid_energies", "fftdg_pair_energies"]
 
@@ -110,6 +110,7 @@ def load():
     L.fftdg_mlp_num_params.argtypes = [p]
     L.fftdg_mlp_set_params.argtypes = [p, p, ctypes.c_int64]
     L.fftdg_mlp_get_params.argtypes = [p, p, ctypes.c_int64]
+    L.fftdg_mlp_set_skip.argtypes = [p, i32, ctypes.c_float]
     L.fftdg_mlp_forward.argtypes = [p, p, i32, p]
     L.fftdg_mlp_grad.argtypes = [p, p, p, p, p, i32, p, p]
     L.fftdg_mlp_train_step.argtypes = [p, p, p, p, p, i32, ctypes.c_float, p]
@@ -335,6 +336,16 @@ class FFTDG:
         self._check(self.L.fftdg_place(self.h_ctx, ctypes.byref(batch.c), cfg, _ptr(U), _ptr(box)))
         return U, box
 
+    def boxes(self, batch: Batch) -> np.ndarray:
+        """Box extents (x, y, z) of every configuration of the batch as the
+        scan places it, [n_cfg][3] (one fftdg_place call each)."""
+        out = np.zeros((batch.n_cfg, 3), np.int32)
+        na_max = int(np.max(np.diff(batch.atom_off)))
+        U = np.zeros((na_max, 3), np.int32)
+        for c in range(batch.n_cfg):
+            self._check(self.L.fftdg_place(self.h_ctx, ctypes.byref(batch.c), c, _ptr(U), _ptr(out[c])))
+        return out
+
     def scan_features(self, batch: Batch, partials, feat, col0: int):
         """Write the N_SCAN_FEATURES descriptors of this context's scan into
         columns col0.. of the device float matrix feat [n_cfg][ld]."""
@@ -500,6 +511,10 @@ class Network:
         if isinstance(a, t.Tensor):
             return a.to(self.device, dtype).contiguous()
         return t.as_tensor(np.ascontiguousarray(a), device=self.device).to(dtype).contiguous()
+
+    def set_skip(self, col: int, scale: float = 1.0):
+        """Output net(x) + scale * x[col] (col = -1: none)."""
+        self._check(self.L.fftdg_mlp_set_skip(self.h, int(col), float(scale)))
 
     def forward(self, X):
         t = self.torch

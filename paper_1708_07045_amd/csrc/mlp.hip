@@ -96,14 +96,18 @@ __global__ void k_gather(const float *__restrict__ X, int n_in, const int32_t *_
     A0[e] = f2bf(v);
 }
 
-// y[b] = H3[b] . W4 + b4 (FP32 accumulation of BF16 activations and weights)
+// y[b] = H3[b] . W4 + b4 (FP32 accumulation of BF16 activations and
+// weights), plus skip_scale times input column skip_col of the row (FP32)
+// when skip_col >= 0
 __global__ void k_out(const uint16_t *__restrict__ H3, int W, const uint16_t *__restrict__ W4, const float *b4,
-                      int B, float *__restrict__ y) {
+                      int B, const float *__restrict__ X, int n_in, const int32_t *__restrict__ idx, int skip_col,
+                      float skip_scale, float *__restrict__ y) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
     float s = 0.f;
     for (int k = 0; k < W; ++k) s += bf2f(H3[(size_t)b * W + k]) * bf2f(W4[k]);
-    y[b] = s + b4[0];
+    const float sk = skip_col >= 0 ? skip_scale * X[(size_t)(idx ? idx[b] : b) * n_in + skip_col] : 0.f;
+    y[b] = s + b4[0] + sk;
 }
 
 // dy = 2 w (y - t) / sum(w) and the loss; one workgroup, fixed reduction tree
@@ -291,6 +295,8 @@ struct fftdg_mlp {
     Buf A0, A0t, H1, H2, H3, H1t, H2t, Z1, Z2, Z3, y, dy, dZf, dZ, dZt, dH, gtmp, loss, idx_tmp;
     Buf pcdf;
     int64_t step = 0;
+    int skip_col = -1;  // output adds skip_scale * x[skip_col] (none if < 0)
+    float skip_scale = 0.f;
 };
 
 namespace {
@@ -380,7 +386,8 @@ int forward(fftdg_mlp *m, const float *X, const int32_t *idx, int B, int Bp) {
                    (uint16_t *)m->H3.p, H)))
         return rc;
     hipLaunchKernelGGL(k_out, dim3(nb((size_t)B)), dim3(256), 0, m->stream, (const uint16_t *)m->H3.p, H,
-                       (const uint16_t *)m->W4.p, p + L.b4, B, (float *)m->y.p);
+                       (const uint16_t *)m->W4.p, p + L.b4, B, X, m->n_in, idx, m->skip_col, m->skip_scale,
+                       (float *)m->y.p);
     MCHK(m, hipGetLastError());
     return FFTDG_OK;
 }
@@ -548,6 +555,15 @@ int fftdg_mlp_get_params(fftdg_mlp *m, float *p_host, int64_t n) {
     MCHK(m, hipSetDevice(m->device));
     MCHK(m, hipMemcpyAsync(p_host, m->P.p, sizeof(float) * n, hipMemcpyDeviceToHost, m->stream));
     MCHK(m, hipStreamSynchronize(m->stream));
+    return FFTDG_OK;
+}
+
+int fftdg_mlp_set_skip(fftdg_mlp *m, int32_t col, float scale) {
+    if (!m) return FFTDG_E_INVALID;
+    if (col < -1 || col >= m->n_in || !std::isfinite(scale))
+        return merr(m, FFTDG_E_INVALID, "set_skip: column out of range or non-finite scale");
+    m->skip_col = col;
+    m->skip_scale = col >= 0 ? scale : 0.f;
     return FFTDG_OK;
 }
 

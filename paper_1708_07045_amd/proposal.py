@@ -14,13 +14,19 @@ Pipeline, each step a library call (this module only arranges them):
      relative log weight ln sum_s W_s Z_{c,s} - max (in units of 5 nats, the
      scale of the scan descriptors); it is trained with the library's Adam
      step on exhaustive fine scans of training ligands, the targets being
-     fftdg_scan_features of those scans;
+     fftdg_scan_features of those scans.  In the residual form the coarse
+     scan's own relative log weight is added to the output (a skip
+     connection with no parameters): the network learns fine - coarse and,
+     with its output layer started at zero, starts from the coarse ranking;
   4. fftdg_is_plan: the top fraction by prediction is scanned exactly, the
      rest sampled from a defensive mixture with 1/q weights;
   5. fftdg_scan with cfg_select, fftdg_reduce with cfg_weight: unbiased
      B_s and dG;
-  6. fallback: when the sampled remainder carries more than `max_share` of
-     the estimate in any snapshot, the ligand is scanned exhaustively.
+  6. fallback: a ligand whose predicted weights put more than `max_share`
+     of the total outside the exact stratum is scanned exhaustively.  The
+     rule depends on the predictions only, fixed before any draw, so each
+     ligand's estimate of sum_c Z_c stays unbiased; the share the sampled
+     stratum actually carries is reported as a diagnostic.
 """
 from __future__ import annotations
 
@@ -45,22 +51,28 @@ def coarse_desc(w, factor: int = 2) -> dict:
 
 def make_context(w, grid: Optional[dict] = None, device: int = 0, snapshots=None):
     """Context with receptor grids of every snapshot (or of the listed ones,
-    equally weighted) built and set."""
+    equally weighted; or, with snapshots == "mean", of one receptor at the
+    snapshots' mean atom coordinates) built and set."""
     import torch
     g = dict(n_rec=w.n_rec, n_fft=w.n_fft, h=w.h, origin=w.origin)
     if grid:
         g.update(grid)
     ctx = fd.FFTDG(g["n_rec"], g["n_fft"], g["h"], g["origin"], w.precision, w.clash_mode, w.ljr_cap, w.occ_f,
                    device)
-    snaps = list(range(w.receptor.n_snap)) if snapshots is None else list(snapshots)
+    if isinstance(snapshots, str) and snapshots == "mean":
+        structures = [np.mean(np.asarray(w.receptor.xyz, np.float64), axis=0)]
+        wts = np.ones(1)
+    else:
+        snaps = list(range(w.receptor.n_snap)) if snapshots is None else list(snapshots)
+        structures = [w.receptor.xyz[s] for s in snaps]
+        wts = w.receptor.weights if snapshots is None else np.full(len(snaps), 1.0 / len(snaps))
     gl, ol = [], []
-    for s in snaps:
-        gg, oo = ctx.receptor_grids(w.receptor.xyz[s], w.receptor.q, w.receptor.sigma, w.receptor.eps)
+    for xyz in structures:
+        gg, oo = ctx.receptor_grids(xyz, w.receptor.q, w.receptor.sigma, w.receptor.eps)
         gl.append(gg)
         ol.append(oo)
     grids = torch.stack(gl).contiguous()
     occ = torch.stack(ol).contiguous() if w.clash_mode == "occ" else None
-    wts = w.receptor.weights if snapshots is None else np.full(len(snaps), 1.0 / len(snaps))
     ctx.set_receptors(grids, occ, wts)
     ctx._grids = (grids, occ)
     return ctx
@@ -90,16 +102,28 @@ def targets(ctx_fine, batch, part_fine):
     return t, torch.as_tensor(w, device=ctx_fine.device)
 
 
-def init_params(n_in: int, width: int, seed: int = 0) -> np.ndarray:
+def init_params(n_in: int, width: int, seed: int = 0, zero_output: bool = False) -> np.ndarray:
     """Flat FP32 parameters (fftdg_mlp layout), each weight and bias
-    uniform in +-1/sqrt(fan_in)."""
+    uniform in +-1/sqrt(fan_in); zero_output starts the output layer at zero
+    (the residual form then starts from its skip input)."""
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([170807045, 5, seed])))
     out = []
-    for rows, cols in ((width, n_in), (width, width), (width, width), (1, width)):
-        a = 1.0 / np.sqrt(cols)
+    for li, (rows, cols) in enumerate(((width, n_in), (width, width), (width, width), (1, width))):
+        a = 0.0 if (zero_output and li == 3) else 1.0 / np.sqrt(cols)
         out.append(rng.uniform(-a, a, rows * cols))
         out.append(rng.uniform(-a, a, rows))
     return np.concatenate(out).astype(np.float32)
+
+
+def make_network(n_in: int, width: int = 256, residual: bool = False, max_batch: int = 512):
+    """The proposal network; residual: the output adds the coarse scan's
+    relative log weight (input column N_FEATURES, same units as the target)
+    and the output layer starts at zero."""
+    net = fd.Network(n_in, width, max_batch)
+    net.set_params(init_params(n_in, width, zero_output=residual))
+    if residual:
+        net.set_skip(fd.N_FEATURES, 1.0)
+    return net
 
 
 def train(net, X, t, w, rows: np.ndarray, epochs: int = 20, batch: int = 512, lr: float = 1e-3,
@@ -131,16 +155,40 @@ def predict(net, X):
     return net.forward(X)
 
 
+def predicted_remainder(batch, yhat, top_frac: float) -> np.ndarray:
+    """Per ligand: the share of the predicted weight sum_c exp(5 yhat_c)
+    outside the ceil(top_frac P) largest predictions (a function of the
+    predictions alone)."""
+    y = 5.0 * np.asarray(yhat, np.float64)
+    out = np.zeros(batch.n_lig)
+    for l in range(batch.n_lig):
+        a, b = batch.cfg_off[l], batch.cfg_off[l + 1]
+        v = np.sort(y[a:b])[::-1]
+        nt = min(v.size, int(np.ceil(top_frac * v.size)))
+        e = np.exp(v - v[0])
+        out[l] = e[nt:].sum() / e.sum()
+    return out
+
+
 def is_estimate(ctx, batch, yhat, top_frac: float, draw_frac: float, alpha: float, tau: float, uniforms,
                 T: float, max_share: float = 0.5):
     """Importance-sampled B [n_lig][n_snap] and per-ligand results from one
-    plan, with the exhaustive fallback per ligand.
+    plan, with the exhaustive fallback per ligand decided before any draw:
+    a ligand goes to the exhaustive scan when its predictions put more than
+    max_share of their weight outside the exact stratum.
 
     yhat is in units of 5 nats, so the mixture's temperature is tau / 5 in
-    those units (tau in nats).  Returns dict(B, res, n_scanned (per ligand),
-    fallback (per ligand, bool), share (per ligand: the largest fraction of
-    a snapshot's estimate that came from sampled configurations))."""
+    those units (tau in nats).  Returns dict(B, res, n_scanned (per ligand:
+    every configuration scanned for it), fallback (per ligand, bool),
+    share (per ligand: the largest fraction of a snapshot's estimate that
+    came from sampled configurations, a diagnostic))."""
+    yh = np.asarray(yhat.cpu().numpy() if hasattr(yhat, "cpu") else yhat, np.float64)
+    fallback = predicted_remainder(batch, yh, top_frac) > max_share
     sel, wt, _ = ctx.is_plan(batch, yhat, top_frac, draw_frac, alpha, tau / 5.0, uniforms)
+    for l in np.flatnonzero(fallback):  # those ligands are scanned whole instead
+        a, b = batch.cfg_off[l], batch.cfg_off[l + 1]
+        sel[a:b] = 1
+        wt[a:b] = 1.0
     bsel = batch.with_select(sel)
     part = ctx.scan(bsel, T)
     B, res = ctx.reduce(bsel, part, T, cfg_weight=wt)
@@ -161,18 +209,6 @@ def is_estimate(ctx, batch, yhat, top_frac: float, draw_frac: float, alpha: floa
             continue
         e = np.exp(z[ok] - m[ok])
         share[l] = np.max(e[:, sel[a:b] == 2].sum(axis=1) / e.sum(axis=1))
-    fallback = share > max_share
-    if np.any(fallback):
-        full = np.zeros(batch.n_cfg, np.uint8)
-        for l in np.flatnonzero(fallback):
-            full[batch.cfg_off[l]:batch.cfg_off[l + 1]] = 1
-        bf = batch.with_select(full)
-        pf = ctx.scan(bf, T)
-        Bf, rf = ctx.reduce(bf, pf, T)
-        for l in np.flatnonzero(fallback):
-            B[l] = Bf[l]
-            res[l] = rf[l]
-            n_scanned[l] = batch.cfg_off[l + 1] - batch.cfg_off[l]
     return dict(B=B, res=res, n_scanned=n_scanned, fallback=fallback, share=share)
 
 
@@ -252,5 +288,6 @@ def rows_of(cfg_off, ligs):
 
 
 __all__ = ["coarse_desc", "make_context", "inputs", "targets", "train", "predict", "is_estimate", "kstar_plain",
+           "make_network", "predicted_remainder",
            "kstar_is", "ligand_weights", "sub_batch", "split_ligands", "rows_of", "BUDGETS", "PLAIN_K",
            "N_IN_FULL", "init_params"]

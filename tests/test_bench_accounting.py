@@ -19,26 +19,42 @@ def bench():
 
 
 def test_vector_peak_from_unit_counts(bench):
-    # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2.4 GHz
-    assert bench.VALU_FP32_PEAK_TFLOPS == pytest.approx(78.6432)
-    assert bench.VALU_FP32_PACKED_PEAK_TFLOPS == pytest.approx(157.2864)
+    # 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x 2 (packed FP32) x 2.4 GHz
+    assert bench.VALU_FP32_PEAK_TFLOPS == pytest.approx(157.2864)
+    assert bench.VALU_FP32_NONPACKED_TFLOPS == pytest.approx(78.6432)
 
 
 def test_zpass_flops_count(bench):
     N = 128
     pencils = N * (N // 2 + 1)
     t = 5 * N * math.log2(N)
-    # occupancy mode: 4 forward + 2 inverse transforms, 3 x 8 + 6 flops per point
+    # plane path, occupancy mode: 4 forward + 2 inverse transforms, 3 x 8 + 6 flops per point
     want = pencils * (6 * t + N * 30)
-    assert bench.zpass_flops(N, True, 1, 1, 1) == pytest.approx(want)
-    assert bench.zpass_flops(N, True, 1, 1, 1) == pytest.approx(255.5904e6)
-    # cap mode: 3 forward + 1 inverse, 3 x 8 flops per point
-    assert bench.zpass_flops(N, False, 1, 1, 1) == pytest.approx(pencils * (4 * t + N * 24))
+    assert bench.zpass_flops(N, 4, 2, True, 1, 1, 1) == pytest.approx(want)
+    assert bench.zpass_flops(N, 4, 2, True, 1, 1, 1) == pytest.approx(255.5904e6)
+    # energy channels only (cap mode, or the fused path): 3 forward + 1 inverse, 3 x 8 flops per point
+    assert bench.zpass_flops(N, 3, 1, False, 1, 1, 1) == pytest.approx(pencils * (4 * t + N * 24))
     # linear in configurations; forward transforms shared by the snapshots of a pass
-    assert bench.zpass_flops(N, True, 10, 1, 1) == pytest.approx(10 * want)
-    one_pass = bench.zpass_flops(N, True, 1, 4, 4)
-    per_snap = bench.zpass_flops(N, True, 1, 4, 1)
+    assert bench.zpass_flops(N, 4, 2, True, 10, 1, 1) == pytest.approx(10 * want)
+    one_pass = bench.zpass_flops(N, 4, 2, True, 1, 4, 4)
+    per_snap = bench.zpass_flops(N, 4, 2, True, 1, 4, 1)
     assert one_pass == pytest.approx(per_snap - 3 * pencils * 4 * t)
+
+
+def test_s8d_bytes_per_configuration(bench):
+    """16 N (N/2+1) (n_in L_z + n_out V_z) + 8 S_h n_rc / B_rc, worked by hand
+    for one configuration: N = 128, box_z = 37 (L_z = 38), V_z = 59,
+    occupancy mode (n_in = n_rc = 4, n_out = 2), B_rc = 16."""
+    nh = 128 * 65
+    want = 16 * nh * (4 * 38 + 2 * 59) + 8 * 128 * nh * 4 / 16
+    assert want == pytest.approx(35_942_400.0 + 2_129_920.0)
+    got = bench.s8d_bytes_per_cfg({"box_z": [37], "V_z": [59]}, 128, True, 16)
+    assert got == pytest.approx(want)
+    # cap mode: 3 input channels, 1 output; the mean over configurations
+    two = bench.s8d_bytes_per_cfg({"box_z": [37, 41], "V_z": [59, 55]}, 128, False, 16)
+    a = 16 * nh * (3 * 38 + 59) + 8 * 128 * nh * 3 / 16
+    b = 16 * nh * (3 * 42 + 55) + 8 * 128 * nh * 3 / 16
+    assert two == pytest.approx((a + b) / 2)
 
 
 def test_recorded_traffic_follows_sources_and_schedule(bench, tmp_path, monkeypatch):
@@ -48,10 +64,11 @@ def test_recorded_traffic_follows_sources_and_schedule(bench, tmp_path, monkeypa
         "# summary", "", f"- hbm_bytes_per_cfg: 1234.5", "- configs_per_chunk: 512", "- energy_xy_direct: 2",
         f"- kernel_source_sha256: `{digest}`", ""]))
     monkeypatch.setattr(bench, "TRAFFIC_PROFILE", str(prof))
-    tun = {"configs_per_chunk": 256, "energy_xy_direct": 2}
+    tun = {"configs_per_chunk": 256, "energy_xy_direct": 2, "fused": 0}
     assert bench.recorded_traffic(tun) == pytest.approx(1234.5)
-    assert bench.recorded_traffic({"configs_per_chunk": 64, "energy_xy_direct": 2}) is None
-    assert bench.recorded_traffic({"configs_per_chunk": 512, "energy_xy_direct": 0}) is None
+    assert bench.recorded_traffic({"configs_per_chunk": 64, "energy_xy_direct": 2, "fused": 0}) is None
+    assert bench.recorded_traffic({"configs_per_chunk": 512, "energy_xy_direct": 0, "fused": 0}) is None
+    assert bench.recorded_traffic({"configs_per_chunk": 512, "energy_xy_direct": 2, "fused": 1}) is None
     prof.write_text(prof.read_text().replace(digest, "0" * 64))
     assert bench.recorded_traffic(tun) is None
 

@@ -82,6 +82,38 @@ def test_gradient_matches_oracle(B):
             assert np.linalg.norm(a - r) <= 3e-2 * np.linalg.norm(r) + 1e-7
 
 
+def test_skip_connection_matches_oracle():
+    """Output net(x) + s x[col]: forward (the skip term exact in FP32, the
+    network part to the BF16 tolerance) and gradients over an index subset
+    against the FP64 oracle with the same skip; removing the skip restores
+    the plain network."""
+    net = _net()
+    p = _params(9)
+    net.set_params(p)
+    X, t, w = _data(500, seed=11)
+    X[:, 4] *= 40.0  # a skip input far larger than the network's output
+    net.set_skip(4, 0.25)
+    y = net.forward(X).cpu().numpy().astype(np.float64)
+    p64 = p.astype(np.float32).astype(np.float64)
+    X32 = X.astype(np.float32).astype(np.float64)
+    yr = omlp.forward(p64, X32, N_IN, WIDTH, skip=(4, 0.25))
+    y0 = omlp.forward(p64, X32, N_IN, WIDTH)
+    # the skip part is added in FP32: residual to the oracle is the network's own error
+    assert np.linalg.norm((y - yr)) <= 2e-2 * np.linalg.norm(y0)
+    idx = np.random.default_rng(12).choice(500, 200, replace=False).astype(np.int32)
+    _, g = net.grad(X, t, w, idx)
+    _, gr = omlp.grad(p64, X32[idx], t[idx].astype(np.float32), w[idx].astype(np.float32), N_IN, WIDTH,
+                      skip=(4, 0.25))
+    g = g.cpu().numpy()
+    assert np.linalg.norm(g - gr) / np.linalg.norm(gr) < 2e-2
+    net.set_skip(-1)
+    y1 = net.forward(X).cpu().numpy().astype(np.float64)
+    assert np.linalg.norm(y1 - y0) / np.linalg.norm(y0) < 2e-2
+    import paper_1708_07045_amd as fd
+    with pytest.raises(fd.FFTDGError):
+        net.set_skip(N_IN, 1.0)
+
+
 def test_gradient_with_index_subset():
     net = _net()
     p = _params(6)
