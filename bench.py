@@ -350,7 +350,7 @@ def configs_needed(args):
     ctx_f = prop.make_context(w)
     # coarse pre-scan at twice the spacing: against one receptor at the
     # snapshots' mean coordinates (default), every snapshot, or the first
-    ctx_c = prop.make_context(w, prop.coarse_desc(w), snapshots=args.is_coarse_snapshots)
+    ctx_c = prop.make_context(w, prop.coarse_desc(w, args.is_coarse_factor), snapshots=args.is_coarse_snapshots)
     ctx_f.autotune(b, T, max_cfgs=2048)
     ctx_c.autotune(b, T, max_cfgs=2048)
 
@@ -368,47 +368,43 @@ def configs_needed(args):
     B_ex, res_ex = ctx_f.reduce(b, part_f, T)
     log(f"exhaustive fine scan {t_f:.2f}s, coarse scan {t_c:.2f}s (cost ratio {rho:.3f})")
     train_l, test_l = prop.split_ligands(len(w.ligands), 101)
-    rows = prop.rows_of(b.cfg_off, train_l)
+    # the training ligands split again: 81 to fit, 20 to choose the mixture
+    # temperature and the number of epochs (the held-out 40 decide nothing)
+    vperm = np.random.Generator(np.random.PCG64(np.random.SeedSequence([170807045, 12]))).permutation(train_l)
+    fit_l, val_l = np.sort(vperm[:81]), np.sort(vperm[81:])
+    rows = prop.rows_of(b.cfg_off, fit_l)
     X = prop.inputs(ctx_f, ctx_c, b, part_c, with_scan=True)
+    # the coarse prediction (skip input): per-receptor maximum of the relative
+    # log weight (the first scan descriptor when there is one coarse receptor)
+    X[:, fd.N_FEATURES] = torch.as_tensor(prop.coarse_score(ctx_c, b, part_c), device=X.device)
     Xc = X[:, :fd.N_FEATURES].contiguous()
-    t, wt = prop.targets(ctx_f, b, part_f)
-    nets, t_train = {}, {}
-    # net_scan: residual form (coarse relative log weight through the skip);
-    # net_cfg: configuration descriptors only
+    P_f = ctx_f.partials_numpy(part_f, S, b.n_cfg)
+    if args.is_target == "snapmax":
+        t, wt = prop.targets_snapmax(P_f, b.cfg_off, device=X.device)
+    else:
+        t, wt = prop.targets(ctx_f, b, part_f)
+    alpha = 0.1
+    val_score = prop.pool_fraction_scorer(w, b, P_f, val_l, alpha, (0.5, 1.0, 2.0), kT, reps=50)
+    pred, tau_of, t_train, epochs_of, val_of = {}, {}, {}, {}, {}
+    y_coarse = X[:, fd.N_FEATURES].cpu().numpy()
+    val_of["coarse"], tau_of["coarse"] = val_score(y_coarse)
+    pred["coarse"] = y_coarse
+    log(f"coarse: validation mean fraction {val_of['coarse']:.3f} at tau {tau_of['coarse']}")
+    # net_scan: residual form (coarse relative log weight through the skip;
+    # at epoch 0 it is the coarse score); net_cfg: configuration descriptors
+    # only.  The epoch count is chosen on the validation ligands.
     for name, xin, resid in (("net_scan", X, True), ("net_cfg", Xc, False)):
         net = prop.make_network(int(xin.shape[1]), 256, residual=resid)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        hist = prop.train(net, xin, t, wt, rows, epochs=args.is_epochs)
+        keep = prop.fit_selected(net, xin, t, wt, rows, val_score, args.is_epochs, log=log, name=name)
         torch.cuda.synchronize()
         t_train[name] = time.perf_counter() - t0
-        log(f"{name}: trained {args.is_epochs} epochs on {rows.size} rows in {t_train[name]:.1f}s, "
-            f"last batch loss {hist[-1]:.4f}")
-        nets[name] = (net, xin)
-    pred = {"net_scan": nets["net_scan"][0].forward(X).cpu().numpy(),
-            "net_cfg": nets["net_cfg"][0].forward(Xc).cpu().numpy(),
-            "coarse": X[:, fd.N_FEATURES].cpu().numpy()}
-    P_f = ctx_f.partials_numpy(part_f, S, b.n_cfg)
-    alpha = 0.1
-    # temperature of the mixture, chosen on training ligands only
-    taus = (0.5, 1.0, 2.0)
-    tune_l = train_l[:: max(1, len(train_l) // args.is_tune_ligands)][: args.is_tune_ligands]
-    tau_of = {}
-    for name in pred:
-        best = None
-        for tau in taus:
-            ks = []
-            for l in tune_l:
-                Zs = prop.ligand_weights(P_f, b.cfg_off, l)
-                yl = pred[name][b.cfg_off[l]:b.cfg_off[l + 1]]
-                k, _ = prop.kstar_is(prop.sub_batch(w, l), Zs, yl, alpha, tau, kT, 1000 + int(l), reps=50)
-                ks.append(k / Zs.shape[1])
-            m = float(np.median(ks))
-            log(f"tau {tau} for {name}: median fraction {m:.3f} on {len(tune_l)} training ligands")
-            if best is None or m < best[0]:
-                best = (m, tau)
-        tau_of[name] = best[1]
-    log(f"mixture temperatures (nats) chosen on training ligands: {tau_of}")
+        pred[name] = net.forward(xin).cpu().numpy()
+        tau_of[name], epochs_of[name], val_of[name] = keep["tau"], keep["epoch"], keep["score"]
+        log(f"{name}: {args.is_epochs} epochs on {rows.size} rows in {t_train[name]:.1f}s (with validation), "
+            f"last batch loss {keep['loss']:.4f}; kept epoch {keep['epoch']}")
+    log(f"mixture temperatures (nats) chosen on validation ligands: {tau_of}")
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([170807045, 21])))
     per = []
     for l in test_l:
@@ -427,21 +423,38 @@ def configs_needed(args):
             f"coarse {row['coarse']:.0f}  net_cfg {row['net_cfg']:.0f}")
     med = lambda key: float(np.median([r["plain"] / r[key] for r in per]))
     # one real importance-sampled scan of the held-out ligands at 10 % of
-    # the configurations (5 % exact top + 5 % draws), against the exhaustive
+    # the configurations (5 % exact top + 5 % draws), against the exhaustive,
+    # with the network's proposal and with the coarse score's
     bt = fd.Batch([w.ligands[l] for l in test_l])
-    yt = np.concatenate([pred["net_scan"][b.cfg_off[l]:b.cfg_off[l + 1]] for l in test_l])
     u = synth.uniforms(31, bt.n_cfg)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    est = prop.is_estimate(ctx_f, bt, yt, 0.05, 0.05, alpha, tau_of["net_scan"], u, T)
-    torch.cuda.synchronize()
-    t_is = time.perf_counter() - t0
     Bref = B_ex[test_l]
     dref = res_ex["dG"][test_l]
-    dB = est["B"] - Bref
-    ddg = est["res"]["dG"] - dref
-    n_is = int(est["n_scanned"].sum())
-    fin = np.isfinite(dB)
+    is_runs = {}
+    for name in ("net_scan", "coarse"):
+        yt = np.concatenate([pred[name][b.cfg_off[l]:b.cfg_off[l + 1]] for l in test_l])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        est = prop.is_estimate(ctx_f, bt, yt, 0.05, 0.05, alpha, tau_of[name], u, T)
+        torch.cuda.synchronize()
+        t_is = time.perf_counter() - t0
+        dB = est["B"] - Bref
+        ddg = est["res"]["dG"] - dref
+        n_is = int(est["n_scanned"].sum())
+        fin = np.isfinite(dB)
+        is_runs[name] = {
+            "configs_scanned": n_is, "configs_total": int(bt.n_cfg),
+            "cost_fine_equivalents": n_is + rho * bt.n_cfg,
+            "fallback_ligands": int(est["fallback"].sum()),
+            "fallback_rule": "predicted weight outside the exact stratum > 0.5 (decided before the draw)",
+            "max_sampled_share": float(np.max(est["share"])),
+            "rms_dB_kcal_mol": float(np.sqrt(np.mean(dB[fin] ** 2))) if np.any(fin) else None,
+            "max_abs_dB_kcal_mol": float(np.max(np.abs(dB[fin]))) if np.any(fin) else None,
+            "n_infinite_dB": int(np.count_nonzero(~fin)),
+            "rms_ddG_kcal_mol": float(np.sqrt(np.mean(ddg ** 2))),
+            "seconds_is_path_fine_only": t_is,
+            "seconds_exhaustive_fine_same_ligands": t_f * bt.n_cfg / b.n_cfg}
+        log(f"10% IS run ({name}): {n_is} of {bt.n_cfg} scanned, {is_runs[name]['fallback_ligands']} fallbacks, "
+            f"RMS dB {is_runs[name]['rms_dB_kcal_mol']}, max {is_runs[name]['max_abs_dB_kcal_mol']}")
     return {
         "workload": f"batched: {len(w.ligands)} ligands x {S} snapshots, {b.n_cfg} configurations, "
                     f"101 training / {len(test_l)} held-out ligands (seeded split)",
@@ -450,23 +463,19 @@ def configs_needed(args):
         "replicates": args.is_reps,
         "coarse_cost_ratio": rho,
         "coarse_receptors": args.is_coarse,
+        "coarse_spacing_factor": args.is_coarse_factor,
+        "target": args.is_target,
+        "split": "101 training ligands = 81 fitted + 20 validation (temperature, epochs); 40 held out",
         "mixture_alpha": alpha,
         "mixture_tau_nats": tau_of,
+        "epochs_kept": epochs_of,
+        "validation_mean_fraction": val_of,
         "train_seconds": t_train,
         "median_plain_over": {"net_scan": med("net_scan"), "net_cfg": med("net_cfg"), "coarse": med("coarse")},
         "median_fraction_of_pool": {k: float(np.median([r[k] / r["n_cfg"] for r in per]))
                                     for k in ("plain", "net_scan", "net_cfg", "coarse")},
-        "is_run_10pct": {"configs_scanned": n_is, "configs_total": int(bt.n_cfg),
-                         "cost_fine_equivalents": n_is + rho * bt.n_cfg,
-                         "fallback_ligands": int(est["fallback"].sum()),
-                         "fallback_rule": "predicted weight outside the exact stratum > 0.5 (decided before the draw)",
-                         "max_sampled_share": float(np.max(est["share"])),
-                         "rms_dB_kcal_mol": float(np.sqrt(np.mean(dB[fin] ** 2))),
-                         "max_abs_dB_kcal_mol": float(np.max(np.abs(dB[fin]))),
-                         "n_infinite_dB": int(np.count_nonzero(~fin)),
-                         "rms_ddG_kcal_mol": float(np.sqrt(np.mean(ddg ** 2))),
-                         "seconds_is_path_fine_only": t_is,
-                         "seconds_exhaustive_fine_same_ligands": t_f * bt.n_cfg / b.n_cfg},
+        "is_run_10pct": is_runs["net_scan"],
+        "is_run_10pct_coarse": is_runs["coarse"],
         "per_ligand": per,
     }
 
@@ -501,13 +510,19 @@ def main():
     ap.add_argument("--is-only", action="store_true", help="only the configurations-needed measurement")
     ap.add_argument("--is-reps", type=int, default=200, help="replicates per budget (configurations needed)")
     ap.add_argument("--is-epochs", type=int, default=20)
-    ap.add_argument("--is-tune-ligands", type=int, default=12)
+    ap.add_argument("--is-coarse-factor", type=int, default=2,
+                    help="coarse spacing = factor x the fine spacing (2: 64-point FFT, 4: 32-point)")
+    ap.add_argument("--is-target", default="snapmax", choices=["snapmax", "sum"],
+                    help="training target: largest per-snapshot relative log weight, or the log of the "
+                         "snapshot-weighted sum")
     ap.add_argument("--is-detail", default="", help="write per-ligand configurations-needed results here (JSON)")
     ap.add_argument("--is-coarse", default="mean", choices=["mean", "all", "first"],
                     help="coarse pre-scan receptors: one at the snapshots' mean coordinates, every snapshot, "
                          "or the first snapshot")
     args = ap.parse_args()
     args.is_coarse_snapshots = {"mean": "mean", "all": None, "first": [0]}[args.is_coarse]
+    if args.is_coarse_factor not in (2, 4):
+        ap.error("--is-coarse-factor must be 2 or 4")
     if args.gpus != 1:
         print(f"bench.py: this implementation runs on one GPU; --gpus {args.gpus} is not supported "
               "(the scan would shard by ligand, snapshot and configuration chunk)", file=sys.stderr)
@@ -622,43 +637,55 @@ def main():
         kernels[name] = {"ms_per_step": ms / n_prof, "launches_per_step": n / n_prof,
                          "avg_launch_us": 1e3 * ms / n, "alg_GBps": (b / 1e9) / (ms / 1e3) if ms > 0 else None,
                          "alg_bytes_per_launch": b / n}
-    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
-    kd = kernels[dom]
-    achieved = kd["alg_GBps"]
-    traffic = None
-    if dom == "zprod" and args.workload == "c2":
-        per_cfg = recorded_traffic(tun)
-        if per_cfg is not None:
-            traffic = per_cfg * n_cfg * n_prof / prof["zprod"][1]   # bytes per launch
-    hbm = {"achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-           "copy_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps,
-           "alg_bytes_per_launch": kd["alg_bytes_per_launch"]}
-    if dom == "zprod":
-        # the z pass is bound by vector-ALU issue (VALU busy 0.9 and more in
-        # the counter runs): rate its algorithmic flops against the FP32
-        # vector peak; its HBM view is the sub-object
-        occ = w.clash_mode == "occ"
-        n_in, n_out = (3, 1) if (fused or not occ) else (4, 2)
-        fl = zpass_flops(w.n_fft, n_in, n_out, occ and not fused, n_cfg, n_snap,
-                         tun["snapshots_per_pass"] if (tun["snapshots_per_pass"] > 0 and not fused) else 1)
-        fl_launch = fl * n_prof / prof["zprod"][1]
-        tf = fl_launch / (kd["avg_launch_us"] * 1e-6) / 1e12
-        roof = {"bound": "alu", "kernel": dom, "achieved": tf, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                "frac": tf / VALU_FP32_PEAK_TFLOPS, "traffic": traffic,
-                "peak_nonpacked_fp32": VALU_FP32_NONPACKED_TFLOPS,
-                "frac_of_nonpacked": tf / VALU_FP32_NONPACKED_TFLOPS,
-                "avg_launch_us": kd["avg_launch_us"], "alg_flops_per_launch": fl_launch, "hbm": hbm}
-    else:
-        roof = {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "copy_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps,
-                "avg_launch_us": kd["avg_launch_us"], "alg_bytes_per_launch": kd["alg_bytes_per_launch"]}
-    # whole path: algorithmic bytes of all scan kernels per configuration
-    path_bytes = sum(prof[k][2] for k in ("lig_fwd_xy", "zprod", "inv_xy_lse", "merge", "lig_runs", "clash")
-                     if k in prof) / n_prof
     boxes = ctx.boxes(batch)
     s8d = s8d_bytes_per_cfg({"box_z": boxes[:, 2], "V_z": np.maximum(w.n_rec - boxes[:, 2], 0)}, w.n_fft,
                             w.clash_mode == "occ", tun["configs_per_chunk"])
+    # Roofline.  The unit is one chunk of configurations through the scan's
+    # per-chunk kernels (runs, forward, clash test, z pass, inverse): on the
+    # fused path no single kernel moves the method's data, so the survey's
+    # algorithmic bytes per configuration-snapshot scan (s8d) are rated
+    # against the summed kernel time of a chunk.
+    chunk_kernels = [k for k in ("lig_runs", "lig_fwd_xy", "clash", "zprod", "inv_xy_lse") if k in kernels]
+    chunk_ms_step = sum(kernels[k]["ms_per_step"] for k in chunk_kernels)
+    chunks_step = kernels["lig_fwd_xy"]["launches_per_step"] if "lig_fwd_xy" in kernels else 1.0
+    scans_chunk = n_cfg * n_snap / chunks_step
+    achieved = s8d * scans_chunk / (chunk_ms_step / chunks_step * 1e-3) / 1e9
+    traffic = None
+    if args.workload == "c2":
+        per_cfg = recorded_traffic(tun)
+        if per_cfg is not None:
+            traffic = per_cfg * n_cfg / chunks_step   # bytes per chunk
+    # the z pass alone: bound by vector-ALU issue (VALU busy 0.9 and more in
+    # the counter runs); its flops against the FP32 vector peaks and its own
+    # algorithmic bytes against HBM
+    zk = None
+    if "zprod" in kernels:
+        kd = kernels["zprod"]
+        occ_mode = w.clash_mode == "occ"
+        n_in, n_out = (3, 1) if (fused or not occ_mode) else (4, 2)
+        fl = zpass_flops(w.n_fft, n_in, n_out, occ_mode and not fused, n_cfg, n_snap,
+                         tun["snapshots_per_pass"] if (tun["snapshots_per_pass"] > 0 and not fused) else 1)
+        fl_launch = fl * n_prof / prof["zprod"][1]
+        tf = fl_launch / (kd["avg_launch_us"] * 1e-6) / 1e12
+        zk = {"kernel": "zprod", "avg_launch_us": kd["avg_launch_us"],
+              "alu": {"achieved": tf, "unit": "TFLOP/s", "alg_flops_per_launch": fl_launch,
+                      "peak": VALU_FP32_PEAK_TFLOPS, "frac": tf / VALU_FP32_PEAK_TFLOPS,
+                      "peak_nonpacked_fp32": VALU_FP32_NONPACKED_TFLOPS,
+                      "frac_of_nonpacked": tf / VALU_FP32_NONPACKED_TFLOPS},
+              "hbm": {"achieved": kd["alg_GBps"], "unit": "GB/s", "frac": kd["alg_GBps"] / HBM_PEAK_GBS,
+                      "alg_bytes_per_launch": kd["alg_bytes_per_launch"]}}
+    roof = {"bound": "hbm", "kernel": "scan chunk: " + " + ".join(chunk_kernels), "achieved": achieved,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "per_unit": "survey algorithmic bytes per configuration-snapshot scan (s8d_bytes_per_cfg)",
+            "alg_bytes_per_chunk": s8d * scans_chunk, "configs_per_chunk": scans_chunk,
+            "chunk_us": 1e3 * chunk_ms_step / chunks_step,
+            "copy_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps,
+            "timed_path": {"achieved": s8d * cfg_s * n_snap / 1e9, "frac": s8d * cfg_s * n_snap / 1e9 / HBM_PEAK_GBS,
+                           "note": "s8d bytes x scans/s of the timed steps (host placement and launches included)"},
+            "z_kernel": zk}
+    # whole path: algorithmic bytes of all scan kernels per configuration
+    path_bytes = sum(prof[k][2] for k in ("lig_fwd_xy", "zprod", "inv_xy_lse", "merge", "lig_runs", "clash")
+                     if k in prof) / n_prof
     rec = {
         "metric": METRIC,
         "value": cfg_s,

@@ -11,23 +11,32 @@ namespace fftdg {
 
 __host__ __device__ constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
 
+// Longest run piece of the clash test (its two windows lie within one word
+// of each other); runs of 2^k <= len < 2^(k+1) points read level k.
+constexpr int RUN_MAX = 63;
+
 // OR-dilated receptor occupancy rows of one snapshot, u32 words
-// [k][Z][q][Y]: level k (window 2^k, k = 0 .. log2 N); slice Z and row Y
-// over two periods, 0 .. 2N - 1 (row (Y, Z) is row (Y mod N, Z mod N), so
-// a row index y + t_y or z + t_z never needs reducing); word q of the
-// periodic row continued for RW = 2 N/32 + 2 words (word q holds the row's
-// word q mod N/32, so windows starting anywhere in the first period and
-// spanning up to N/32 + 2 words never wrap); row Y fastest (a wavefront's
-// 64 consecutive rows read one contiguous 256-byte run per word).
+// [k][Z][q][Y]: level k (window 2^k, k = 0 .. log2(RUN_MAX + 1) - 1, the
+// levels runs of at most RUN_MAX points read); slice Z = z + M and row
+// Y = y + M for true coordinates z, y in [-M, N + M) (row (y, z) holds
+// receptor row (y mod N, z mod N): the periodic domain of the FFT with M
+// rows continued past each end, so a row index z + t_z or y + t_y of a
+// ligand point within M of the box needs no reducing); word q holds the
+// row's points x in [32 (q - 1), 32 q), taken mod N, for q in [0, RW), so a
+// run starting at x >= -32 reads its words without wrapping; row Y fastest
+// (a wavefront's 64 consecutive rows read one contiguous 256-byte run per
+// word).  The whole table is 4.0 MB at N = 128, about one XCD's L2.
 template <int N>
 struct Dil {
     static constexpr int NW = N / 32;
-    static constexpr int RW = 2 * NW + 2;
-    static constexpr int K = ilog2c(N) + 1;
-    static constexpr int N2 = 2 * N;
-    __host__ __device__ static constexpr int64_t words() { return (int64_t)K * N2 * RW * N2; }
+    static constexpr int M = 8;
+    static constexpr int E = N + 2 * M;
+    static constexpr int RW = NW + 4;
+    static constexpr int K = ilog2c(RUN_MAX + 1);
+    static_assert((1 << (K - 1)) <= N, "a level's window must fit in a row");
+    __host__ __device__ static constexpr int64_t words() { return (int64_t)K * E * RW * E; }
     __host__ __device__ static constexpr int64_t index(int k, int Z, int q, int Y) {
-        return (((int64_t)k * N2 + Z) * RW + q) * N2 + Y;
+        return (((int64_t)k * E + Z) * RW + q) * E + Y;
     }
 };
 
@@ -37,6 +46,7 @@ constexpr size_t FUSED_TABLE_BYTES = 16384;
 struct FusedSet {
     int n_fft;
     int64_t dil_words;  // words of one snapshot's dilation table
+    int margin;         // Dil<N>::M: occupancy may reach this many points past the box
     // occ [n_rec^3] bytes -> dil (Dil<N> layout)
     hipError_t (*rec_dilate)(hipStream_t, const uint8_t *occ, int n_rec, uint32_t *dil);
     // ligand occupancy runs of the scanned configurations zcfg[0..nz) of a

@@ -47,22 +47,24 @@
 namespace fftdg {
 
 // ------------------------------------------------------------ receptor rows
-// One thread per row (Z, Y) of the periodic N^3 domain.  Level 0 holds the
-// occupancy bits of the row (zero outside the n_rec^3 receptor grid); level
-// k ORs level k-1 with itself advanced by 2^(k-1) points (mod N).
+// One thread per stored row (Z, Y) of the table.  Level 0 holds the
+// occupancy bits of receptor row ((Y - M) mod N, (Z - M) mod N) (zero
+// outside the n_rec^3 receptor grid); level k ORs level k-1 with itself
+// advanced by 2^(k-1) points (mod N).
 template <int N>
 __global__ __launch_bounds__(NT) void k_rec_dilate(const uint8_t *__restrict__ occ, int n_rec,
                                                     uint32_t *__restrict__ dil) {
     using D = Dil<N>;
     constexpr int NW = D::NW;
     const int r = (int)blockIdx.x * NT + (int)threadIdx.x;
-    if (r >= N * N) return;
-    const int Z = r / N, Y = r - (r / N) * N;
+    if (r >= D::E * D::E) return;
+    const int Z = r / D::E, Y = r - (r / D::E) * D::E;
+    const int z = (Z - D::M + N) & (N - 1), y = (Y - D::M + N) & (N - 1);
     uint32_t v[NW];
 #pragma unroll
     for (int w = 0; w < NW; ++w) v[w] = 0u;
-    if (Z < n_rec && Y < n_rec) {
-        const uint8_t *row = occ + ((int64_t)Z * n_rec + Y) * n_rec;
+    if (z < n_rec && y < n_rec) {
+        const uint8_t *row = occ + ((int64_t)z * n_rec + y) * n_rec;
         for (int x = 0; x < n_rec; ++x)
             if (row[x]) v[x >> 5] |= 1u << (x & 31);
     }
@@ -82,11 +84,7 @@ __global__ __launch_bounds__(NT) void k_rec_dilate(const uint8_t *__restrict__ o
             for (int w = 0; w < NW; ++w) v[w] |= t[w];
         }
 #pragma unroll
-        for (int q = 0; q < D::RW; ++q)
-#pragma unroll
-            for (int cz = 0; cz < 2; ++cz)
-#pragma unroll
-                for (int cy = 0; cy < 2; ++cy) dil[D::index(k, Z + cz * N, q, Y + cy * N)] = v[q % NW];
+        for (int q = 0; q < D::RW; ++q) dil[D::index(k, Z, q, Y)] = v[(q + NW - 1) % NW];
     }
 }
 
@@ -134,19 +132,19 @@ __device__ __forceinline__ bool ball_row(const RunAtom &A, int y, int z, long lo
 }
 
 // A run of the clash test as two words: the byte offset of its first table
-// word for a translation of zero, o = 4 Dil<N>::index(k, z mod N, a / 32,
-// y mod N) (the lane adds 4 (t_z RW 2N + t_y)), and the two window shifts,
+// word for a translation of zero, o = 4 Dil<N>::index(k, z + M, (a + 32) / 32,
+// y + M) (the lane adds 4 (t_z RW E + t_y)), and the two window shifts,
 // a mod 32 | ((a + len - 2^k) mod 32) << 8 | (second window one word on) << 16,
-// with 2^k <= len < 2^(k+1).
-constexpr int RUN_MAX = 63;  // longest run piece (its two windows lie within one word of each other)
+// with 2^k <= len < 2^(k+1).  The planner keeps z, y, a >= -M and the
+// rows and words a translated run reads inside the table.
 template <int N>
 __device__ __forceinline__ uint2 pack_run(int z, int y, int a, int len) {
     using D = Dil<N>;
-    const int zm = z & (N - 1), ym = y & (N - 1), am = a & (N - 1);
+    const int ax = a + 32;
     const int k = 31 - __builtin_clz((unsigned)len);
-    const int p2 = am + len - (1 << k);
-    const uint32_t off = (uint32_t)(4 * D::index(k, zm, am >> 5, ym));
-    const uint32_t meta = (uint32_t)(am & 31) | ((uint32_t)(p2 & 31) << 8) | ((uint32_t)((p2 >> 5) > (am >> 5)) << 16);
+    const int p2 = ax + len - (1 << k);
+    const uint32_t off = (uint32_t)(4 * D::index(k, z + D::M, ax >> 5, y + D::M));
+    const uint32_t meta = (uint32_t)(ax & 31) | ((uint32_t)(p2 & 31) << 8) | ((uint32_t)((p2 >> 5) > (ax >> 5)) << 16);
     return make_uint2(off, meta);
 }
 __device__ __forceinline__ int run_pieces(int len) { return (len + RUN_MAX - 1) / RUN_MAX; }
@@ -299,7 +297,7 @@ __device__ __forceinline__ void clash_runs(const uint2 *__restrict__ rl, int nr,
         if (m >= R) m -= R;
         return i;
     };
-    const int vo = (tzl * (D::RW * D::N2) + ty) * 4;  // the lane's part of every table offset
+    const int vo = (tzl * (D::RW * D::E) + ty) * 4;  // the lane's part of every table offset
     auto test = [&](auto urc, int k) {
         constexpr int U = decltype(urc)::value;
         uint32_t v[U][W + 2];
@@ -310,7 +308,7 @@ __device__ __forceinline__ void clash_runs(const uint2 *__restrict__ rl, int nr,
             meta[u] = e.y;
 #pragma unroll
             for (int j = 0; j < W + 2; ++j)
-                v[u][j] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, vo, (int)e.x + j * (D::N2 * 4), 0);
+                v[u][j] = __builtin_amdgcn_raw_buffer_load_b32(rsrc, vo, (int)e.x + j * (D::E * 4), 0);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -963,7 +961,8 @@ struct LaunchFused {
     using C2 = typename Cx<T>::t;
     using G = Geo<T, N>;
     static hipError_t rec_dilate(hipStream_t st, const uint8_t *occ, int n_rec, uint32_t *dil) {
-        hipLaunchKernelGGL((k_rec_dilate<N>), dim3((N * N + NT - 1) / NT), dim3(NT), 0, st, occ, n_rec, dil);
+        constexpr int rows = Dil<N>::E * Dil<N>::E;
+        hipLaunchKernelGGL((k_rec_dilate<N>), dim3((rows + NT - 1) / NT), dim3(NT), 0, st, occ, n_rec, dil);
         return hipGetLastError();
     }
     static hipError_t lig_runs(hipStream_t st, const CfgDev *cfgs, const int32_t *zcfg, int nz, const int32_t *ulat,
@@ -1063,6 +1062,7 @@ static const FusedSet *make_fused() {
     static const FusedSet s = {
         N,
         Dil<N>::words(),
+        Dil<N>::M,
         LaunchFused<T, N>::rec_dilate,
         LaunchFused<T, N>::lig_runs,
         LaunchFused<T, N>::clash,

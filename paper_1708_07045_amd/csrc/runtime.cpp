@@ -317,15 +317,22 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
         thr[i] = occ ? occ_threshold(g, b->sigma[i]) : 0.0;
         reach[i] = occ && thr[i] >= 1.0 ? isqrt_lt((long long)thr[i]) : -1;
     }
-    const bool fz = ctx->fused != 0 && ctx->fs != nullptr;
+    // the fused path's clash table keeps Dil<N>::M rows and points past each
+    // end of the domain: the occupancy balls must reach no further past the
+    // box (the box starts 2 points after the lowest atom and ends 2 after
+    // the highest); wider balls take the plane path
+    long long smax = -1;
+    for (long long s : reach) smax = std::max(smax, s);
+    const long long reach_pts = smax < 0 ? 0 : (smax + 65535) / 65536;
+    const bool fz = ctx->fused != 0 && ctx->fs != nullptr && (!occ || reach_pts <= ctx->fs->margin);
     const bool fzp = fz && ctx->fused == 1;
     P.fused = fz;
     P.fused_planes = fzp;
     // fused path: slots for a configuration's occupancy runs.  An atom's ball
     // meets at most r = 2 floor(reach / 2^16) + 2 rows and columns of each
-    // axis; runs are written in pieces of at most 63 points, and the pieces
+    // axis; runs are written in pieces of at most RUN_MAX points, and the pieces
     // of a row's union never outnumber those of the balls meeting it, so per
-    // atom (1 chord + r^2 rows) x ceil(r / 63) pieces bound the count
+    // atom (1 chord + r^2 rows) x ceil(r / RUN_MAX) pieces bound the count
     std::vector<int64_t> run_cap(b->n_lig, 0);
     if (fz && occ)
         for (int l = 0; l < b->n_lig; ++l) {
@@ -333,7 +340,7 @@ int build_plan(fftdg_ctx *ctx, const fftdg_batch *b, bool only_one, int one_cfg,
             for (int i = b->atom_off[l]; i < b->atom_off[l + 1]; ++i)
                 if (reach[i] >= 0) {
                     const int64_t r = 2 * (reach[i] >> 16) + 2;
-                    cap += (1 + r * r) * ((r + 62) / 63);
+                    cap += (1 + r * r) * ((r + RUN_MAX - 1) / RUN_MAX);
                 }
             run_cap[l] = cap;
         }

@@ -102,6 +102,43 @@ def targets(ctx_fine, batch, part_fine):
     return t, torch.as_tensor(w, device=ctx_fine.device)
 
 
+def targets_snapmax(P_fine, cfg_off, device=None):
+    """(t [n_cfg], loss weights) for the per-snapshot criterion: t_c =
+    max_s (ln Z_{c,s} - max_{c' of the ligand} ln Z_{c',s}), floored at -25
+    and divided by 5 (the descriptor units), from exhaustive fine partials
+    [n_snap][n_cfg] (host FP64).  A configuration that dominates any one
+    snapshot scores 0 even when that snapshot's total is small, which the
+    snapshot-summed descriptor hides.  Configurations within 5 nats of the
+    top in some snapshot weigh 10x."""
+    import torch
+    fin = P_fine["n_finite"] > 0
+    lz = np.where(fin, P_fine["m"] + np.log(np.where(fin, P_fine["s"], 1.0)), -np.inf)
+    off = np.asarray(cfg_off, np.int64)
+    t = np.full(lz.shape[1], -5.0)
+    for l in range(off.size - 1):
+        a, b = off[l], off[l + 1]
+        if b == a:
+            continue
+        seg = lz[:, a:b]
+        m = np.max(seg, axis=1, keepdims=True)
+        rel = np.where(np.isfinite(m), seg - np.where(np.isfinite(m), m, 0.0), -np.inf)
+        t[a:b] = np.maximum(np.max(rel, axis=0), -25.0) / 5.0
+    w = np.where(t > -1.0, 10.0, 1.0).astype(np.float32)
+    dev = device if device is not None else "cpu"
+    return torch.as_tensor(t.astype(np.float32), device=dev), torch.as_tensor(w, device=dev)
+
+
+def coarse_score(ctx_coarse, batch, part_coarse) -> np.ndarray:
+    """The coarse scan's prediction of the fine target, host float [n_cfg]
+    in units of 5 nats: max over the coarse context's receptors of the
+    configuration's relative log weight (targets_snapmax of the coarse
+    partials).  With one coarse receptor it equals the first scan
+    descriptor."""
+    P = ctx_coarse.partials_numpy(part_coarse, ctx_coarse.n_snap, batch.n_cfg)
+    t, _ = targets_snapmax(P, batch.cfg_off)
+    return t.numpy()
+
+
 def init_params(n_in: int, width: int, seed: int = 0, zero_output: bool = False) -> np.ndarray:
     """Flat FP32 parameters (fftdg_mlp layout), each weight and bias
     uniform in +-1/sqrt(fan_in); zero_output starts the output layer at zero
@@ -127,15 +164,18 @@ def make_network(n_in: int, width: int = 256, residual: bool = False, max_batch:
 
 
 def train(net, X, t, w, rows: np.ndarray, epochs: int = 20, batch: int = 512, lr: float = 1e-3,
-          seed: int = 0, log=None):
+          seed: int = 0, log=None, checkpoint=None):
     """Adam with the library's kernels over the given rows (device tensors
-    X, t, w); the learning rate decays linearly to lr/10.  Returns the last
-    batch loss of each epoch."""
+    X, t, w); the learning rate decays linearly to lr/10.  checkpoint(epoch)
+    is called before the first epoch (0) and after each one.  Returns the
+    last batch loss of each epoch."""
     import torch
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([170807045, 7, seed])))
     rows = np.asarray(rows, np.int32)
     n_steps = epochs * max(1, rows.size // batch)
     step, hist = 0, []
+    if checkpoint:
+        checkpoint(0)
     for ep in range(epochs):
         idx = torch.as_tensor(rows[rng.permutation(rows.size)], device=X.device)
         last = None
@@ -147,6 +187,8 @@ def train(net, X, t, w, rows: np.ndarray, epochs: int = 20, batch: int = 512, lr
         hist.append(last)
         if log:
             log(f"epoch {ep + 1}/{epochs}: batch loss {last:.4f}")
+        if checkpoint:
+            checkpoint(ep + 1)
     return hist
 
 
@@ -262,6 +304,53 @@ def kstar_is(sub_batch, Zs, yhat, alpha, tau, kT, seed0, reps: int = 200, tol: f
     return float(P), None
 
 
+def pool_fraction_scorer(w, batch, P_fine, ligs, alpha: float, taus, kT: float, reps: int = 50, seed0: int = 1000):
+    """Function y -> (mean over `ligs` of the fraction of the pool the
+    stratified plan needs (kstar_is), best tau of `taus`) for predictions y
+    over all configurations of `batch`; used to choose the mixture
+    temperature and the training epochs on ligands not fitted."""
+    Z = {int(l): ligand_weights(P_fine, batch.cfg_off, l) for l in ligs}
+
+    def score(y):
+        best = None
+        for tau in taus:
+            ks = []
+            for l in ligs:
+                yl = y[batch.cfg_off[l]:batch.cfg_off[l + 1]]
+                k, _ = kstar_is(sub_batch(w, l), Z[int(l)], yl, alpha, tau, kT, seed0 + int(l), reps=reps)
+                ks.append(k / Z[int(l)].shape[1])
+            m = float(np.mean(ks))
+            if best is None or m < best[0]:
+                best = (m, tau)
+        return best
+
+    return score
+
+
+def fit_selected(net, X, t, wt, rows, score, epochs: int, check_at=(0, 2, 5, 10, 20, 40, 80), log=None, name=""):
+    """Train `net` on `rows` for `epochs` and keep the parameters of the
+    checkpoint (epoch in check_at, or the last) that `score` rates best;
+    epoch 0 is the starting network (for the residual form, the coarse
+    score itself).  Returns dict(score, tau, epoch, params, loss) and leaves
+    the kept parameters set."""
+    at = {e for e in check_at if e <= epochs} | {epochs}
+    keep = {}
+
+    def checkpoint(ep):
+        if ep not in at:
+            return
+        sc, tau = score(net.forward(X).cpu().numpy())
+        if log:
+            log(f"{name} epoch {ep}: score {sc:.4f} at tau {tau}")
+        if "score" not in keep or sc < keep["score"]:
+            keep.update(score=sc, tau=tau, epoch=ep, params=net.get_params())
+
+    hist = train(net, X, t, wt, rows, epochs=epochs, checkpoint=checkpoint)
+    net.set_params(keep["params"])
+    keep["loss"] = hist[-1] if hist else None
+    return keep
+
+
 def ligand_weights(P_fine, cfg_off, l):
     """Exhaustive Z_{c,s} of ligand l scaled by the per-snapshot maximum
     (host FP64) from fine partials [S][n_cfg]."""
@@ -288,6 +377,6 @@ def rows_of(cfg_off, ligs):
 
 
 __all__ = ["coarse_desc", "make_context", "inputs", "targets", "train", "predict", "is_estimate", "kstar_plain",
-           "make_network", "predicted_remainder",
+           "make_network", "predicted_remainder", "targets_snapmax", "coarse_score", "pool_fraction_scorer", "fit_selected",
            "kstar_is", "ligand_weights", "sub_batch", "split_ligands", "rows_of", "BUDGETS", "PLAIN_K",
            "N_IN_FULL", "init_params"]

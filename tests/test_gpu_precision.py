@@ -3,7 +3,9 @@ scanned in FP32 on the GPU (FP32 transforms, products, energies and
 max-shifted log-sum-exp; FP64 accumulation over configurations and the dG
 logarithm) against the FP64 oracle's results stored by
 tests/golden/make_c2_oracle.py, in occupancy mode and in capped-repulsion
-mode.  Errors are printed per result."""
+mode, with the cavity atom parameters and (stress) with the tiny case's
+larger charges and well depths, whose energies span a wider range.  Errors
+are printed per result."""
 import json
 import math
 import os
@@ -15,17 +17,30 @@ from workload import synth
 
 pytestmark = pytest.mark.gpu
 
-GOLD = os.path.join(os.path.dirname(__file__), "golden", "c2_oracle.json")
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 
-@pytest.mark.parametrize("mode,tol", [("occ", 0.01), ("cap", 0.01)])
+# Capped-repulsion mode with the stress parameters: the clamped repulsion of
+# overlapping poses reaches ~10^5 kcal/mol, and FP32 transform round-off is
+# normwise (about 1e-7 of the field's norm per pass), so the error on the
+# low-energy translations that carry the Boltzmann weight scales with those
+# values: measured 0.015 kcal/mol on B = -225 kcal/mol (7e-5 relative).
+# That case is held to 0.05 kcal/mol; occupancy mode (the paper's) meets
+# 0.01 with both parameter sets.
+TOL = {("occ", "cavity"): 0.01, ("cap", "cavity"): 0.01, ("occ", "stress"): 0.01, ("cap", "stress"): 0.05}
+
+
+@pytest.mark.parametrize("params", ["cavity", "stress"])
+@pytest.mark.parametrize("mode", ["occ", "cap"])
 @pytest.mark.parametrize("fused,energy_xy_direct", [(1, 0), (2, 0), (0, 0), (0, 2)])
-def test_full_c2_fp32_against_fp64_oracle(mode, tol, fused, energy_xy_direct):
+def test_full_c2_fp32_against_fp64_oracle(params, mode, fused, energy_xy_direct):
+    tol = TOL[(mode, params)]
     import torch
     import paper_1708_07045_amd as fd
-    ref = json.load(open(GOLD))[mode]
-    print(f"precision study: c2 {mode} fused={fused} energy_xy_direct={energy_xy_direct}", flush=True)
-    w = synth.config2()
+    gold = "c2_oracle.json" if params == "cavity" else "c2_stress_oracle.json"
+    ref = json.load(open(os.path.join(GOLDEN, gold)))[mode]
+    print(f"precision study: c2 {params} {mode} fused={fused} energy_xy_direct={energy_xy_direct}", flush=True)
+    w = synth.config2(params=synth.CAVITY_PARAMS if params == "cavity" else synth.TINY_PARAMS)
     w.clash_mode = mode
     ctx = fd.FFTDG.from_workload(w)
     ctx.set_tuning(energy_xy_direct=energy_xy_direct, configs_per_chunk=512, fused=fused)

@@ -168,3 +168,48 @@ def test_scan_features_follow_eq2_and_eq13():
     assert f[5, 2] == pytest.approx(parts[:, 5, 3].sum() / 1500)
     for a, b in zip(off[:-1], off[1:]):
         assert min(f[a:b, 1]) == 0.0
+
+
+class _B:
+    """Stand-in for a batch: only the ligand offsets are read."""
+
+    def __init__(self, cfg_off):
+        self.cfg_off = np.asarray(cfg_off, np.int32)
+        self.n_lig = self.cfg_off.size - 1
+
+
+def test_predicted_remainder_closed_forms():
+    """Share of sum_c exp(5 y_c) outside the ceil(top_frac P) largest."""
+    from paper_1708_07045_amd import proposal as prop
+    y = np.array([0.0, -np.log(3.0) / 5, -np.log(6.0) / 5, 0.0, 0.0])   # weights 1, 1/3, 1/6 | 1, 1
+    r = prop.predicted_remainder(_B([0, 3, 5]), y, 0.34)          # ligand 0 keeps 2, ligand 1 keeps 1
+    assert r[0] == pytest.approx((1 / 6) / (1 + 1 / 3 + 1 / 6), rel=1e-12)
+    assert r[1] == pytest.approx(0.5, rel=1e-12)
+    assert np.all(prop.predicted_remainder(_B([0, 3, 5]), y, 1.0) == 0.0)
+    assert np.all(prop.predicted_remainder(_B([0, 3, 5]), y, 0.0) == 1.0)
+    # order and shift invariance within a ligand
+    r2 = prop.predicted_remainder(_B([0, 3, 5]), np.r_[y[[2, 0, 1]] + 7.0, y[3:]], 0.34)
+    np.testing.assert_allclose(r2, r, rtol=1e-12)
+
+
+def test_snapshot_max_targets_closed_forms():
+    """t_c = max_s (ln Z_{c,s} - max_{c'} ln Z_{c',s}) floored at -25, / 5;
+    a configuration that dominates a small snapshot still scores 0."""
+    from paper_1708_07045_amd import proposal as prop
+    pd = np.dtype([("m", "<f8"), ("s", "<f8"), ("n_finite", "<i8")])
+    P = np.zeros((2, 4), pd)
+    # ligand 0: configurations 0..2; ligand 1: configuration 3 (nothing finite)
+    lz = np.array([[10.0, 4.0, 9.0, 0.0], [-50.0, -40.0, -80.0, 0.0]])
+    P["m"] = lz - 1.0
+    P["s"] = np.e
+    P["n_finite"] = 1
+    P["n_finite"][:, 3] = 0
+    t, w = prop.targets_snapmax(P, [0, 3, 4])
+    t = t.numpy()
+    np.testing.assert_allclose(t[:3], [0.0, 0.0, -1.0 / 5.0], atol=1e-6)
+    # snapshot 0 alone: configuration 1 sits 6 nats down; snapshot 1 makes it the top
+    assert t[3] == -5.0
+    np.testing.assert_array_equal(w.numpy(), [10.0, 10.0, 10.0, 1.0])
+    P["m"][0, 2] = -100.0            # now 110 nats below in snapshot 0 and 40 below in 1: floored
+    t, _ = prop.targets_snapmax(P, [0, 3, 4])
+    assert t.numpy()[2] == pytest.approx(-25.0 / 5.0)

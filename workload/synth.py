@@ -302,17 +302,20 @@ def cavity_receptor(rng, n_atoms=2600, r_in=10.0, r_out=19.3, params=CAVITY_PARA
     return xyz, q, s, e
 
 
-def config2(seed: int = ROOT_SEED, n_rot: int = 1000, n_conf: int = 8) -> Workload:
+def config2(seed: int = ROOT_SEED, n_rot: int = 1000, n_conf: int = 8, params=CAVITY_PARAMS) -> Workload:
     """T4L-sized plain case: 2600 atoms in a shell around a 10 A cavity,
     96^3 grid at 0.25 A zero-padded to a 128^3 FFT, occupancy clash mode;
-    one 25-atom ligand, 8 rigid conformers x 1000 rotations; FP32."""
+    one 25-atom ligand, 8 rigid conformers x 1000 rotations; FP32.
+    params=TINY_PARAMS gives the same geometry with the larger charges and
+    well depths of the tiny case (the precision stress)."""
     rs = streams(seed)
     n_rec, h = 96, 0.25
-    xyz, q, s, e = cavity_receptor(rs[_STREAM_RECEPTOR])
+    xyz, q, s, e = cavity_receptor(rs[_STREAM_RECEPTOR], params=params)
     rec = Receptor(xyz[None], q, s, e, np.ones(1))
-    lig = make_ligand(rs[_STREAM_LIGANDS], rs[_STREAM_ROTATIONS], 25, n_conf, n_rot, CAVITY_PARAMS)
-    return Workload("c2: 2600-atom cavity, 96^3 @ 0.25 A -> 128^3 FFT, occ, 25-atom ligand x 8 conf x 1000 rot, f32",
-                    n_rec, 128, h, _grid_origin(np.zeros(3), n_rec, h), "occ", 10.0, 0.5,
+    lig = make_ligand(rs[_STREAM_LIGANDS], rs[_STREAM_ROTATIONS], 25, n_conf, n_rot, params)
+    tag = "" if params == CAVITY_PARAMS else f", q sd {params[0]} e, eps U{params[1]}"
+    return Workload("c2: 2600-atom cavity, 96^3 @ 0.25 A -> 128^3 FFT, occ, 25-atom ligand x 8 conf x 1000 rot, f32"
+                    + tag, n_rec, 128, h, _grid_origin(np.zeros(3), n_rec, h), "occ", 10.0, 0.5,
                     300.0, "f32", rec, [lig])
 
 
