@@ -208,6 +208,28 @@ int fftdg_reduce(fftdg_ctx *ctx, const fftdg_batch *b, const fftdg_partial *p_de
                  const double *cfg_weight_dev, double T_K, double *B_host,
                  fftdg_ligand_result *res_host);
 
+/* Bytes of the static device scratch behind fftdg_reduce_static. */
+#define FFTDG_REDUCE_STATIC_BYTES (4 << 20)
+
+/* fftdg_reduce for callers that cannot allocate device memory at call time
+ * (code between graph captures, tight serving loops, hosts that forbid
+ * hipMalloc): same arguments, same kernel, bit-identical B_host and res_host.
+ * Its staging buffers (cfg_off, W, B, per-ligand results; 256-byte aligned
+ * pieces) live in one static device array of FFTDG_REDUCE_STATIC_BYTES per
+ * device, looked up once per device by fftdg_create and held until the
+ * process ends; the call makes no hipMalloc, hipFree or other allocation.
+ * Batches needing more, about 4 (n_lig + 1) + 8 n_snap + 8 n_lig n_snap +
+ * 40 n_lig bytes plus alignment (some 33 000 ligands at 10 snapshots), get
+ * E_INVALID with the figures in fftdg_last_error.  Every call on one device
+ * shares that device's array and nothing in it must start at zero (the kernel
+ * writes every output): calls that overlap in time on one device (other
+ * threads, other contexts or streams) race; one call ends with a stream
+ * synchronize, so calls made one after the other do not.  Not recorded by
+ * fftdg_profile. */
+int fftdg_reduce_static(fftdg_ctx *ctx, const fftdg_batch *b, const fftdg_partial *p_dev,
+                        const double *cfg_weight_dev, double T_K, double *B_host,
+                        fftdg_ligand_result *res_host);
+
 /* Kernel timing with HIP events recorded on the context's stream around
  * every launch the library makes (for benchmarks).  Kernel ids:
  *   0 ligand xy forward   1 z-pencil product   2 inverse xy + log-sum-exp

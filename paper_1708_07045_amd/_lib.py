@@ -56,7 +56,7 @@ class BatchC(ctypes.Structure):
 
 EXPORTS = ["fftdg_version", "fftdg_status_string", "fftdg_create", "fftdg_destroy", "fftdg_last_error",
            "fftdg_set_stream", "fftdg_receptor_grids", "fftdg_set_receptors", "fftdg_scan",
-           "fftdg_energy_grid", "fftdg_place", "fftdg_reduce", "fftdg_profile", "fftdg_profile_read",
+           "fftdg_energy_grid", "fftdg_place", "fftdg_reduce", "fftdg_reduce_static", "fftdg_profile", "fftdg_profile_read",
            "fftdg_get_tuning", "fftdg_set_tuning", "fftdg_autotune", "fftdg_config_features",
            "fftdg_mlp_create", "fftdg_mlp_destroy", "fftdg_mlp_last_error", "fftdg_mlp_num_params",
            "fftdg_mlp_set_params", "fftdg_mlp_get_params", "fftdg_mlp_set_skip", "fftdg_mlp_forward", "fftdg_mlp_grad",
@@ -96,6 +96,7 @@ def load():
     L.fftdg_energy_grid.argtypes = [p, i32, ctypes.POINTER(BatchC), i32, d, p, p, p]
     L.fftdg_place.argtypes = [p, ctypes.POINTER(BatchC), i32, p, p]
     L.fftdg_reduce.argtypes = [p, ctypes.POINTER(BatchC), p, p, d, p, p]
+    L.fftdg_reduce_static.argtypes = [p, ctypes.POINTER(BatchC), p, p, d, p, p]
     L.fftdg_profile.argtypes = [p, ctypes.c_int]
     L.fftdg_profile_read.argtypes = [p, i32, p, p, p]
     L.fftdg_get_tuning.argtypes = [p, ctypes.POINTER(Tuning)]
@@ -374,13 +375,26 @@ class FFTDG:
         return cfg, t, psi
 
     def reduce(self, batch: Batch, partials, T: float, cfg_weight=None):
+        return self._reduce(self.L.fftdg_reduce, batch, partials, T, cfg_weight)
+
+    def reduce_static(self, batch: Batch, partials, T: float, cfg_weight=None):
+        """fftdg_reduce_static: the same results with the library's static
+        device scratch (no device allocation in the call; cfg_weight, if
+        given, should already be a float64 device tensor)."""
+        return self._reduce(self.L.fftdg_reduce_static, batch, partials, T, cfg_weight)
+
+    def _reduce(self, fn, batch, partials, T, cfg_weight):
         B = np.zeros((batch.n_lig, self.n_snap), np.float64)
         res = np.zeros(batch.n_lig, RESULT_DTYPE)
-        w = None
+        w = cfg_weight
         if cfg_weight is not None:
-            w = self.torch.as_tensor(np.ascontiguousarray(cfg_weight, np.float64), device=self.device)
-        self._check(self.L.fftdg_reduce(self.h_ctx, ctypes.byref(batch.c), _ptr(partials), _ptr(w), float(T),
-                                        _ptr(B), _ptr(res)))
+            if self.torch.is_tensor(cfg_weight) and cfg_weight.is_cuda:
+                if (cfg_weight.dtype != self.torch.float64 or not cfg_weight.is_contiguous()
+                        or cfg_weight.numel() != batch.n_cfg):
+                    raise ValueError("cfg_weight: need a contiguous float64 device tensor of n_cfg entries")
+            else:
+                w = self.torch.as_tensor(np.ascontiguousarray(cfg_weight, np.float64), device=self.device)
+        self._check(fn(self.h_ctx, ctypes.byref(batch.c), _ptr(partials), _ptr(w), float(T), _ptr(B), _ptr(res)))
         return B, res
 
 

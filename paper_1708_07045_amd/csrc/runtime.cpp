@@ -6,7 +6,9 @@
 #include <atomic>
 #include <cmath>
 #include <cstdio>
+#include <cstddef>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <thread>
 #include <vector>
@@ -31,11 +33,57 @@ struct DevBuf {
 
 }  // namespace
 
+// Device scratch of fftdg_reduce_static: one copy per device, held until the
+// process ends.  In host code `scratch` names a host-side stand-in, so host
+// code never hands it to a kernel or a copy; it uses the device address that
+// fftdg_create looks up once per device (static_scratch_ptr).
+static __device__ __align__(256) unsigned char scratch[FFTDG_REDUCE_STATIC_BYTES];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::mutex scratch_mu;
+void *scratch_addr[kMaxDevices] = {};  // device address of `scratch` per device, nullptr until looked up
+
+// Device address of `scratch` on `device` (the current device), looked up
+// on the first call for that device; nullptr with *why set on failure.
+void *static_scratch_ptr(int device, std::string *why) {
+    if (device < 0 || device >= kMaxDevices) {
+        *why = "device index beyond the static scratch table";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(scratch_mu);
+    if (!scratch_addr[device]) {
+        void *ptr = nullptr;
+        hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr) {
+            (void)hipGetLastError();
+            *why = std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e);
+            return nullptr;
+        }
+        scratch_addr[device] = ptr;
+    }
+    return scratch_addr[device];
+}
+
+// The device reduce writes LigRed records that the host copies straight into
+// fftdg_ligand_result.
+static_assert(sizeof(LigRed) == sizeof(fftdg_ligand_result), "LigRed layout");
+static_assert(offsetof(LigRed, dG) == offsetof(fftdg_ligand_result, dG) &&
+                  offsetof(LigRed, v_site) == offsetof(fftdg_ligand_result, v_site) &&
+                  offsetof(LigRed, psi_min) == offsetof(fftdg_ligand_result, psi_min) &&
+                  offsetof(LigRed, n_finite) == offsetof(fftdg_ligand_result, n_finite) &&
+                  offsetof(LigRed, n_samples) == offsetof(fftdg_ligand_result, n_samples),
+              "LigRed layout");
+
+}  // namespace
+
 struct fftdg_ctx {
     fftdg_grid_desc g{};
     int device = 0;
     hipStream_t stream = nullptr;
     std::string err;
+    void *scratch = nullptr;  // device address of the static scratch on `device`
     const KernelSet *ks = nullptr;
     const FusedSet *fs = nullptr;  // fused path (nullptr where not built)
     int n_ch = 3;  // receptor/ligand channels: 3 energy (+1 occupancy)
@@ -905,6 +953,42 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     return FFTDG_OK;
 }
 
+// Argument checks shared by the two reduce entry points.
+int reduce_check(fftdg_ctx *ctx, const fftdg_batch *b, const fftdg_partial *p, double T_K, const double *B_host,
+                 const fftdg_ligand_result *res_host, const char *who) {
+    if (!ctx) return FFTDG_E_INVALID;
+    if (ctx->n_snap <= 0) return set_err(ctx, FFTDG_E_STATE, std::string(who) + " before set_receptors");
+    if (!b || b->n_lig <= 0 || !b->cfg_off) return set_err(ctx, FFTDG_E_INVALID, std::string(who) + ": bad batch");
+    if (!p || !B_host || !res_host) return set_err(ctx, FFTDG_E_INVALID, std::string(who) + ": NULL pointer");
+    if (!(T_K > 0.0) || !is_fin(T_K))
+        return set_err(ctx, FFTDG_E_INVALID, std::string(who) + ": temperature must be > 0");
+    return FFTDG_OK;
+}
+
+// Eqs. 2, 12 and 13 on the device with the given buffers (cfg_off [n_lig + 1],
+// W [n_snap], B [n_lig][n_snap], res [n_lig]); copies B and res to the host
+// and synchronizes the stream.  Allocates nothing.
+int reduce_into(fftdg_ctx *ctx, const fftdg_batch *b, const fftdg_partial *p, const double *cfg_w, double T_K,
+                double *B_host, fftdg_ligand_result *res_host, int32_t *off_d, double *W_d, double *B_d,
+                LigRed *res_d, bool profiled) {
+    const int nl = b->n_lig, ns = ctx->n_snap;
+    HIPCHK(ctx, hipMemcpyAsync(off_d, b->cfg_off, sizeof(int32_t) * (nl + 1), hipMemcpyHostToDevice, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(W_d, ctx->W.data(), sizeof(double) * ns, hipMemcpyHostToDevice, ctx->stream));
+    const double kT = kR * T_K;
+    const double h3 = ctx->g.h * ctx->g.h * ctx->g.h;
+    auto launch = [&] {
+        return launch_reduce(ctx->stream, p, b->cfg_off[nl], ns, nl, off_d, cfg_w, W_d, kT, h3, kC0, B_d, res_d);
+    };
+    if (profiled)
+        HIPCHK(ctx, timed(ctx, FFTDG_K_REDUCE, (double)sizeof(fftdg_partial) * (double)b->cfg_off[nl] * ns, launch));
+    else
+        HIPCHK(ctx, launch());
+    HIPCHK(ctx, hipMemcpyAsync(B_host, B_d, sizeof(double) * (size_t)nl * ns, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipMemcpyAsync(res_host, res_d, sizeof(LigRed) * nl, hipMemcpyDeviceToHost, ctx->stream));
+    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
+    return FFTDG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -965,6 +1049,14 @@ int fftdg_create(fftdg_ctx **out, const fftdg_grid_desc *g, int device, void *hi
         (void)hipGetLastError();
         delete c;
         return fail(FFTDG_E_DEVICE, "hipSetDevice/hipEventCreate failed");
+    }
+    {
+        std::string why;
+        c->scratch = static_scratch_ptr(device, &why);
+        if (!c->scratch) {
+            fftdg_destroy(c);
+            return fail(FFTDG_E_DEVICE, why);
+        }
     }
     // twiddles w_N^k = exp(-2 pi i k / N), FP64 then rounded once
     const int N = g->n_fft;
@@ -1151,39 +1243,38 @@ int fftdg_place(fftdg_ctx *ctx, const fftdg_batch *b, int32_t cfg, int32_t *U, i
 
 int fftdg_reduce(fftdg_ctx *ctx, const fftdg_batch *b, const fftdg_partial *p, const double *cfg_w, double T_K,
                  double *B_host, fftdg_ligand_result *res_host) {
-    if (!ctx) return FFTDG_E_INVALID;
-    if (ctx->n_snap <= 0) return set_err(ctx, FFTDG_E_STATE, "reduce before set_receptors");
-    if (!b || b->n_lig <= 0 || !b->cfg_off) return set_err(ctx, FFTDG_E_INVALID, "reduce: bad batch");
-    if (!p || !B_host || !res_host) return set_err(ctx, FFTDG_E_INVALID, "reduce: NULL pointer");
-    if (!(T_K > 0.0) || !is_fin(T_K)) return set_err(ctx, FFTDG_E_INVALID, "reduce: temperature must be > 0");
+    int rc = reduce_check(ctx, b, p, T_K, B_host, res_host, "reduce");
+    if (rc) return rc;
     HIPCHK(ctx, hipSetDevice(ctx->device));
     const int nl = b->n_lig, ns = ctx->n_snap;
-    int rc;
     if ((rc = reserve(ctx, ctx->red_off, sizeof(int32_t) * (nl + 1)))) return rc;
     if ((rc = reserve(ctx, ctx->red_W, sizeof(double) * ns))) return rc;
     if ((rc = reserve(ctx, ctx->red_B, sizeof(double) * (size_t)nl * ns))) return rc;
     if ((rc = reserve(ctx, ctx->red_res, sizeof(LigRed) * nl))) return rc;
-    HIPCHK(ctx, hipMemcpyAsync(ctx->red_off.p, b->cfg_off, sizeof(int32_t) * (nl + 1), hipMemcpyHostToDevice, ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(ctx->red_W.p, ctx->W.data(), sizeof(double) * ns, hipMemcpyHostToDevice, ctx->stream));
-    const double kT = kR * T_K;
-    const double h3 = ctx->g.h * ctx->g.h * ctx->g.h;
-    HIPCHK(ctx, timed(ctx, FFTDG_K_REDUCE, (double)sizeof(fftdg_partial) * (double)b->cfg_off[nl] * ns, [&] {
-               return launch_reduce(ctx->stream, p, b->cfg_off[nl], ns, nl, (const int32_t *)ctx->red_off.p, cfg_w,
-                                    (const double *)ctx->red_W.p, kT, h3, kC0, (double *)ctx->red_B.p,
-                                    (LigRed *)ctx->red_res.p);
-           }));
-    std::vector<LigRed> r(nl);
-    HIPCHK(ctx, hipMemcpyAsync(B_host, ctx->red_B.p, sizeof(double) * (size_t)nl * ns, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(ctx, hipMemcpyAsync(r.data(), ctx->red_res.p, sizeof(LigRed) * nl, hipMemcpyDeviceToHost, ctx->stream));
-    HIPCHK(ctx, hipStreamSynchronize(ctx->stream));
-    for (int l = 0; l < nl; ++l) {
-        res_host[l].dG = r[l].dG;
-        res_host[l].v_site = r[l].v_site;
-        res_host[l].psi_min = r[l].psi_min;
-        res_host[l].n_finite = r[l].n_finite;
-        res_host[l].n_samples = r[l].n_samples;
-    }
-    return FFTDG_OK;
+    return reduce_into(ctx, b, p, cfg_w, T_K, B_host, res_host, (int32_t *)ctx->red_off.p, (double *)ctx->red_W.p,
+                       (double *)ctx->red_B.p, (LigRed *)ctx->red_res.p, true);
+}
+
+int fftdg_reduce_static(fftdg_ctx *ctx, const fftdg_batch *b, const fftdg_partial *p, const double *cfg_w,
+                        double T_K, double *B_host, fftdg_ligand_result *res_host) {
+    int rc = reduce_check(ctx, b, p, T_K, B_host, res_host, "reduce_static");
+    if (rc) return rc;
+    const size_t nl = (size_t)b->n_lig, ns = (size_t)ctx->n_snap;
+    // scratch layout: cfg_off [nl + 1] | W [ns] | B [nl][ns] | LigRed [nl], each 256-byte aligned
+    auto up = [](size_t x) { return (x + 255) & ~(size_t)255; };
+    const size_t o_W = up(sizeof(int32_t) * (nl + 1));
+    const size_t o_B = o_W + up(sizeof(double) * ns);
+    const size_t o_res = o_B + up(sizeof(double) * nl * ns);
+    const size_t need = o_res + sizeof(LigRed) * nl;
+    if (need > (size_t)FFTDG_REDUCE_STATIC_BYTES)
+        return set_err(ctx, FFTDG_E_INVALID,
+                       "reduce_static: " + std::to_string(nl) + " ligands x " + std::to_string(ns) +
+                           " snapshots need " + std::to_string(need) + " bytes of static scratch; the limit is " +
+                           std::to_string((size_t)FFTDG_REDUCE_STATIC_BYTES) + " (fftdg_reduce has no limit)");
+    HIPCHK(ctx, hipSetDevice(ctx->device));
+    char *base = (char *)ctx->scratch;
+    return reduce_into(ctx, b, p, cfg_w, T_K, B_host, res_host, (int32_t *)base, (double *)(base + o_W),
+                       (double *)(base + o_B), (LigRed *)(base + o_res), false);
 }
 
 int fftdg_profile(fftdg_ctx *ctx, int enable) {

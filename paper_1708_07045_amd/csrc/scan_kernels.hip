@@ -1339,8 +1339,6 @@ __global__ __launch_bounds__(NT) void k_reduce(const fftdg_partial *__restrict__
     double pmin_all = INFINITY;
     long long nfin_all = 0, nsamp = 0;
     double gmax = -INFINITY;
-    double Bs_local[1];
-    (void)Bs_local;
     for (int s = 0; s < n_snap; ++s) {
         const fftdg_partial *ps = p + (int64_t)s * n_cfg_total;
         double mx = -INFINITY;
