@@ -351,19 +351,28 @@ int fftdg_pair_energies(int device, void *hip_stream, int32_t n_rec_atoms, const
  *                      factors (no forward planes).  energy_xy_direct and
  *                      snapshots_per_pass are then not used.  0: the
  *                      occupancy channel as a fourth FFT channel thresholded
- *                      at 1/2 (the paper's formulation). */
+ *                      at 1/2 (the paper's formulation);
+ *   clash_stream       fused path in OCC mode: 1 (default) runs the clash
+ *                      test of the next (chunk, snapshot) on a second stream
+ *                      of the context (default priority, created on first
+ *                      use) beside the z pass and inverse of the current one,
+ *                      its results double-buffered and the streams ordered
+ *                      by events; 0 runs everything on the context's stream.
+ *                      Not used while profiling or exporting energies. */
 typedef struct {
     int32_t configs_per_chunk;
     int32_t energy_xy_direct;
     int32_t snapshots_per_pass;
     int32_t use_graph;
     int32_t fused;
+    int32_t clash_stream;
 } fftdg_tuning;
 int fftdg_get_tuning(const fftdg_ctx *ctx, fftdg_tuning *out);
 int fftdg_set_tuning(fftdg_ctx *ctx, const fftdg_tuning *t);
 
 /* Autotuner: times the candidate schedules (configurations per chunk in
- * {64, 128, 256, 512}, use_graph in {0, 1}, and fused in {1, 2} where available or
+ * {64, 128, 256, 512}, use_graph in {0, 1}, and fused in {1, 2} with
+ * clash_stream in {0, 1} (OCC mode) where available or
  * fused = 0 with energy_xy_direct in {0, 1, 2} and snapshots_per_pass in
  * {1, n_snap} when there are several snapshots) with
  * HIP events, each by the fastest of four runs after a warm-up, on an evenly

@@ -39,12 +39,14 @@ class GridDesc(ctypes.Structure):
 
 class Tuning(ctypes.Structure):
     _fields_ = [("configs_per_chunk", ctypes.c_int32), ("energy_xy_direct", ctypes.c_int32),
-                ("snapshots_per_pass", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("fused", ctypes.c_int32)]
+                ("snapshots_per_pass", ctypes.c_int32), ("use_graph", ctypes.c_int32), ("fused", ctypes.c_int32),
+                ("clash_stream", ctypes.c_int32)]
 
 
 def _tuning_dict(t: Tuning) -> dict:
     return {"configs_per_chunk": t.configs_per_chunk, "energy_xy_direct": t.energy_xy_direct,
-            "snapshots_per_pass": t.snapshots_per_pass, "use_graph": t.use_graph, "fused": t.fused}
+            "snapshots_per_pass": t.snapshots_per_pass, "use_graph": t.use_graph, "fused": t.fused,
+            "clash_stream": t.clash_stream}
 
 
 class BatchC(ctypes.Structure):
@@ -227,7 +229,7 @@ class FFTDG:
 
     def set_tuning(self, configs_per_chunk: Optional[int] = None, energy_xy_direct: Optional[int] = None,
                    snapshots_per_pass: Optional[int] = None, use_graph: Optional[int] = None,
-                   fused: Optional[int] = None):
+                   fused: Optional[int] = None, clash_stream: Optional[int] = None):
         cur = self.get_tuning()
         if configs_per_chunk is not None:
             cur["configs_per_chunk"] = int(configs_per_chunk)
@@ -239,8 +241,10 @@ class FFTDG:
             cur["use_graph"] = int(use_graph)
         if fused is not None:
             cur["fused"] = int(fused)
+        if clash_stream is not None:
+            cur["clash_stream"] = int(clash_stream)
         t = Tuning(cur["configs_per_chunk"], cur["energy_xy_direct"], cur["snapshots_per_pass"],
-                   cur["use_graph"], cur["fused"])
+                   cur["use_graph"], cur["fused"], cur["clash_stream"])
         self._check(self.L.fftdg_set_tuning(self.h_ctx, ctypes.byref(t)))
 
     def autotune(self, batch: "Batch", T: float, max_cfgs: int = 2048):

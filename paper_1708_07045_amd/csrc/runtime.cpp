@@ -103,6 +103,9 @@ struct fftdg_ctx {
     int snap_group = 1;  // snapshots per z launch (limited by workspace)
     bool use_graph = false;
     int fused = 0;  // 0 plane path; fused path with energy planes from the forward pass (1) or built in the z kernel (2)
+    bool clash_stream = true;  // fused path, OCC: clash test of the next item on `side` beside the current z pass
+    hipStream_t side = nullptr;  // second stream (default priority), created on first use
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_clash[2] = {nullptr, nullptr}, ev_inv[2] = {nullptr, nullptr};
     hipStream_t cap_stream = nullptr;   // capture only; graphs run on `stream`
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -746,13 +749,27 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
         if ((rc = reserve(ctx, ctx->zat, ctx->fs->zat_bytes * (size_t)max_nz_atoms))) return rc;
         if ((rc = reserve(ctx, ctx->zbt, sizeof(int32_t) * (size_t)nzmax * (g.n_fft + 2)))) return rc;
     }
+    // fused path, OCC: the clash test of the next (chunk, snapshot) item runs
+    // on the side stream beside the z pass and inverse of the current one;
+    // its results (free bits, live flags, undecided-row lists) alternate
+    // between two buffer sets
+    const bool overlap = P.fused && occ && ctx->clash_stream && !ctx->prof && !psi_out && !clash_out;
+    const int nsets = overlap ? 2 : 1;
+    const size_t e_free = (size_t)std::max<int64_t>(P.max_free, 1), e_items = (size_t)std::max<int64_t>(P.max_items, 1);
+    const size_t e_surv = (size_t)std::max<int64_t>(P.max_surv, 1), e_cfgs = (size_t)std::max<int64_t>(P.max_chunk_cfgs, 1);
     if (P.fused && occ) {
         if ((rc = reserve(ctx, ctx->runs, 2 * sizeof(uint32_t) * (size_t)std::max<int64_t>(P.max_runs, 1)))) return rc;
-        if ((rc = reserve(ctx, ctx->run_cnt, sizeof(int32_t) * (size_t)std::max<int64_t>(P.max_chunk_cfgs, 1)))) return rc;
-        if ((rc = reserve(ctx, ctx->fbits, sizeof(uint32_t) * (size_t)std::max<int64_t>(P.max_free, 1)))) return rc;
-        if ((rc = reserve(ctx, ctx->lives, (size_t)std::max<int64_t>(P.max_items, 1)))) return rc;
-        if ((rc = reserve(ctx, ctx->surv, sizeof(uint32_t) * (size_t)std::max<int64_t>(P.max_surv, 1)))) return rc;
-        if ((rc = reserve(ctx, ctx->scnt, sizeof(int32_t) * (size_t)std::max<int64_t>(P.max_chunk_cfgs, 1)))) return rc;
+        if ((rc = reserve(ctx, ctx->run_cnt, sizeof(int32_t) * e_cfgs))) return rc;
+        if ((rc = reserve(ctx, ctx->fbits, sizeof(uint32_t) * e_free * nsets))) return rc;
+        if ((rc = reserve(ctx, ctx->lives, e_items * nsets))) return rc;
+        if ((rc = reserve(ctx, ctx->surv, sizeof(uint32_t) * e_surv * nsets))) return rc;
+        if ((rc = reserve(ctx, ctx->scnt, sizeof(int32_t) * e_cfgs * nsets))) return rc;
+    }
+    if (overlap && !ctx->side) {
+        HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+        for (hipEvent_t *e : {&ctx->ev_fork, &ctx->ev_join, &ctx->ev_clash[0], &ctx->ev_clash[1], &ctx->ev_inv[0],
+                              &ctx->ev_inv[1]})
+            HIPCHK(ctx, hipEventCreateWithFlags(e, hipEventDisableTiming));
     }
     // snapshots whose inverse planes share the workspace: the z kernel keeps
     // a configuration's forward spectra in registers across the group
@@ -798,15 +815,28 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     const FusedSet *fs = ctx->fs;
     uint32_t *runs = (uint32_t *)ctx->runs.p;
     int32_t *rcnt = (int32_t *)ctx->run_cnt.p;
-    uint32_t *fb = (uint32_t *)ctx->fbits.p;
-    uint8_t *lv = (uint8_t *)ctx->lives.p;
     const double b_spec3 = 3.0 * (double)g.n_fft * ctx->ks->np * cb;
+    // buffer set p of the clash results
+    auto fb_of = [&](int p) { return (uint32_t *)ctx->fbits.p + (size_t)p * e_free; };
+    auto lv_of = [&](int p) { return (uint8_t *)ctx->lives.p + (size_t)p * e_items; };
+    auto surv_of = [&](int p) { return (uint32_t *)ctx->surv.p + (size_t)p * e_surv; };
+    auto scnt_of = [&](int p) { return (int32_t *)ctx->scnt.p + (size_t)p * e_cfgs; };
+    // stream of the occupancy runs and the clash test; with the overlap it
+    // starts after the work already ordered on `st` (the table upload)
+    hipStream_t sc = st;
+    if (overlap) {
+        sc = ctx->side;
+        HIPCHK(ctx, hipEventRecord(ctx->ev_fork, st));
+        HIPCHK(ctx, hipStreamWaitEvent(sc, ctx->ev_fork, 0));
+    }
+    int item = 0;
     for (const Plan::Chunk &ch : P.chunks) {
         const CfgDev *ccfg = dcfg + ch.c0;
         const int nloc = ch.c1 - ch.c0;
+        // the runs of this chunk follow the previous chunk's clash tests on `sc`
         if (occ)
             HIPCHK(ctx, timed(ctx, FFTDG_K_RUNS, 8.0 * (double)ch.nruns, [&] {
-                       return fs->lig_runs(st, ccfg, dz + ch.z0, (int)ch.nz, du, dthr, runs, rcnt);
+                       return fs->lig_runs(sc, ccfg, dz + ch.z0, (int)ch.nz, du, dthr, runs, rcnt);
                    }));
         if (P.fused_planes)
             HIPCHK(ctx, timed(ctx, FFTDG_K_FWD, (double)ch.ws_fwd * cb, [&] {
@@ -818,14 +848,22 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
                        return fs->zprep(st, ccfg, dz + ch.z0, (int)ch.nz, std::max(ch.max_atoms, 1), du, dgam,
                                         ctx->zat.p, (int32_t *)ctx->zbt.p);
                    }));
-        for (int s = s_begin; s < s_end; ++s) {
+        for (int s = s_begin; s < s_end; ++s, ++item) {
+            const int p = overlap ? (item & 1) : 0;
+            uint32_t *fb = fb_of(p);
+            uint8_t *lv = lv_of(p);
             if (occ) {
+                // set p was last read by the inverse of item - 2
+                if (overlap && item >= 2) HIPCHK(ctx, hipStreamWaitEvent(sc, ctx->ev_inv[p], 0));
                 const uint32_t *dil = (const uint32_t *)ctx->dil.p + (size_t)s * (size_t)fs->dil_words;
                 HIPCHK(ctx, timed(ctx, FFTDG_K_CLASH, 4.0 * (double)ch.nfree + (double)ch.nitems, [&] {
-                           return fs->clash(st, ditem + ch.off0, ditem2 + ch.off0, nloc, ch.nitems, ch.nitems2, ccfg,
-                                            runs, rcnt, dil, fb, lv, (uint32_t *)ctx->surv.p,
-                                            (int32_t *)ctx->scnt.p);
+                           return fs->clash(sc, ditem + ch.off0, ditem2 + ch.off0, nloc, ch.nitems, ch.nitems2, ccfg,
+                                            runs, rcnt, dil, fb, lv, surv_of(p), scnt_of(p));
                        }));
+                if (overlap) {
+                    HIPCHK(ctx, hipEventRecord(ctx->ev_clash[p], sc));
+                    HIPCHK(ctx, hipStreamWaitEvent(st, ctx->ev_clash[p], 0));
+                }
             }
             const char *rs = (const char *)ctx->rspec.p + spec_per_snap * s;
             // planes written are counted on the device (those the inverse reads)
@@ -843,8 +881,13 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
                                       ctx->tw.p, fb, lv, pp_s, psi_out, clash_out,
                                       ctx->prof ? (unsigned int *)ctx->prof_cnt.p : nullptr);
                    }));
+            if (overlap) HIPCHK(ctx, hipEventRecord(ctx->ev_inv[p], st));
             if (ctx->prof) ctx->prof_fused = true;
         }
+    }
+    if (overlap) {  // join: later work on `st` sees the side stream's work done
+        HIPCHK(ctx, hipEventRecord(ctx->ev_join, sc));
+        HIPCHK(ctx, hipStreamWaitEvent(st, ctx->ev_join, 0));
     }
     if (out)
         for (int s = s_begin; s < s_end; ++s) {
@@ -903,6 +946,7 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     const bool graph_ok = ctx->use_graph && !ctx->prof && !psi_out && !clash_out && out;
     if (!graph_ok) return launch_all(ctx->stream);
     std::vector<int64_t> sig = {(int64_t)(intptr_t)ks, occ, ctx->edirect, grp, s_begin, s_end, P.fused, P.fused_planes,
+                                overlap, (int64_t)(intptr_t)ctx->side,
                                 (int64_t)(intptr_t)ctx->runs.p, (int64_t)(intptr_t)ctx->run_cnt.p,
                                 (int64_t)(intptr_t)ctx->fbits.p, (int64_t)(intptr_t)ctx->lives.p,
                                 (int64_t)(intptr_t)ctx->dil.p, (int64_t)o_item, (int64_t)(intptr_t)ctx->zat.p,
@@ -1109,6 +1153,9 @@ void fftdg_destroy(fftdg_ctx *c) {
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+    for (hipEvent_t e : {c->ev_fork, c->ev_join, c->ev_clash[0], c->ev_clash[1], c->ev_inv[0], c->ev_inv[1]})
+        if (e) (void)hipEventDestroy(e);
+    if (c->side) (void)hipStreamDestroy(c->side);
     delete c;
 }
 
@@ -1340,6 +1387,7 @@ int fftdg_get_tuning(const fftdg_ctx *ctx, fftdg_tuning *t) {
     t->snapshots_per_pass = ctx->snap_group;
     t->use_graph = ctx->use_graph ? 1 : 0;
     t->fused = ctx->fused;
+    t->clash_stream = ctx->clash_stream ? 1 : 0;
     return FFTDG_OK;
 }
 
@@ -1352,14 +1400,17 @@ int fftdg_set_tuning(fftdg_ctx *ctx, const fftdg_tuning *t) {
     if (t->energy_xy_direct == 1 && ctx->g.n_fft > 128)
         return set_err(ctx, FFTDG_E_INVALID, "set_tuning: energy_xy_direct = 1 needs n_fft <= 128");
     if (t->snapshots_per_pass < 1) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: snapshots_per_pass must be >= 1");
-    ctx->chunk_cfgs = t->configs_per_chunk;
-    ctx->edirect = t->energy_xy_direct;
     if (t->use_graph != 0 && t->use_graph != 1) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: use_graph must be 0 or 1");
     if (t->fused < 0 || t->fused > 2) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: fused must be 0, 1 or 2");
     if (t->fused && !ctx->fs) return set_err(ctx, FFTDG_E_INVALID, "set_tuning: the fused path needs n_fft <= 128");
+    if (t->clash_stream != 0 && t->clash_stream != 1)
+        return set_err(ctx, FFTDG_E_INVALID, "set_tuning: clash_stream must be 0 or 1");
+    ctx->chunk_cfgs = t->configs_per_chunk;
+    ctx->edirect = t->energy_xy_direct;
     ctx->snap_group = t->snapshots_per_pass;
     ctx->use_graph = t->use_graph != 0;
     ctx->fused = t->fused;
+    ctx->clash_stream = t->clash_stream != 0;
     return FFTDG_OK;
 }
 
@@ -1433,7 +1484,15 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
     bs.cfg_select = sel.data();
     if ((rc = reserve(ctx, ctx->tune_out, sizeof(fftdg_partial) * (size_t)ncfg * ctx->n_snap))) return rc;
     const fftdg_tuning keep = {ctx->chunk_cfgs, ctx->edirect, ctx->snap_group, ctx->use_graph ? 1 : 0,
-                               ctx->fused};
+                               ctx->fused, ctx->clash_stream ? 1 : 0};
+    auto apply = [&](const fftdg_tuning &t) {
+        ctx->chunk_cfgs = t.configs_per_chunk;
+        ctx->edirect = t.energy_xy_direct;
+        ctx->snap_group = t.snapshots_per_pass;
+        ctx->use_graph = t.use_graph != 0;
+        ctx->fused = t.fused;
+        ctx->clash_stream = t.clash_stream != 0;
+    };
     const bool prof = ctx->prof;
     ctx->prof = false;
     std::vector<fftdg_tuning> cand;
@@ -1442,11 +1501,14 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
     for (int chunk : {64, 128, 256, 512}) {
         if (ctx->fs)
             for (int fu : {1, 2})
-                for (int gr : {0, 1}) cand.push_back(fftdg_tuning{chunk, ctx->edirect, 1, gr, fu});
+                for (int gr : {0, 1})
+                    for (int cs : {0, 1})
+                        if (cs == 0 || ctx->g.clash_mode == FFTDG_OCC)
+                            cand.push_back(fftdg_tuning{chunk, ctx->edirect, 1, gr, fu, cs});
         for (int ed : {0, 1, 2})
             for (int sp : passes)
                 for (int gr : {0, 1})
-                    if (ed != 1 || ctx->g.n_fft <= 128) cand.push_back(fftdg_tuning{chunk, ed, sp, gr, 0});
+                    if (ed != 1 || ctx->g.n_fft <= 128) cand.push_back(fftdg_tuning{chunk, ed, sp, gr, 0, 0});
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(ctx, hipEventCreate(&e0));
@@ -1455,11 +1517,7 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
     fftdg_tuning bt = keep;
     int err = FFTDG_OK;
     for (const fftdg_tuning &t : cand) {
-        ctx->chunk_cfgs = t.configs_per_chunk;
-        ctx->edirect = t.energy_xy_direct;
-        ctx->snap_group = t.snapshots_per_pass;
-        ctx->use_graph = t.use_graph != 0;
-        ctx->fused = t.fused;
+        apply(t);
         float tmin = INFINITY;
         for (int rep = 0; rep < 5 && !err; ++rep) {  // a warm-up run, then the fastest of four
             Plan P;
@@ -1482,19 +1540,11 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
     (void)hipEventDestroy(e1);
     ctx->prof = prof;
     if (err) {
-        ctx->chunk_cfgs = keep.configs_per_chunk;
-        ctx->edirect = keep.energy_xy_direct;
-        ctx->snap_group = keep.snapshots_per_pass;
-        ctx->use_graph = keep.use_graph != 0;
-        ctx->fused = keep.fused;
+        apply(keep);
         if (err == FFTDG_E_DEVICE && ctx->err.empty()) ctx->err = "autotune: HIP event error";
         return err;
     }
-    ctx->chunk_cfgs = bt.configs_per_chunk;
-    ctx->edirect = bt.energy_xy_direct;
-    ctx->snap_group = bt.snapshots_per_pass;
-    ctx->use_graph = bt.use_graph != 0;
-    ctx->fused = bt.fused;
+    apply(bt);
     if (out) *out = bt;
     if (ms_host) *ms_host = best / ((double)nsel * ctx->n_snap);
     return FFTDG_OK;

@@ -301,6 +301,33 @@ def test_scan_batched_uneven_ligands_three_snapshots_fused(fused, chunk):
     assert P.shape[0] == 3
 
 
+@pytest.mark.parametrize("fused", [1, 2])
+def test_clash_stream_matches_one_stream(fused):
+    """The clash test on the second stream (next item beside the current z
+    pass and inverse, double-buffered results, event-ordered) gives the same
+    partials bit for bit as one stream, eagerly and as a captured graph
+    replayed several times with eager work and synchronizations between
+    replays; ragged three-snapshot batch, chunks of 5 (many items)."""
+    import torch
+    w = synth.config3(n_ligands=5, n_snap=3, cfg_scale=0.02)
+    ctx, grids, occ = _gpu_setup(w, fused=fused, configs_per_chunk=5, clash_stream=0, use_graph=0)
+    b = _batch(w)
+    _announce(f"clash stream vs one stream: fused={fused} n_cfg={b.n_cfg} n_snap=3")
+    ref = ctx.scan(b, w.T).cpu().numpy()
+    ctx.set_tuning(clash_stream=1)
+    np.testing.assert_array_equal(ctx.scan(b, w.T).cpu().numpy(), ref)
+    ctx.set_tuning(use_graph=1)
+    out = ctx.alloc_partials(b)
+    for rep in range(3):
+        out.zero_()
+        ctx.scan(b, w.T, out)
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(out.cpu().numpy(), ref)
+        x = torch.randn(1 << 20, device="cuda")
+        (x * 2).sum().item()
+    assert ctx.get_tuning()["clash_stream"] == 1
+
+
 def test_cfg_select_and_empty_configs():
     """cfg_select scans a subset; unscanned configurations still count their
     translations; a configuration whose box exceeds the grid has n_valid 0."""
