@@ -348,8 +348,8 @@ def configs_needed(args):
     S = w.receptor.n_snap
     log(f"configs needed: {len(w.ligands)} ligands, {b.n_cfg} configurations x {S} snapshots")
     ctx_f = prop.make_context(w)
-    # coarse pre-scan at twice the spacing: against one receptor at the
-    # snapshots' mean coordinates (default), every snapshot, or the first
+    # coarse pre-scan at twice the spacing: against every snapshot (default),
+    # one receptor at the snapshots' mean coordinates, or the first snapshot
     ctx_c = prop.make_context(w, prop.coarse_desc(w, args.is_coarse_factor), snapshots=args.is_coarse_snapshots)
     ctx_f.autotune(b, T, max_cfgs=2048)
     ctx_c.autotune(b, T, max_cfgs=2048)
@@ -519,7 +519,7 @@ def main():
                     help="training target: largest per-snapshot relative log weight, or the log of the "
                          "snapshot-weighted sum")
     ap.add_argument("--is-detail", default="", help="write per-ligand configurations-needed results here (JSON)")
-    ap.add_argument("--is-coarse", default="mean", choices=["mean", "all", "first"],
+    ap.add_argument("--is-coarse", default="all", choices=["mean", "all", "first"],
                     help="coarse pre-scan receptors: one at the snapshots' mean coordinates, every snapshot, "
                          "or the first snapshot")
     args = ap.parse_args()

@@ -162,3 +162,36 @@ def test_n256_graph_replays_and_pose_resampling():
         tx, ty, tz = t[k]
         assert not bool(cl[tz, ty, tx].item())
         assert abs(float(e[tz, ty, tx].item()) - psi[k]) <= 1e-6 * max(1.0, abs(psi[k]))
+
+
+def test_c6_full_size_subset_bpmf_against_oracle():
+    """Full whole-surface size, every translation: the BPMF pooled over an
+    evenly strided subset of 16 of the 8000 configurations (Eq. 2) and the
+    per-configuration partials against the FP64 oracle's, stored by
+    tests/golden/make_c6_subset_oracle.py, in the schedule the bench times
+    (64 configurations per chunk, direct energy planes)."""
+    import json
+    import os
+    import paper_1708_07045_amd as fd
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "c6_subset_oracle.json")))
+    w = synth.subset(synth.config6(), 16, stride=500)
+    assert [int(c) for c in np.arange(0, 8000, 500)] == ref["configs"]
+    print("c6 full-size subset: 16 configurations x all translations", flush=True)
+    ctx = _ctx(w, energy_xy_direct=2, configs_per_chunk=64)
+    b = fd.Batch(w.ligands)
+    part = ctx.scan(b, w.T)
+    B, res = ctx.reduce(b, part, w.T)
+    P = ctx.partials_numpy(part, 1, b.n_cfg)[0]
+    parts = np.asarray(ref["partials"])
+    np.testing.assert_array_equal(P["n_valid"], parts[:, 2].astype(np.int64))
+    np.testing.assert_array_equal(P["n_finite"], parts[:, 3].astype(np.int64))
+    lz_ref = est.log_z(parts)
+    fin = P["n_finite"] > 0
+    lz = np.where(fin, P["m"] + np.log(np.where(fin, P["s"], 1.0)), -np.inf)
+    kT = est.kT(w.T)
+    ok = np.isfinite(lz_ref)
+    np.testing.assert_array_equal(np.isfinite(lz), ok)
+    dcfg = np.max(np.abs(kT * (lz[ok] - lz_ref[ok]))) if ok.any() else 0.0
+    print(f"  |dB| = {abs(B[0, 0] - ref['B']):.3g} kcal/mol, max per-configuration |kT d lnZ| = {dcfg:.3g}",
+          flush=True)
+    assert abs(B[0, 0] - ref["B"]) < 0.01 and dcfg < 0.01
