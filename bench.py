@@ -68,7 +68,7 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "zprod_t4l_8000cfg_hbm_traffic.md")
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "scan_t4l_8000cfg_hbm_traffic.md")
 KERNEL_SOURCES = ["scan_kernels.hip", "fused_kernels.hip", "fft_device.hpp", "scan_types.hpp", "kernels.hpp",
                   "scan_common.hpp", "fused.hpp"]
 
@@ -83,9 +83,10 @@ def kernel_source_digest() -> str:
 
 
 def recorded_traffic(tuning: dict):
-    """HBM bytes per configuration of the z-pencil kernel measured by the
-    FETCH_SIZE / WRITE_SIZE counter runs recorded in the profile summary, if
-    those runs used these kernel sources and energy schedule (else None)."""
+    """HBM bytes per configuration of one scan (all of its kernels) measured
+    by the FETCH_SIZE / WRITE_SIZE counter runs recorded in the profile
+    summary, if those runs used these kernel sources and scan path (else
+    None)."""
     if not os.path.exists(TRAFFIC_PROFILE):
         return None
     rec = {}
@@ -94,9 +95,9 @@ def recorded_traffic(tuning: dict):
             k, v = line[2:].split(": ", 1)
             rec[k.strip()] = v.strip().strip("`")
     try:
-        # per configuration the z kernel's traffic does not depend on the
-        # chunk size except for the receptor spectra read once per launch
-        # (about 1 % of its bytes at 128 configurations per chunk, less above)
+        # per configuration the scan's traffic does not depend on the chunk
+        # size except for the receptor spectra read once per chunk (about 1 %
+        # of the bytes at 128 configurations per chunk, less above)
         if rec["kernel_source_sha256"] != kernel_source_digest():
             return None
         if int(rec.get("fused", 0)) != tuning.get("fused", 0) or tuning["configs_per_chunk"] < 128:
