@@ -87,6 +87,16 @@ __device__ __forceinline__ long long isqrt_lt(long long rem) {
     return s;
 }
 
+// XCD-aware block order for any grid size: workgroups land on the 8 XCDs
+// round-robin (block b on XCD b mod 8), so XCD x is given the contiguous
+// logical range [x q + min(x, r), ...) of its blocks, nb = 8 q + r;
+// neighbouring logical blocks (e.g. the column tiles of one plane, whose
+// rows straddle the same cache lines) then share one L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+    const int q = nb >> 3, r = nb & 7, x = b & 7;
+    return x * q + (x < r ? x : r) + (b >> 3);
+}
+
 // Largest i in [0, n) with off[i] <= b, for a running count off[0..n]
 // (off[0] = 0 <= b < off[n]); configurations without work repeat a value.
 __device__ __forceinline__ int find_cfg(const int32_t *__restrict__ off, int n, int b) {

@@ -708,7 +708,8 @@ __global__ __launch_bounds__(NT) void k_fwd_cols(const int32_t *__restrict__ fwd
     using TL = Tile<T, N>;
     __shared__ C2 tb[N * TL::TS];
     __shared__ C2 tw[N];
-    const int bi = (int)blockIdx.x / TL::NTILE, tile = (int)blockIdx.x % TL::NTILE;
+    const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int bi = lb / TL::NTILE, tile = lb % TL::NTILE;
     const int ic = find_cfg(fwd_off, n_cfg, bi);
     const CfgDev c = cfgs[ic];
     const int item = bi - fwd_off[ic];
@@ -1441,7 +1442,8 @@ __global__ __launch_bounds__(NT) void k_inv_cols(const int32_t *__restrict__ inv
     __shared__ C2 tw[N];
     constexpr int NCH = OCC ? 2 : 1;
     const int per = NCH * TL::NTILE;
-    const int bi = (int)blockIdx.x / per, rem = (int)blockIdx.x % per;
+    const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
+    const int bi = lb / per, rem = lb % per;
     const int och = rem / TL::NTILE, tile = rem % TL::NTILE;
     const int ic = find_cfg(inv_off, n_cfg, bi);
     const CfgDev c = cfgs[ic];

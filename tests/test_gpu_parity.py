@@ -281,6 +281,16 @@ def test_scan_c2_subset_fp32_fused(fused, chunk, graph):
     _scan_parity(w, "f32", 0.01, fused=fused, configs_per_chunk=chunk, use_graph=graph)
 
 
+def test_wide_occupancy_balls_take_the_plane_path():
+    """Ligand atoms whose occupancy balls reach more than the clash table's
+    8-point margin past the box (sigma x 1.3: radius up to 9.3 points) are
+    scanned on the plane path even with the fused path selected; results
+    match the oracle."""
+    w = synth.subset(synth.config2(), 40, stride=197)
+    w.ligands[0].sigma = w.ligands[0].sigma * 1.3
+    _scan_parity(w, "f32", 0.01, fused=1, configs_per_chunk=16)
+
+
 @pytest.mark.parametrize("snap_pass,chunk,edirect", [(16, 256, 0), (1, 256, 0), (2, 5, 0), (1, 64, 2), (16, 9, 2)])
 def test_scan_batched_uneven_ligands_three_snapshots(snap_pass, chunk, edirect):
     """Ragged batch: 5 ligands of 8..40 atoms with different configuration
