@@ -853,22 +853,81 @@ void k_zprod(const CfgDev *__restrict__ cfgs, const int32_t *__restrict__ zcfg,
     // correlation of the shifted ligand grid is the wanted one shifted by
     // zo0, C(t) = C'(t + zo0 mod N), so the store takes element z to
     // translation t = z - zo0 mod N.
+    //
+    // N = 256 (4 pencils per wavefront): a lane's own elements lie in 16
+    // planes at 4 pencils each, 32-byte pieces per load.  There the block
+    // loads and stores its 16 pencils plane row by plane row instead (thread
+    // (r, q): pencil q, planes r + 16 i; each plane row 128 contiguous bytes)
+    // and transposes through LDS (the wavefronts' exchange regions, between
+    // block barriers).
     constexpr int HZ = R2 / 2;
-    const int po = ok ? pen : NP * N;  // out of every descriptor's range
+    constexpr bool STG = N == 256;
+    constexpr int SQ = P + 1;  // LDS row stride of the staging transpose (complex)
+    static_assert(!STG || (P == 16 && NT == 256 && N * SQ <= 4 * G::WREG), "staging layout");
+    const int po = ok ? pen : NP * N;
+    const int sr = threadIdx.x / P, sq = threadIdx.x % P;            // staging: plane row, pencil
+    const int spo = (tile * P + sq < NP) ? tile * P + sq : NP * N;  // out of every descriptor's range
     C2 pf[HZ];
     auto fetch = [&](int ch) {
+        const int lz = STG ? sr : n1, lp = STG ? spo : po;
         if (ch < 3) {
             const auto rs = make_rsrc(ws + c.off_fwd + (int64_t)ch * c.Le * NP, c.Le * NP * (int)sizeof(C2));
 #pragma unroll
             for (int i = 0; i < HZ; ++i) {
-                const int s = (n1 + R1 * i - c.ze0) & (N - 1);
-                pf[i] = buf_load(rs, (s * NP + po) * (int)sizeof(C2), (C2 *)nullptr);
+                const int s = (lz + R1 * i - c.ze0) & (N - 1);
+                pf[i] = buf_load(rs, (s * NP + lp) * (int)sizeof(C2), (C2 *)nullptr);
             }
         } else {
             const auto rs = make_rsrc(ws + c.off_fwd + (int64_t)c.occ_slot0 * NP, c.Lo * NP * (int)sizeof(C2));
 #pragma unroll
             for (int i = 0; i < HZ; ++i)
-                pf[i] = buf_load(rs, ((n1 + R1 * i) * NP + po) * (int)sizeof(C2), (C2 *)nullptr);
+                pf[i] = buf_load(rs, ((lz + R1 * i) * NP + lp) * (int)sizeof(C2), (C2 *)nullptr);
+        }
+    };
+    // the prefetched planes into this lane's registers (lower half), upper half zero
+    auto take = [&](T *re, T *im) {
+        if constexpr (STG) {
+            __syncthreads();  // every wavefront is done with its exchange region
+#pragma unroll
+            for (int i = 0; i < HZ; ++i) buf[(sr + R1 * i) * SQ + sq] = pf[i];
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < HZ; ++i) {
+                const C2 v = buf[(n1 + R1 * i) * SQ + p];
+                re[i] = v.x;
+                im[i] = v.y;
+            }
+            __syncthreads();  // read before the exchange regions are reused
+        } else {
+#pragma unroll
+            for (int i = 0; i < HZ; ++i) {
+                re[i] = pf[i].x;
+                im[i] = pf[i].y;
+            }
+        }
+#pragma unroll
+        for (int i = HZ; i < R2; ++i) re[i] = im[i] = (T)0;
+    };
+    // store this lane's transform outputs (element z = n1 + R1 i) at
+    // translation (z - z0) mod N of an inverse region of Vz planes
+    auto put = [&](const T *re, const T *im, C2 *dst, int Vzz, int z0) {
+        const auto rd = make_rsrc(dst, Vzz * NP * (int)sizeof(C2));
+        if constexpr (STG) {
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < R2; ++i) buf[(n1 + R1 * i) * SQ + p] = C2{re[i], im[i]};
+            __syncthreads();
+#pragma unroll
+            for (int i = 0; i < R2; ++i) {
+                const int z = sr + R1 * i, t = (z - z0) & (N - 1);
+                buf_store(rd, (t * NP + spo) * (int)sizeof(C2), buf[z * SQ + sq]);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < R2; ++i) {
+                const int t = (n1 + R1 * i - z0) & (N - 1);
+                buf_store(rd, (t * NP + po) * (int)sizeof(C2), C2{re[i], im[i]});
+            }
         }
     };
     T er[R2], ei[R2];
@@ -878,35 +937,20 @@ void k_zprod(const CfgDev *__restrict__ cfgs, const int32_t *__restrict__ zcfg,
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
         T re[R2], im[R2];
-#pragma unroll
-        for (int i = 0; i < HZ; ++i) {
-            re[i] = pf[i].x;
-            im[i] = pf[i].y;
-            re[i + HZ] = im[i + HZ] = (T)0;
-        }
+        take(re, im);
         if (ch < 2 || OCC) fetch(ch + 1);
         fft_unit<T, N, false, true>(re, im, n1, ex, PW, tw, true, PAD);
         rprod<T, N, true>(make_rsrc(rspec + (int64_t)ch * N * NP, N * NP * (int)sizeof(C2)), rlane, re, im, er, ei);
     }
     const int Vz = c.V[2];
     fft_unit_rev<T, N, true>(er, ei, n1, ex, PW, tw, true, PAD);
-    {
-        // valid z-translations only: tz >= Vz lies beyond the descriptor
-        const auto rd = make_rsrc(wsi + c.off_inv, Vz * NP * (int)sizeof(C2));
-#pragma unroll
-        for (int i = 0; i < R2; ++i)
-            buf_store(rd, ((n1 + R1 * i) * NP + po) * (int)sizeof(C2), C2{er[i], ei[i]});
-    }
+    // valid z-translations only: tz >= Vz lies beyond the descriptor
+    put(er, ei, wsi + c.off_inv, Vz, 0);
     // the energy stores are issued before any occupancy work is scheduled
     __builtin_amdgcn_sched_barrier(0);
     if (OCC) {
         T re[R2], im[R2];
-#pragma unroll
-        for (int i = 0; i < HZ; ++i) {
-            re[i] = pf[i].x;
-            im[i] = pf[i].y;
-            re[i + HZ] = im[i + HZ] = (T)0;
-        }
+        take(re, im);
         if (!olong || c.Lo <= N / 2) {
             fft_unit<T, N, false, true>(re, im, n1, ex, PW, tw, true, PAD);
         } else {
@@ -923,12 +967,7 @@ void k_zprod(const CfgDev *__restrict__ cfgs, const int32_t *__restrict__ zcfg,
         rprod<T, N, false>(make_rsrc(rspec + (int64_t)3 * N * NP, N * NP * (int)sizeof(C2)), rlane, re, im, nullptr,
                            nullptr);
         fft_unit_rev<T, N, true>(re, im, n1, ex, PW, tw, true, PAD);
-        const auto rd = make_rsrc(wsi + c.off_inv + (int64_t)Vz * NP, Vz * NP * (int)sizeof(C2));
-#pragma unroll
-        for (int i = 0; i < R2; ++i) {
-            const int t = (n1 + R1 * i - c.zo0) & (N - 1);
-            buf_store(rd, (t * NP + po) * (int)sizeof(C2), C2{re[i], im[i]});
-        }
+        put(re, im, wsi + c.off_inv + (int64_t)Vz * NP, Vz, c.zo0);
     }
     } else if constexpr (!MULTI) {
     T er[R2], ei[R2];
