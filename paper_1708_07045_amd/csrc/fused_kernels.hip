@@ -286,7 +286,10 @@ __device__ __forceinline__ void clash_runs(const uint2 *__restrict__ rl, int nr,
                                            int ty, bool act, uint32_t lm, __amdgpu_buffer_rsrc_t rsrc,
                                            uint32_t *acc) {
     using D = Dil<N>;
-    constexpr int UR = W <= 1 ? 16 : (W == 2 ? 12 : (W == 3 ? 8 : 6));  // runs in flight: about 48 words
+    // runs in flight (their table words all requested before use): few, so
+    // that the kernel's 42 VGPRs let two of its wavefronts sit beside the z
+    // kernel's three on a SIMD when it runs on the second stream
+    constexpr int UR = W <= 1 ? 6 : (W == 2 ? 4 : (W == 3 ? 3 : 2));
     // phase 1: position m of the strided walk over the runs after the chords
     int m = 0;
     const int R = nr - NCH;
