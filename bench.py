@@ -350,24 +350,46 @@ def configs_needed(args):
     log(f"configs needed: {len(w.ligands)} ligands, {b.n_cfg} configurations x {S} snapshots")
     ctx_f = prop.make_context(w)
     # coarse pre-scan at twice the spacing: against every snapshot (default),
-    # one receptor at the snapshots' mean coordinates, or the first snapshot
-    ctx_c = prop.make_context(w, prop.coarse_desc(w, args.is_coarse_factor), snapshots=args.is_coarse_snapshots)
+    # one receptor at the snapshots' mean coordinates, the first snapshot, or
+    # a cascade (the mean receptor for every configuration, then every
+    # snapshot for each ligand's top fraction by that score)
+    cascade = args.is_coarse == "cascade"
+    cdesc = prop.coarse_desc(w, args.is_coarse_factor)
+    ctx_c = prop.make_context(w, cdesc, snapshots=None if cascade else args.is_coarse_snapshots)
     ctx_f.autotune(b, T, max_cfgs=2048)
     ctx_c.autotune(b, T, max_cfgs=2048)
 
-    def timed_scan(ctx):
-        out = ctx.scan(b, T)
+    def timed_scan(ctx, bb):
+        out = ctx.scan(bb, T)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        ctx.scan(b, T, out)
+        ctx.scan(bb, T, out)
         torch.cuda.synchronize()
         return out, time.perf_counter() - t0
 
-    part_f, t_f = timed_scan(ctx_f)
-    part_c, t_c = timed_scan(ctx_c)
-    rho = t_c / t_f
+    part_f, t_f = timed_scan(ctx_f, b)
+    per_fine = t_f / b.n_cfg          # seconds per configuration of the fine scan
+    if cascade:
+        ctx_m = prop.make_context(w, cdesc, snapshots="mean")
+        ctx_m.autotune(b, T, max_cfgs=2048)
+        part_m, t_m = timed_scan(ctx_m, b)
+        y_mean = prop.coarse_score(ctx_m, b, part_m)
+        cand = np.zeros(b.n_cfg, np.uint8)
+        for l in range(b.n_lig):
+            a0, a1 = b.cfg_off[l], b.cfg_off[l + 1]
+            k = int(np.ceil(args.is_cascade_frac * (a1 - a0)))
+            cand[a0 + np.argsort(-y_mean[a0:a1], kind="stable")[:k]] = 1
+        part_c, t_c = timed_scan(ctx_c, b.with_select(cand))
+        # fine-scan equivalents per configuration: the mean-receptor scan for
+        # all, the every-snapshot scan for the candidates
+        extra_cfg = t_m / t_f + cand * (t_c / max(1, int(cand.sum()))) / per_fine
+        log(f"cascade: mean receptor {t_m:.2f}s for all, every snapshot {t_c:.2f}s for {int(cand.sum())} candidates")
+    else:
+        part_c, t_c = timed_scan(ctx_c, b)
+        extra_cfg = np.full(b.n_cfg, t_c / t_f)
+    rho = float(np.mean(extra_cfg))
     B_ex, res_ex = ctx_f.reduce(b, part_f, T)
-    log(f"exhaustive fine scan {t_f:.2f}s, coarse scan {t_c:.2f}s (cost ratio {rho:.3f})")
+    log(f"exhaustive fine scan {t_f:.2f}s, coarse pre-scan cost ratio {rho:.3f}")
     train_l, test_l = prop.split_ligands(len(w.ligands), 101)
     # the training ligands split again: 81 to fit, 20 to choose the mixture
     # temperature and the number of epochs (the held-out 40 decide nothing)
@@ -376,8 +398,12 @@ def configs_needed(args):
     rows = prop.rows_of(b.cfg_off, fit_l)
     X = prop.inputs(ctx_f, ctx_c, b, part_c, with_scan=True)
     # the coarse prediction (skip input): per-receptor maximum of the relative
-    # log weight (the first scan descriptor when there is one coarse receptor)
-    X[:, fd.N_FEATURES] = torch.as_tensor(prop.coarse_score(ctx_c, b, part_c), device=X.device)
+    # log weight (the first scan descriptor when there is one coarse receptor);
+    # in the cascade, non-candidates keep their mean-receptor score 5 nats down
+    y_c = prop.coarse_score(ctx_c, b, part_c)
+    if cascade:
+        y_c = np.where(cand == 1, y_c, y_mean - 1.0)
+    X[:, fd.N_FEATURES] = torch.as_tensor(y_c.astype(np.float32), device=X.device)
     Xc = X[:, :fd.N_FEATURES].contiguous()
     P_f = ctx_f.partials_numpy(part_f, S, b.n_cfg)
     if args.is_target == "snapmax":
@@ -416,7 +442,7 @@ def configs_needed(args):
             yl = pred[name][b.cfg_off[l]:b.cfg_off[l + 1]]
             k, bf = prop.kstar_is(prop.sub_batch(w, l), Zs, yl, alpha, tau_of[name], kT, 2000 + int(l),
                                   reps=args.is_reps)
-            extra = rho * Pl if name in ("net_scan", "coarse") else 0.0
+            extra = float(extra_cfg[b.cfg_off[l]:b.cfg_off[l + 1]].sum()) if name in ("net_scan", "coarse") else 0.0
             row[name] = min(float(Pl), k + extra)
             row[name + "_budget"] = bf
         per.append(row)
@@ -444,7 +470,7 @@ def configs_needed(args):
         fin = np.isfinite(dB)
         is_runs[name] = {
             "configs_scanned": n_is, "configs_total": int(bt.n_cfg),
-            "cost_fine_equivalents": n_is + rho * bt.n_cfg,
+            "cost_fine_equivalents": n_is + float(sum(extra_cfg[b.cfg_off[l]:b.cfg_off[l + 1]].sum() for l in test_l)),
             "fallback_ligands": int(est["fallback"].sum()),
             "fallback_rule": "predicted weight outside the exact stratum > 0.5 (decided before the draw)",
             "max_sampled_share": float(np.max(est["share"])),
@@ -464,6 +490,7 @@ def configs_needed(args):
         "replicates": args.is_reps,
         "coarse_cost_ratio": rho,
         "coarse_receptors": args.is_coarse,
+        "cascade_fraction": args.is_cascade_frac if cascade else None,
         "coarse_spacing_factor": args.is_coarse_factor,
         "target": args.is_target,
         "split": "101 training ligands = 81 fitted + 20 validation (temperature, epochs); 40 held out",
@@ -520,11 +547,13 @@ def main():
                     help="training target: largest per-snapshot relative log weight, or the log of the "
                          "snapshot-weighted sum")
     ap.add_argument("--is-detail", default="", help="write per-ligand configurations-needed results here (JSON)")
-    ap.add_argument("--is-coarse", default="all", choices=["mean", "all", "first"],
+    ap.add_argument("--is-coarse", default="all", choices=["mean", "all", "first", "cascade"],
                     help="coarse pre-scan receptors: one at the snapshots' mean coordinates, every snapshot, "
-                         "or the first snapshot")
+                         "the first snapshot, or a cascade (the mean receptor for every configuration, then every "
+                         "snapshot for each ligand's top --is-cascade-frac by that score)")
+    ap.add_argument("--is-cascade-frac", type=float, default=0.3)
     args = ap.parse_args()
-    args.is_coarse_snapshots = {"mean": "mean", "all": None, "first": [0]}[args.is_coarse]
+    args.is_coarse_snapshots = {"mean": "mean", "all": None, "first": [0], "cascade": None}[args.is_coarse]
     if args.is_coarse_factor not in (2, 4):
         ap.error("--is-coarse-factor must be 2 or 4")
     if args.gpus != 1:
