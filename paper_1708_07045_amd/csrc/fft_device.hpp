@@ -190,6 +190,45 @@ __device__ __forceinline__ void fft_unit(T *re, T *im, int n1, typename Cx<T>::t
     for (int i = 0; i < M; ++i) dft_reg<R1, INV>(re + i * R1, im + i * R1);
 }
 
+// fft_unit for shapes with R1 == R2 (N = 256), twiddles from a per-lane table
+// tw2[n1 TW2S + k2] = w_N^(n1 k2) (TW2S = R2 + 1: the lanes' rows on distinct
+// banks) and the padded exchange layout: every LDS access of a lane is one
+// base address plus an immediate offset, so the routine holds two address
+// registers instead of one per element.
+template <int N>
+struct LaneTw {
+    static constexpr int S = Shape<N>::R2 + 1;     // row stride
+    static constexpr int SIZE = Shape<N>::R1 * S;  // complex entries
+};
+template <typename T, int N, bool INV>
+__device__ __forceinline__ void fft_unit_lt(T *re, T *im, int n1, typename Cx<T>::t *ex, int es,
+                                            const typename Cx<T>::t *tw2, bool live, int pad) {
+    using C2 = typename Cx<T>::t;
+    constexpr int R1 = Shape<N>::R1, R2 = Shape<N>::R2;
+    static_assert(R1 == R2, "one output slot per lane and k1");
+    dft_reg<R2, INV, T>(re, im);
+    const C2 *tr = tw2 + n1 * LaneTw<N>::S;
+#pragma unroll
+    for (int k2 = 1; k2 < R2; ++k2) cmul_tw(re[k2], im[k2], tr[k2], INV);
+    wave_sync();  // the exchange area may still be read by a previous step
+    if (live) {
+        C2 *w = ex + n1 * es;  // element k2 R1 + n1 of block k2
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) w[k2 * (R1 * es + pad)] = C2{re[k2], im[k2]};
+    }
+    wave_sync();
+    if (live) {
+        const C2 *r = ex + n1 * (R1 * es + pad);  // block n1
+#pragma unroll
+        for (int a = 0; a < R1; ++a) {
+            const C2 v = r[a * es];
+            re[a] = v.x;
+            im[a] = v.y;
+        }
+    }
+    dft_reg<R1, INV>(re, im);
+}
+
 // Reverse of fft_unit's layouts: input in the spectral layout (lane j holds
 // X[R2*k1 + j*M + i] in slot i*R1 + k1), output natural (lane n1 holds
 // x[n1 + R1*n2] in slot n2).  Same transform definition as fft_unit.

@@ -293,8 +293,8 @@ struct LseAcc {
 // Workgroup reduction of the per-thread partials in a fixed tree: a
 // butterfly over the lanes of each wavefront (shuffles, no barrier), then
 // thread 0 merges the wavefronts' results in order and stores the plane
-// partial.  red holds one entry per wavefront.
-template <typename T>
+// partial.  red holds one entry per wavefront of the NTH-thread workgroup.
+template <typename T, int NTH = NT>
 __device__ __forceinline__ void block_partial_store(LseAcc<T> a, LseAcc<T> *red, PlanePartial<T> *out) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -310,7 +310,7 @@ __device__ __forceinline__ void block_partial_store(LseAcc<T> a, LseAcc<T> *red,
     __syncthreads();
     if (threadIdx.x == 0) {
         LseAcc<T> r = red[0];
-        for (int w = 1; w < NT / 64; ++w) r.merge(red[w]);
+        for (int w = 1; w < NTH / 64; ++w) r.merge(red[w]);
         PlanePartial<T> o;
         o.m = r.m;
         o.s = r.s;
@@ -377,19 +377,27 @@ __device__ __forceinline__ uint32_t row_pair_epilogue(T *re, T *im, int n1, int 
     }
     const uint32_t use = vb & ~(OCC ? clash : 0u);
     if (use == 0u) return 0u;
-    // minimum psi (its -beta multiple is the maximum of the exponents)
+    // minimum psi (its -beta multiple is the maximum of the exponents): the
+    // first minimum in (h, x) order, which is the order of the linear index,
+    // so the lowest index among equal minima; the index is formed once
+    constexpr int M = R2 / R1;
     T pm = (T)INFINITY;
-    int am = 0x7fffffff;
+    int best = -1;  // flag bit 2 sl + h of the minimum
 #pragma unroll
-    for (int sl = 0; sl < R2; ++sl)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const T v = h ? im[sl] : re[sl];
-            const int lin = (tz * Vy + y + h) * Vx + spec_index<N>(n1, sl / R1, sl % R1);
-            const bool better = ((use >> (2 * sl + h)) & 1u) && (v < pm || (v == pm && lin < am));
-            pm = better ? v : pm;
-            am = better ? lin : am;
-        }
+        for (int k1 = 0; k1 < R1; ++k1)
+#pragma unroll
+            for (int i = 0; i < M; ++i) {
+                const int sl = i * R1 + k1;  // x = spec_index(n1, i, k1), increasing in (k1, i)
+                const T v = h ? im[sl] : re[sl];
+                const bool better = ((use >> (2 * sl + h)) & 1u) && (v < pm || (best < 0 && v == pm));
+                pm = better ? v : pm;
+                best = better ? 2 * sl + h : best;
+            }
+    const int sb = best >> 1;
+    const int am = best < 0 ? 0x7fffffff
+                            : (tz * Vy + y + (best & 1)) * Vx + spec_index<N>(n1, sb / R1, sb % R1);
     const T ml = -beta * pm;
     T sm = (T)0;
 #pragma unroll

@@ -1578,6 +1578,205 @@ __global__ __launch_bounds__(NT) void k_inv_rows_lse(const int32_t *__restrict__
     block_partial_store(acc, red, pp + c.pp_base + tz);
 }
 
+// A copy of v the compiler cannot see through: index arithmetic derived from
+// it is recomputed where it is used instead of being hoisted out of loops and
+// held in registers across the whole kernel.
+__device__ __forceinline__ int opaque(int v) {
+    asm volatile("" : "+v"(v));
+    return v;
+}
+
+// Whole-plane inverse xy for the split-plane grid: one workgroup of WT = 1024
+// threads (64 FFT units of R1 = 16 lanes) per (configuration, valid z), so
+// each plane is read from device memory once and nothing is written back.
+// Inverse y: columns kx = 1 .. N/2-1 of the half spectrum, and columns 0 and
+// N/2 packed as one complex column (both transform to real rows: Re and Im
+// of the packed result), N/2 columns in all, staged through LDS in batches of
+// 64 by coalesced row reads; each unit reads one column into registers,
+// transforms it in a private region of the tile and keeps its outputs, rows
+// y = R1 k1 + n1, in registers.  Inverse x (C2R): rows y < Vy are transposed
+// through LDS 128 at a time and each unit transforms one row pair (y, y + 1)
+// packed as one complex row, its two tile rows doubling as its exchange
+// area; then the clash bits, energies and partial as k_inv_rows_lse.
+template <bool B>
+struct BoolTag {
+    static constexpr bool value = B;
+};
+
+template <typename T, int N>
+struct Whole {
+    static constexpr int WT = 1024;
+    static constexpr int R1 = Shape<N>::R1, R2 = Shape<N>::R2;
+    static constexpr int U = WT / R1;            // units
+    static constexpr int H = N / 2 + 1, NP = N * H;
+    static constexpr int NHALF = (N / 2) / U;    // column batches of U packed columns
+    static constexpr int NRND = N / (2 * U);     // row batches of 2U rows
+    static constexpr int KR = R2 / NRND;         // output slots per row batch
+    static constexpr int XP = 1;                 // exchange pad per block of R2
+    static constexpr int XR = N + R1 * XP;       // exchange region (complex)
+    // LDS row strides (complex): the strided column reads (TSA) and the
+    // transposing writes (TSB) spread a wavefront's lanes over the banks
+    static constexpr int TSA = U + 4, TSB = N / 2 + 9;
+    static constexpr int TA = N * TSA > U * XR ? N * TSA : U * XR;
+    static constexpr int TILE = TA > 2 * U * TSB ? TA : 2 * U * TSB;
+    static_assert(Shape<N>::R2 == Shape<N>::R1, "one output slot per k1");
+    static_assert(NHALF * U == N / 2 && NRND * 2 * U == N && KR * NRND == R2, "tiling");
+    static_assert(2 * TSB >= XR, "a row pair holds its exchange area");
+};
+
+template <typename T, int N, bool OCC>
+__global__ __launch_bounds__(1024) void k_inv_plane(const int32_t *__restrict__ inv_off, int n_cfg,
+                                                    const CfgDev *__restrict__ cfgs,
+                                                    const typename Cx<T>::t *__restrict__ wsi, T beta, T inv_n3,
+                                                    const typename Cx<T>::t *__restrict__ twg,
+                                                    PlanePartial<T> *__restrict__ pp, T *__restrict__ psi_out,
+                                                    uint8_t *__restrict__ clash_out,
+                                                    unsigned int *__restrict__ e_count) {
+    using C2 = typename Cx<T>::t;
+    using W = Whole<T, N>;
+    constexpr int R1 = W::R1, R2 = W::R2, U = W::U, H = W::H, WT = W::WT;
+    constexpr int NHALF = W::NHALF, NRND = W::NRND, KR = W::KR, TSA = W::TSA, TSB = W::TSB;
+    static_assert(WT == 1024, "launch bounds");
+    __shared__ C2 tile[W::TILE];
+    __shared__ C2 tw2[LaneTw<N>::SIZE];
+    __shared__ LseAcc<T> red[WT / 64];
+    const int ic = find_cfg(inv_off, n_cfg, (int)blockIdx.x);
+    const CfgDev c = cfgs[ic];
+    const int Vx = c.V[0], Vy = c.V[1], Vz = c.V[2], tz = (int)blockIdx.x - inv_off[ic];
+    if (threadIdx.x < R1 * R2) {  // tw2[n1 S + k2] = w_N^(n1 k2)
+        const int a = (int)threadIdx.x / R2, k2 = (int)threadIdx.x % R2;
+        tw2[a * LaneTw<N>::S + k2] = twg[a * k2];
+    }
+    const int unit = threadIdx.x / R1, n1 = threadIdx.x % R1;
+    LseAcc<T> acc;
+    acc.init();
+    int any_free = 0;
+    uint32_t cw[NRND];
+#pragma unroll
+    for (int r = 0; r < NRND; ++r) cw[r] = 0u;
+    // one channel of the plane: the occupancy pass (clash bits) or the energies
+    auto channel = [&](auto occ_tag) {
+        constexpr bool OCC_PASS = decltype(occ_tag)::value;
+        const int och = OCC_PASS ? 1 : 0;
+        const C2 *src = wsi + c.off_inv + ((int64_t)och * Vz + tz) * W::NP;
+        if (!OCC_PASS && threadIdx.x == 0 && e_count) atomicAdd(e_count, 1u);
+        // inverse y: column batch hb holds packed columns hb U .. hb U + U - 1
+        const __amdgpu_buffer_rsrc_t rs = make_rsrc(src, W::NP * (int)sizeof(C2));
+        T cr[NHALF][R2], ci[NHALF][R2];
+#pragma unroll
+        for (int hb = 0; hb < NHALF; ++hb) {
+            // wavefront w stages rows w + (WT/U) j, one row segment of U columns per load
+            constexpr int RS = WT / U, NJ = N / RS;
+            const int r0 = (int)threadIdx.x / U, cc = (int)threadIdx.x % U;
+            const int voff = (r0 * H + hb * U + cc) * (int)sizeof(C2);
+            C2 v[NJ];
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) v[j] = buf_load(rs, voff, j * RS * H * (int)sizeof(C2), (C2 *)nullptr);
+            // column N/2, packed into column 0 as its imaginary part: row t by thread t
+            C2 q = C2{(T)0, (T)0};
+            if (hb == 0 && threadIdx.x < N) q = buf_load(rs, ((int)threadIdx.x * H + N / 2) * (int)sizeof(C2), (C2 *)nullptr);
+            __syncthreads();  // the tile's previous readers are done
+#pragma unroll
+            for (int j = 0; j < NJ; ++j) tile[(r0 + RS * j) * TSA + cc] = v[j];
+            __syncthreads();
+            if (hb == 0 && threadIdx.x < N) {
+                C2 &t0 = tile[threadIdx.x * TSA];
+                t0 = C2{t0.x - q.y, t0.y + q.x};
+            }
+            if (hb == 0) __syncthreads();
+            const int m1 = opaque(n1) & (R1 - 1);
+            T re[R2], im[R2];
+            {
+                const C2 *colp = tile + unit + m1 * TSA;
+#pragma unroll
+                for (int i = 0; i < R2; ++i) {
+                    const C2 x = colp[R1 * TSA * i];
+                    re[i] = x.x;
+                    im[i] = x.y;
+                }
+            }
+            __syncthreads();  // every column is in registers: the tile becomes the units' exchange regions
+            fft_unit_lt<T, N, true>(re, im, m1, tile + unit * W::XR, 1, tw2, true, W::XP);
+#pragma unroll
+            for (int k1 = 0; k1 < R2; ++k1) {  // row y = R1 k1 + n1 of column hb U + unit
+                cr[hb][k1] = re[k1];
+                ci[hb][k1] = im[k1];
+            }
+        }
+        // inverse x: row batch rd holds rows rd 2U .. rd 2U + 2U - 1.  The
+        // next batch is written to the tile as soon as this batch's
+        // transforms are done with it, before the epilogue, so its registers
+        // are free while the epilogue runs.
+        auto put = [&](int rd) {  // the outputs of row batch rd into the tile
+            C2 *wp = tile + (opaque(n1) & (R1 - 1)) * TSB + unit;
+#pragma unroll
+            for (int hb = 0; hb < NHALF; ++hb)
+#pragma unroll
+                for (int kk = 0; kk < KR; ++kk)
+                    wp[R1 * TSB * kk + hb * U] = C2{cr[hb][rd * KR + kk], ci[hb][rd * KR + kk]};
+        };
+        __syncthreads();  // the tile's previous readers are done
+        put(0);
+        __syncthreads();
+#pragma unroll
+        for (int rd = 0; rd < NRND; ++rd) {
+            const int y0 = rd * 2 * U;
+            if (y0 >= Vy) break;  // block-uniform
+            const int y = y0 + 2 * unit;
+            const bool live = y < Vy, has_b = y + 1 < Vy;
+            C2 *ra = tile + (2 * unit) * TSB, *rb = ra + TSB;
+            const int m1 = opaque(n1) & (R1 - 1);
+            T re[R2], im[R2];
+#pragma unroll
+            for (int i = 0; i < R2; ++i) {
+                const int k = m1 + R1 * i;
+                // rows past Vy hold stale tile data: transformed, never used
+                C2 a, bq;
+                if (k == 0 || k == N / 2) {  // the packed column: Re at x-frequency 0, Im at N/2
+                    const C2 p = ra[0], q = rb[0];
+                    a = C2{k == 0 ? p.x : p.y, (T)0};
+                    bq = C2{k == 0 ? q.x : q.y, (T)0};
+                } else if (k < N / 2) {
+                    a = ra[k];
+                    bq = rb[k];
+                } else {
+                    a = ra[N - k];
+                    bq = rb[N - k];
+                    a.y = -a.y;
+                    bq.y = -bq.y;
+                }
+                if (!has_b) bq = C2{(T)0, (T)0};
+                re[i] = a.x - bq.y;
+                im[i] = a.y + bq.x;
+            }
+            fft_unit_lt<T, N, true>(re, im, m1, ra, 1, tw2, true, W::XP);
+            if (rd + 1 < NRND && y0 + 2 * U < Vy) {  // block-uniform
+                __syncthreads();  // every unit is done with this batch's rows
+                put(rd + 1);
+                __syncthreads();
+            }
+            if (live) {
+                uint32_t vb;
+                const uint32_t f = row_pair_epilogue<T, N, OCC>(re, im, m1, y, Vx, Vy, tz, OCC_PASS,
+                                                                (OCC && !OCC_PASS) ? cw[rd] : 0u, inv_n3, beta,
+                                                                psi_out, clash_out, acc, vb);
+                if (OCC_PASS) {
+                    cw[rd] = f;
+                    any_free |= (vb & ~f) != 0u;
+                }
+            }
+        }
+    };
+    if constexpr (OCC) {
+        channel(BoolTag<true>{});
+        // the energies only where some translation is clash-free (always when exporting)
+        if (psi_out || __syncthreads_or(any_free)) channel(BoolTag<false>{});
+    } else {
+        channel(BoolTag<false>{});
+    }
+    block_partial_store<T, WT>(acc, red, pp + c.pp_base + tz);
+}
+
 // Per-configuration descriptors of a finished scan (inputs of the learned
 // proposal), one block per ligand, FP64:
 //   x_c   = ln sum_s W_s Z_{c,s}            (Eq. 2 numerator of one configuration)
@@ -1988,19 +2187,14 @@ struct LaunchSplit {
                           uint8_t *clash_out, unsigned int *e_count) {
         if (n_items <= 0) return hipSuccess;
         const T b = (T)beta, s = (T)(1.0 / ((double)N * N * N));
-        if (occ) {
-            hipLaunchKernelGGL((k_inv_cols<T, N, true>), dim3(n_items * 2 * Tile<T, N>::NTILE), dim3(NT), 0, st,
-                               inv_off, n_cfg, cfgs, (C2 *)wsi, (const C2 *)tw);
-            hipLaunchKernelGGL((k_inv_rows_lse<T, N, true>), dim3(n_items), dim3(NT), 0, st, inv_off, n_cfg, cfgs,
-                               (const C2 *)wsi, b, s, (const C2 *)tw, (PlanePartial<T> *)pp, (T *)psi_out, clash_out,
-                               e_count);
-        } else {
-            hipLaunchKernelGGL((k_inv_cols<T, N, false>), dim3(n_items * Tile<T, N>::NTILE), dim3(NT), 0, st,
-                               inv_off, n_cfg, cfgs, (C2 *)wsi, (const C2 *)tw);
-            hipLaunchKernelGGL((k_inv_rows_lse<T, N, false>), dim3(n_items), dim3(NT), 0, st, inv_off, n_cfg, cfgs,
-                               (const C2 *)wsi, b, s, (const C2 *)tw, (PlanePartial<T> *)pp, (T *)psi_out, clash_out,
-                               e_count);
-        }
+        if (occ)
+            hipLaunchKernelGGL((k_inv_plane<T, N, true>), dim3(n_items), dim3(Whole<T, N>::WT), 0, st, inv_off, n_cfg,
+                               cfgs, (const C2 *)wsi, b, s, (const C2 *)tw, (PlanePartial<T> *)pp, (T *)psi_out,
+                               clash_out, e_count);
+        else
+            hipLaunchKernelGGL((k_inv_plane<T, N, false>), dim3(n_items), dim3(Whole<T, N>::WT), 0, st, inv_off, n_cfg,
+                               cfgs, (const C2 *)wsi, b, s, (const C2 *)tw, (PlanePartial<T> *)pp, (T *)psi_out,
+                               clash_out, e_count);
         return hipGetLastError();
     }
 };
