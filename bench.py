@@ -355,7 +355,10 @@ def configs_needed(args):
     # snapshot for each ligand's top fraction by that score)
     cascade = args.is_coarse == "cascade"
     cdesc = prop.coarse_desc(w, args.is_coarse_factor)
-    ctx_c = prop.make_context(w, cdesc, snapshots=None if cascade else args.is_coarse_snapshots)
+    csnaps = None if cascade else args.is_coarse_snapshots
+    if csnaps == "half":
+        csnaps = list(range(0, S, 2))
+    ctx_c = prop.make_context(w, cdesc, snapshots=csnaps, clash_mode=args.is_coarse_clash)
     ctx_f.autotune(b, T, max_cfgs=2048)
     ctx_c.autotune(b, T, max_cfgs=2048)
 
@@ -370,7 +373,7 @@ def configs_needed(args):
     part_f, t_f = timed_scan(ctx_f, b)
     per_fine = t_f / b.n_cfg          # seconds per configuration of the fine scan
     if cascade:
-        ctx_m = prop.make_context(w, cdesc, snapshots="mean")
+        ctx_m = prop.make_context(w, cdesc, snapshots="mean", clash_mode=args.is_coarse_clash)
         ctx_m.autotune(b, T, max_cfgs=2048)
         part_m, t_m = timed_scan(ctx_m, b)
         y_mean = prop.coarse_score(ctx_m, b, part_m)
@@ -492,6 +495,7 @@ def configs_needed(args):
         "coarse_receptors": args.is_coarse,
         "cascade_fraction": args.is_cascade_frac if cascade else None,
         "coarse_spacing_factor": args.is_coarse_factor,
+        "coarse_clash_mode": args.is_coarse_clash,
         "target": args.is_target,
         "split": "101 training ligands = 81 fitted + 20 validation (temperature, epochs); 40 held out",
         "mixture_alpha": alpha,
@@ -547,13 +551,17 @@ def main():
                     help="training target: largest per-snapshot relative log weight, or the log of the "
                          "snapshot-weighted sum")
     ap.add_argument("--is-detail", default="", help="write per-ligand configurations-needed results here (JSON)")
-    ap.add_argument("--is-coarse", default="all", choices=["mean", "all", "first", "cascade"],
+    ap.add_argument("--is-coarse", default="all", choices=["mean", "all", "half", "first", "cascade"],
                     help="coarse pre-scan receptors: one at the snapshots' mean coordinates, every snapshot, "
-                         "the first snapshot, or a cascade (the mean receptor for every configuration, then every "
+                         "every other snapshot, the first snapshot, or a cascade (the mean receptor for every configuration, then every "
                          "snapshot for each ligand's top --is-cascade-frac by that score)")
     ap.add_argument("--is-cascade-frac", type=float, default=0.3)
+    ap.add_argument("--is-coarse-clash", default="occ", choices=["occ", "cap"],
+                    help="clash handling of the coarse pre-scan: occupancy exclusion (as the fine scan) or "
+                         "capped repulsion (one inverse channel)")
     args = ap.parse_args()
-    args.is_coarse_snapshots = {"mean": "mean", "all": None, "first": [0], "cascade": None}[args.is_coarse]
+    args.is_coarse_snapshots = {"mean": "mean", "all": None, "half": "half", "first": [0],
+                                "cascade": None}[args.is_coarse]
     if args.is_coarse_factor not in (2, 4):
         ap.error("--is-coarse-factor must be 2 or 4")
     if args.gpus != 1:

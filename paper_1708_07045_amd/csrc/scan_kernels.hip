@@ -1467,117 +1467,6 @@ __global__ __launch_bounds__(NT) void k_reduce(const fftdg_partial *__restrict__
     }
 }
 
-// Split-plane inverse, column pass (one block per (configuration, valid z)):
-// inverse y transform of every column kx in [0, N/2] of the energy and
-// occupancy planes, rows y < Vy written back in place.
-template <typename T, int N, bool OCC>
-__global__ __launch_bounds__(NT) void k_inv_cols(const int32_t *__restrict__ inv_off, int n_cfg,
-                                                  const CfgDev *__restrict__ cfgs,
-                                                  typename Cx<T>::t *__restrict__ wsi,
-                                                  const typename Cx<T>::t *__restrict__ twg) {
-    using C2 = typename Cx<T>::t;
-    using TL = Tile<T, N>;
-    __shared__ C2 tb[N * TL::TS];
-    __shared__ C2 tw[N];
-    constexpr int NCH = OCC ? 2 : 1;
-    const int per = NCH * TL::NTILE;
-    const int lb = xcd_block((int)blockIdx.x, (int)gridDim.x);
-    const int bi = lb / per, rem = lb % per;
-    const int och = rem / TL::NTILE, tile = rem % TL::NTILE;
-    const int ic = find_cfg(inv_off, n_cfg, bi);
-    const CfgDev c = cfgs[ic];
-    const int Vy = c.V[1], Vz = c.V[2], tz = bi - inv_off[ic];
-    load_tw<T, N>(tw, twg);
-    cols_tile<T, N, true>(wsi + c.off_inv + ((int64_t)och * Vz + tz) * Geo<T, N>::NP, tile, 0, N, Vy, tb, tw);
-}
-
-// Split-plane inverse, row pass: inverse x (C2R) of the row pairs y < Vy of
-// the planes left by k_inv_cols, clash bits from the occupancy plane, then
-// the energies and the max-shifted log-sum-exp partial of the plane (as
-// k_inv_xy_lse).
-template <typename T, int N, bool OCC>
-__global__ __launch_bounds__(NT) void k_inv_rows_lse(const int32_t *__restrict__ inv_off, int n_cfg,
-                                                      const CfgDev *__restrict__ cfgs,
-                                                      const typename Cx<T>::t *__restrict__ wsi, T beta, T inv_n3,
-                                                      const typename Cx<T>::t *__restrict__ twg,
-                                                      PlanePartial<T> *__restrict__ pp, T *__restrict__ psi_out,
-                                                      uint8_t *__restrict__ clash_out,
-                                                      unsigned int *__restrict__ e_count) {
-    using C2 = typename Cx<T>::t;
-    using SG = Split<T, N>;
-    constexpr int R1 = SG::R1, R2 = SG::R2, U = SG::U, H = SG::H;
-    __shared__ C2 reg_all[SG::U * SG::XREG];
-    __shared__ C2 tw[N];
-    constexpr int MAXR = (N / 2 + U - 1) / U;  // rounds of row pairs
-    __shared__ uint32_t cflags[MAXR * NT];     // per thread and round: clash flags of its outputs
-    __shared__ LseAcc<T> red[NT / 64];
-    const int ic = find_cfg(inv_off, n_cfg, (int)blockIdx.x);
-    const CfgDev c = cfgs[ic];
-    const int Vx = c.V[0], Vy = c.V[1], Vz = c.V[2], tz = (int)blockIdx.x - inv_off[ic];
-    load_tw<T, N>(tw, twg);
-    const int unit = threadIdx.x / R1, n1 = threadIdx.x % R1;
-    C2 *reg = reg_all + unit * SG::XREG;
-    LseAcc<T> acc;
-    acc.init();
-    int any_free = 0;
-    constexpr int NCH = OCC ? 2 : 1;
-    for (int pass = 0; pass < NCH; ++pass) {
-        const int och = OCC ? 1 - pass : 0;  // occupancy first
-        const C2 *src = wsi + c.off_inv + ((int64_t)och * Vz + tz) * SG::NP;
-        __syncthreads();
-        if (OCC && och == 0 && !psi_out) {
-            if (!__syncthreads_or(any_free)) break;
-        }
-        if (och == 0 && threadIdx.x == 0 && e_count) atomicAdd(e_count, 1u);
-        const int npairs = (Vy + 1) / 2;
-        for (int rd = 0; rd < (npairs + U - 1) / U; ++rd) {
-            const int y = 2 * (unit + U * rd);
-            const bool live = y < Vy;
-            const bool has_b = y + 1 < Vy;
-            const C2 *ra = src + (int64_t)(live ? y : 0) * H;
-            const C2 *rb = src + (int64_t)(has_b ? y + 1 : 0) * H;
-            T re[R2], im[R2];
-#pragma unroll
-            for (int i = 0; i < R2; ++i) {
-                const int k = n1 + R1 * i;
-                re[i] = im[i] = (T)0;
-                if (live) {
-                    C2 a, bq = C2{(T)0, (T)0};
-                    if (k <= N / 2) {
-                        a = ra[k];
-                        if (has_b) bq = rb[k];
-                        if (k == 0 || k == N / 2) {
-                            a.y = (T)0;
-                            bq.y = (T)0;
-                        }
-                    } else {
-                        a = ra[N - k];
-                        if (has_b) bq = rb[N - k];
-                        a.y = -a.y;
-                        bq.y = -bq.y;
-                    }
-                    re[i] = a.x - bq.y;
-                    im[i] = a.y + bq.x;
-                }
-            }
-            fft_unit<T, N, true>(re, im, n1, reg, 1, tw, live, SG::XPAD);
-            if (live) {
-                uint32_t &cw = cflags[rd * NT + threadIdx.x];  // written and read by this thread only
-                uint32_t vb;
-                const uint32_t f = row_pair_epilogue<T, N, OCC>(re, im, n1, y, Vx, Vy, tz, OCC && och == 1,
-                                                                (OCC && och == 0) ? cw : 0u, inv_n3, beta, psi_out,
-                                                                clash_out, acc, vb);
-                if (OCC && och == 1) {
-                    cw = f;
-                    any_free |= (vb & ~f) != 0u;
-                }
-            }
-            wave_sync();
-        }
-    }
-    block_partial_store(acc, red, pp + c.pp_base + tz);
-}
-
 // A copy of v the compiler cannot see through: index arithmetic derived from
 // it is recomputed where it is used instead of being hoisted out of loops and
 // held in registers across the whole kernel.
@@ -1597,7 +1486,7 @@ __device__ __forceinline__ int opaque(int v) {
 // y = R1 k1 + n1, in registers.  Inverse x (C2R): rows y < Vy are transposed
 // through LDS 128 at a time and each unit transforms one row pair (y, y + 1)
 // packed as one complex row, its two tile rows doubling as its exchange
-// area; then the clash bits, energies and partial as k_inv_rows_lse.
+// area; then the clash bits, energies and partial as k_inv_xy_lse.
 template <bool B>
 struct BoolTag {
     static constexpr bool value = B;

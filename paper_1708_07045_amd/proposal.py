@@ -49,15 +49,19 @@ def coarse_desc(w, factor: int = 2) -> dict:
     return dict(n_rec=n_rec, n_fft=w.n_fft // factor, h=h, origin=centre - 0.5 * (n_rec - 1) * h)
 
 
-def make_context(w, grid: Optional[dict] = None, device: int = 0, snapshots=None):
+def make_context(w, grid: Optional[dict] = None, device: int = 0, snapshots=None,
+                 clash_mode: Optional[str] = None):
     """Context with receptor grids of every snapshot (or of the listed ones,
     equally weighted; or, with snapshots == "mean", of one receptor at the
-    snapshots' mean atom coordinates) built and set."""
+    snapshots' mean atom coordinates) built and set.  clash_mode overrides
+    the workload's (a coarse pre-scan may cap the repulsion instead of
+    excluding overlaps: one inverse channel instead of two)."""
     import torch
     g = dict(n_rec=w.n_rec, n_fft=w.n_fft, h=w.h, origin=w.origin)
     if grid:
         g.update(grid)
-    ctx = fd.FFTDG(g["n_rec"], g["n_fft"], g["h"], g["origin"], w.precision, w.clash_mode, w.ljr_cap, w.occ_f,
+    mode = clash_mode or w.clash_mode
+    ctx = fd.FFTDG(g["n_rec"], g["n_fft"], g["h"], g["origin"], w.precision, mode, w.ljr_cap, w.occ_f,
                    device)
     if isinstance(snapshots, str) and snapshots == "mean":
         structures = [np.mean(np.asarray(w.receptor.xyz, np.float64), axis=0)]
@@ -72,7 +76,7 @@ def make_context(w, grid: Optional[dict] = None, device: int = 0, snapshots=None
         gl.append(gg)
         ol.append(oo)
     grids = torch.stack(gl).contiguous()
-    occ = torch.stack(ol).contiguous() if w.clash_mode == "occ" else None
+    occ = torch.stack(ol).contiguous() if mode == "occ" else None
     ctx.set_receptors(grids, occ, wts)
     ctx._grids = (grids, occ)
     return ctx
