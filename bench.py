@@ -350,9 +350,10 @@ def configs_needed(args):
     log(f"configs needed: {len(w.ligands)} ligands, {b.n_cfg} configurations x {S} snapshots")
     ctx_f = prop.make_context(w)
     # coarse pre-scan at twice the spacing: against every snapshot (default),
-    # one receptor at the snapshots' mean coordinates, the first snapshot, or
-    # a cascade (the mean receptor for every configuration, then every
-    # snapshot for each ligand's top fraction by that score)
+    # one receptor at the snapshots' mean coordinates, every other snapshot,
+    # the first snapshot, or a cascade (the mean receptor for every
+    # configuration, then every snapshot for each ligand's top fraction by
+    # that score); repulsion capped (default) or overlaps excluded
     cascade = args.is_coarse == "cascade"
     cdesc = prop.coarse_desc(w, args.is_coarse_factor)
     csnaps = None if cascade else args.is_coarse_snapshots
@@ -556,9 +557,9 @@ def main():
                          "every other snapshot, the first snapshot, or a cascade (the mean receptor for every configuration, then every "
                          "snapshot for each ligand's top --is-cascade-frac by that score)")
     ap.add_argument("--is-cascade-frac", type=float, default=0.3)
-    ap.add_argument("--is-coarse-clash", default="occ", choices=["occ", "cap"],
-                    help="clash handling of the coarse pre-scan: occupancy exclusion (as the fine scan) or "
-                         "capped repulsion (one inverse channel)")
+    ap.add_argument("--is-coarse-clash", default="cap", choices=["occ", "cap"],
+                    help="clash handling of the coarse pre-scan: capped repulsion (one inverse channel; default) "
+                         "or occupancy exclusion (as the fine scan)")
     args = ap.parse_args()
     args.is_coarse_snapshots = {"mean": "mean", "all": None, "half": "half", "first": [0],
                                 "cascade": None}[args.is_coarse]
