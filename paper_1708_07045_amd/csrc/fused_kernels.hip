@@ -812,8 +812,14 @@ __global__ __launch_bounds__(NT) void k_zplanes(const CfgDev *__restrict__ cfgs,
 // packed columns, C2R along x on row pairs, Eq. 2 partial over the
 // clash-free translations.  CLASH: free bits from k_clash; a plane without
 // any is not read (its partial is empty) unless energies are exported.
-template <typename T, int N, bool CLASH>
-__global__ __launch_bounds__(NT) void k_inv_fused(const int32_t *__restrict__ inv_off, int n_cfg,
+// WT threads per plane (N = 128: 512, 64 units with one packed column and
+// one row pair each, two planes per CU at 4 wavefronts per SIMD).
+template <int N>
+__host__ __device__ constexpr int inv_fused_threads() {
+    return N == 128 ? 512 : NT;
+}
+template <typename T, int N, bool CLASH, int WT = inv_fused_threads<N>()>
+__global__ __launch_bounds__(WT, WT == 512 ? 4 : 1) void k_inv_fused(const int32_t *__restrict__ inv_off, int n_cfg,
                                                    const CfgDev *__restrict__ cfgs,
                                                    const typename Cx<T>::t *__restrict__ wsi, T beta, T inv_n3,
                                                    const typename Cx<T>::t *__restrict__ twg,
@@ -823,12 +829,12 @@ __global__ __launch_bounds__(NT) void k_inv_fused(const int32_t *__restrict__ in
                                                    unsigned int *__restrict__ e_count) {
     using C2 = typename Cx<T>::t;
     using G = Geo<T, N>;
-    constexpr int R1 = G::R1, R2 = G::R2, M = G::M, S = G::S, U = G::U, NP = G::NP;
+    constexpr int R1 = G::R1, R2 = G::R2, M = G::M, S = G::S, U = WT / R1, NP = G::NP;
     constexpr int NW = N / 32;
     static_assert(N + (R1 - 1) * G::RPAD <= 2 * S, "row-pair exchange must fit in two rows");
     __shared__ C2 Pl[N * S];
     __shared__ C2 tw[N];
-    __shared__ LseAcc<T> red[NT / 64];
+    __shared__ LseAcc<T> red[WT / 64];
     const int ic = find_cfg(inv_off, n_cfg, (int)blockIdx.x);
     const CfgDev c = cfgs[ic];
     const int Vx = c.V[0], Vy = c.V[1], tz = (int)blockIdx.x - inv_off[ic];
@@ -856,7 +862,7 @@ __global__ __launch_bounds__(NT) void k_inv_fused(const int32_t *__restrict__ in
     load_tw<T, N>(tw, twg);
     const int unit = threadIdx.x / R1, n1 = threadIdx.x % R1;
     const C2 *src = wsi + c.off_inv + (int64_t)tz * NP;
-    plane_copy<T, N, true>(Pl, const_cast<C2 *>(src));
+    plane_copy<T, N, true, WT>(Pl, const_cast<C2 *>(src));
     __syncthreads();
     T re[R2], im[R2];
     // inverse y on columns (kx = 0 and N/2 packed into column 0), keep y < Vy
@@ -955,7 +961,7 @@ __global__ __launch_bounds__(NT) void k_inv_fused(const int32_t *__restrict__ in
                                                 clash_out, acc, vb);
         }
     }
-    block_partial_store(acc, red, pp + c.pp_base + tz);
+    block_partial_store<T, WT>(acc, red, pp + c.pp_base + tz);
 }
 
 // ------------------------------------------------------------ launchers
@@ -1049,11 +1055,13 @@ struct LaunchFused {
         if (n_items <= 0) return hipSuccess;
         const T b = (T)beta, s = (T)(1.0 / ((double)N * N * N));
         if (clash)
-            hipLaunchKernelGGL((k_inv_fused<T, N, true>), dim3(n_items), dim3(NT), 0, st, inv_off, n_cfg, cfgs,
+            hipLaunchKernelGGL((k_inv_fused<T, N, true>), dim3(n_items), dim3(inv_fused_threads<N>()), 0, st, inv_off,
+                               n_cfg, cfgs,
                                (const C2 *)wsi, b, s, (const C2 *)tw, fb, live, (PlanePartial<T> *)pp, (T *)psi_out,
                                clash_out, e_count);
         else
-            hipLaunchKernelGGL((k_inv_fused<T, N, false>), dim3(n_items), dim3(NT), 0, st, inv_off, n_cfg, cfgs,
+            hipLaunchKernelGGL((k_inv_fused<T, N, false>), dim3(n_items), dim3(inv_fused_threads<N>()), 0, st, inv_off,
+                               n_cfg, cfgs,
                                (const C2 *)wsi, b, s, (const C2 *)tw, fb, live, (PlanePartial<T> *)pp, (T *)psi_out,
                                clash_out, e_count);
         return hipGetLastError();

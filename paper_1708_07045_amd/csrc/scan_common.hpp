@@ -150,13 +150,14 @@ __device__ __forceinline__ void buf_store(__amdgpu_buffer_rsrc_t r, int off, dou
 // layout [N][S].  Elements travel in aligned pairs (16 B for FP32) and every
 // load of a thread is issued before the first LDS store, so a plane costs
 // one memory round trip instead of one per element.  g must be 16-byte
-// aligned for FP32 (planes start at multiples of NP, which is even).
-template <typename T, int N, bool TO_LDS>
+// aligned for FP32 (planes start at multiples of NP, which is even).  NTH
+// threads take part.
+template <typename T, int N, bool TO_LDS, int NTH = NT>
 __device__ __forceinline__ void plane_copy(typename Cx<T>::t *Pl, typename Cx<T>::t *g) {
     using C2 = typename Cx<T>::t;
     constexpr int H = N / 2 + 1, S = Geo<T, N>::S, NP = N * H;
     constexpr int NPAIR = NP / 2;
-    constexpr int PER = (NPAIR + NT - 1) / NT;
+    constexpr int PER = (NPAIR + NTH - 1) / NTH;
     struct alignas(2 * sizeof(C2)) Pair {
         C2 a, b;
     };
@@ -164,17 +165,17 @@ __device__ __forceinline__ void plane_copy(typename Cx<T>::t *Pl, typename Cx<T>
     if (TO_LDS) {
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            const int q = threadIdx.x + j * NT;
+            const int q = threadIdx.x + j * NTH;
             if (q < NPAIR) v[j] = reinterpret_cast<const Pair *>(g)[q];
         }
     }
-    // (row, column) of element 2q, q = threadIdx.x + j NT, stepped by 2 NT
+    // (row, column) of element 2q, q = threadIdx.x + j NTH, stepped by 2 NTH
     // elements per j instead of divided out per element
-    constexpr int DY = (2 * NT) / H, DX = (2 * NT) % H;
+    constexpr int DY = (2 * NTH) / H, DX = (2 * NTH) % H;
     int y0 = (2 * (int)threadIdx.x) / H, x0 = 2 * (int)threadIdx.x - y0 * H;
 #pragma unroll
     for (int j = 0; j < PER; ++j) {
-        const int q = threadIdx.x + j * NT;
+        const int q = threadIdx.x + j * NTH;
         if (q < NPAIR) {
             const bool wrap = x0 + 1 == H;
             const int o0 = y0 * S + x0, o1 = wrap ? (y0 + 1) * S : o0 + 1;
@@ -196,7 +197,7 @@ __device__ __forceinline__ void plane_copy(typename Cx<T>::t *Pl, typename Cx<T>
     if (!TO_LDS) {
 #pragma unroll
         for (int j = 0; j < PER; ++j) {
-            const int q = threadIdx.x + j * NT;
+            const int q = threadIdx.x + j * NTH;
             if (q < NPAIR) reinterpret_cast<Pair *>(g)[q] = v[j];
         }
     }
