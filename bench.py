@@ -525,8 +525,9 @@ def main():
                     help="0: plane path; 1: fused path, energy planes from the forward pass; 2: fused path, "
                          "z inputs formed in the z kernel (default: autotuned)")
     ap.add_argument("--clash-stream", type=int, default=-1,
-                    help="fused path: 1 runs the clash test of the next item on a second stream, 0 on one stream "
-                         "(default: autotuned, or the library default with --fused)")
+                    help="1 uses a second stream (fused path: the clash test of the next item; plane path: the "
+                         "inverse of one z pass beside the next), 0 one stream (default: autotuned, or the library "
+                         "default with --fused)")
     ap.add_argument("--workload", default="c2", choices=["c2", "c3", "c6"],
                     help="c2: the 8000-configuration T4L-sized scan (the metric's workload); "
                          "c3: 141 ligands x 10 receptor snapshots (batched); "

@@ -352,13 +352,17 @@ int fftdg_pair_energies(int device, void *hip_stream, int32_t n_rec_atoms, const
  *                      snapshots_per_pass are then not used.  0: the
  *                      occupancy channel as a fourth FFT channel thresholded
  *                      at 1/2 (the paper's formulation);
- *   clash_stream       fused path in OCC mode: 1 (default) runs the clash
- *                      test of the next (chunk, snapshot) on a second stream
- *                      of the context (default priority, created on first
- *                      use) beside the z pass and inverse of the current one,
- *                      its results double-buffered and the streams ordered
- *                      by events; 0 runs everything on the context's stream.
- *                      Not used while profiling or exporting energies. */
+ *   clash_stream       1 (default) uses a second stream of the context
+ *                      (default priority, created on first use), its
+ *                      buffers double-buffered and the streams ordered by
+ *                      events: on the fused path in OCC mode the clash test
+ *                      of the next (chunk, snapshot) runs on it beside the z
+ *                      pass and inverse of the current one; on the plane
+ *                      path (fused = 0) the inverse xy of one z pass runs on
+ *                      it beside the next z pass (twice the inverse
+ *                      workspace).  0 runs everything on the context's
+ *                      stream.  Not used while profiling or exporting
+ *                      energies. */
 typedef struct {
     int32_t configs_per_chunk;
     int32_t energy_xy_direct;
@@ -373,8 +377,8 @@ int fftdg_set_tuning(fftdg_ctx *ctx, const fftdg_tuning *t);
 /* Autotuner: times the candidate schedules (configurations per chunk in
  * {64, 128, 256, 512}, use_graph in {0, 1}, and fused in {1, 2} with
  * clash_stream in {0, 1} (OCC mode) where available or
- * fused = 0 with energy_xy_direct in {0, 1, 2} and snapshots_per_pass in
- * {1, n_snap} when there are several snapshots) with
+ * fused = 0 with energy_xy_direct in {0, 1, 2}, clash_stream in {0, 1} and
+ * snapshots_per_pass in {1, n_snap} when there are several snapshots) with
  * HIP events, each by the fastest of four runs after a warm-up, on an evenly
  * strided sample of at most max_cfgs configurations of the batch (all
  * receptor snapshots), keeps the fastest in the context and writes it to

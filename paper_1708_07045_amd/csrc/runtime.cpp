@@ -103,9 +103,14 @@ struct fftdg_ctx {
     int snap_group = 1;  // snapshots per z launch (limited by workspace)
     bool use_graph = false;
     int fused = 0;  // 0 plane path; fused path with energy planes from the forward pass (1) or built in the z kernel (2)
-    bool clash_stream = true;  // fused path, OCC: clash test of the next item on `side` beside the current z pass
+    // second stream: the fused path (OCC) tests the clash of the next item on
+    // `side` beside the current z pass and inverse; the plane path runs the
+    // inverse xy of one z pass on `side` beside the next z pass
+    bool clash_stream = true;
     hipStream_t side = nullptr;  // second stream (default priority), created on first use
-    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_clash[2] = {nullptr, nullptr}, ev_inv[2] = {nullptr, nullptr};
+    // buffer set p: work on `side` (ev_side) and on the context's stream
+    // (ev_main) that last produced or read it
+    hipEvent_t ev_fork = nullptr, ev_join = nullptr, ev_side[2] = {nullptr, nullptr}, ev_main[2] = {nullptr, nullptr};
     hipStream_t cap_stream = nullptr;   // capture only; graphs run on `stream`
     hipGraph_t graph = nullptr;
     hipGraphExec_t graph_exec = nullptr;
@@ -749,11 +754,13 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
         if ((rc = reserve(ctx, ctx->zat, ctx->fs->zat_bytes * (size_t)max_nz_atoms))) return rc;
         if ((rc = reserve(ctx, ctx->zbt, sizeof(int32_t) * (size_t)nzmax * (g.n_fft + 2)))) return rc;
     }
-    // fused path, OCC: the clash test of the next (chunk, snapshot) item runs
-    // on the side stream beside the z pass and inverse of the current one;
-    // its results (free bits, live flags, undecided-row lists) alternate
-    // between two buffer sets
-    const bool overlap = P.fused && occ && ctx->clash_stream && !ctx->prof && !psi_out && !clash_out;
+    // second stream.  Fused path, OCC: the clash test of the next (chunk,
+    // snapshot) item runs on the side stream beside the z pass and inverse of
+    // the current one; its results (free bits, live flags, undecided-row
+    // lists) alternate between two buffer sets.  Plane path: the inverse xy
+    // of one z pass runs on the side stream beside the next z pass; the
+    // inverse planes alternate between two workspace sets.
+    const bool overlap = (P.fused ? occ : true) && ctx->clash_stream && !ctx->prof && !psi_out && !clash_out;
     const int nsets = overlap ? 2 : 1;
     const size_t e_free = (size_t)std::max<int64_t>(P.max_free, 1), e_items = (size_t)std::max<int64_t>(P.max_items, 1);
     const size_t e_surv = (size_t)std::max<int64_t>(P.max_surv, 1), e_cfgs = (size_t)std::max<int64_t>(P.max_chunk_cfgs, 1);
@@ -767,8 +774,8 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     }
     if (overlap && !ctx->side) {
         HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
-        for (hipEvent_t *e : {&ctx->ev_fork, &ctx->ev_join, &ctx->ev_clash[0], &ctx->ev_clash[1], &ctx->ev_inv[0],
-                              &ctx->ev_inv[1]})
+        for (hipEvent_t *e : {&ctx->ev_fork, &ctx->ev_join, &ctx->ev_side[0], &ctx->ev_side[1], &ctx->ev_main[0],
+                              &ctx->ev_main[1]})
             HIPCHK(ctx, hipEventCreateWithFlags(e, hipEventDisableTiming));
     }
     // snapshots whose inverse planes share the workspace: the z kernel keeps
@@ -780,7 +787,8 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     const int grp = P.fused ? 1
                             : (int)std::max<int64_t>(1, std::min<int64_t>({(int64_t)(s_end - s_begin), room / inv1,
                                                                            (int64_t)ctx->snap_group}));
-    if ((rc = reserve(ctx, ctx->ws_inv, cb * (size_t)inv1 * grp))) return rc;
+    const size_t inv_set = cb * (size_t)inv1 * grp;  // bytes of one workspace set of inverse planes
+    if ((rc = reserve(ctx, ctx->ws_inv, inv_set * (overlap && !P.fused ? 2 : 1)))) return rc;
     // plane partials of the whole scan, one region per snapshot, merged into
     // configuration partials once per snapshot after the last chunk
     const size_t pp_snap = (size_t)ctx->ks->ppbytes * (size_t)std::max<int64_t>(P.total_pp, 1);
@@ -854,15 +862,15 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
             uint8_t *lv = lv_of(p);
             if (occ) {
                 // set p was last read by the inverse of item - 2
-                if (overlap && item >= 2) HIPCHK(ctx, hipStreamWaitEvent(sc, ctx->ev_inv[p], 0));
+                if (overlap && item >= 2) HIPCHK(ctx, hipStreamWaitEvent(sc, ctx->ev_main[p], 0));
                 const uint32_t *dil = (const uint32_t *)ctx->dil.p + (size_t)s * (size_t)fs->dil_words;
                 HIPCHK(ctx, timed(ctx, FFTDG_K_CLASH, 4.0 * (double)ch.nfree + (double)ch.nitems, [&] {
                            return fs->clash(sc, ditem + ch.off0, ditem2 + ch.off0, nloc, ch.nitems, ch.nitems2, ccfg,
                                             runs, rcnt, dil, fb, lv, surv_of(p), scnt_of(p));
                        }));
                 if (overlap) {
-                    HIPCHK(ctx, hipEventRecord(ctx->ev_clash[p], sc));
-                    HIPCHK(ctx, hipStreamWaitEvent(st, ctx->ev_clash[p], 0));
+                    HIPCHK(ctx, hipEventRecord(ctx->ev_side[p], sc));
+                    HIPCHK(ctx, hipStreamWaitEvent(st, ctx->ev_side[p], 0));
                 }
             }
             const char *rs = (const char *)ctx->rspec.p + spec_per_snap * s;
@@ -881,7 +889,7 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
                                       ctx->tw.p, fb, lv, pp_s, psi_out, clash_out,
                                       ctx->prof ? (unsigned int *)ctx->prof_cnt.p : nullptr);
                    }));
-            if (overlap) HIPCHK(ctx, hipEventRecord(ctx->ev_inv[p], st));
+            if (overlap) HIPCHK(ctx, hipEventRecord(ctx->ev_main[p], st));
             if (ctx->prof) ctx->prof_fused = true;
         }
     }
@@ -900,6 +908,13 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
     };
     auto launch_all = [&](hipStream_t st) -> int {
     if (P.fused) return launch_fused(st);
+    hipStream_t si = st;  // stream of the inverse xy
+    if (overlap) {
+        si = ctx->side;
+        HIPCHK(ctx, hipEventRecord(ctx->ev_fork, st));
+        HIPCHK(ctx, hipStreamWaitEvent(si, ctx->ev_fork, 0));
+    }
+    int zpass = 0;
     for (const Plan::Chunk &ch : P.chunks) {
         const CfgDev *ccfg = dcfg + ch.c0;
         // algorithmic bytes: forward planes written once (fwd), read once and
@@ -915,24 +930,38 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
         for (int s0 = s_begin; s0 < s_end; s0 += grp) {
           const int ng = std::min(grp, s_end - s0);
           const char *rs = (const char *)ctx->rspec.p + spec_per_snap * s0;
+          const int p = overlap ? (zpass & 1) : 0;
+          char *wsi = (char *)ctx->ws_inv.p + (size_t)p * inv_set;
+          // set p was last read by the inverse of z pass zpass - 2
+          if (overlap && zpass >= 2) HIPCHK(ctx, hipStreamWaitEvent(st, ctx->ev_side[p], 0));
           HIPCHK(ctx, timed(ctx, FFTDG_K_ZPROD, b_fwd + ng * (b_inv + (double)spec_per_snap), [&] {
                      return ks->zprod(st, occ, ctx->edirect == 1, ch.zhalf, ccfg, dz + ch.z0, (int)ch.nz, ctx->ws_fwd.p, rs,
-                                      ctx->tw.p, ctx->ws_inv.p, du, dgam, ng, (int64_t)(spec_per_snap / cb),
+                                      ctx->tw.p, wsi, du, dgam, ng, (int64_t)(spec_per_snap / cb),
                                       (int64_t)ch.ws_inv);
                  }));
+          if (overlap) {
+              HIPCHK(ctx, hipEventRecord(ctx->ev_main[p], st));
+              HIPCHK(ctx, hipStreamWaitEvent(si, ctx->ev_main[p], 0));
+          }
           for (int s = s0; s < s0 + ng; ++s) {
-            void *wsi_s = (char *)ctx->ws_inv.p + (size_t)(s - s0) * (size_t)ch.ws_inv * cb;
+            void *wsi_s = wsi + (size_t)(s - s0) * (size_t)ch.ws_inv * cb;
             // inverse xy: occupancy planes always, energy planes only where the
             // plane has a clash-free translation (counted on the device)
             const double b_inv_fixed = (occ ? 0.5 * b_inv : 0.0) + pb * ch.pp;
             void *pp_s = (char *)ctx->pp.p + pp_snap * (size_t)(s - s_begin);
             HIPCHK(ctx, timed(ctx, FFTDG_K_INV, b_inv_fixed, [&] {
-                       return ks->inv(st, occ, dinv + ch.off0, ch.c1 - ch.c0, (int)ch.ninv, ccfg, wsi_s, beta,
+                       return ks->inv(si, occ, dinv + ch.off0, ch.c1 - ch.c0, (int)ch.ninv, ccfg, wsi_s, beta,
                                       ctx->tw.p, pp_s, psi_out, clash_out,
                                       ctx->prof ? (unsigned int *)ctx->prof_cnt.p : nullptr);
                    }));
           }
+          if (overlap) HIPCHK(ctx, hipEventRecord(ctx->ev_side[p], si));
+          ++zpass;
         }
+    }
+    if (overlap) {  // join: later work on `st` sees the side stream's work done
+        HIPCHK(ctx, hipEventRecord(ctx->ev_join, si));
+        HIPCHK(ctx, hipStreamWaitEvent(st, ctx->ev_join, 0));
     }
     if (out)
         for (int s = s_begin; s < s_end; ++s) {
@@ -1153,7 +1182,7 @@ void fftdg_destroy(fftdg_ctx *c) {
     if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
-    for (hipEvent_t e : {c->ev_fork, c->ev_join, c->ev_clash[0], c->ev_clash[1], c->ev_inv[0], c->ev_inv[1]})
+    for (hipEvent_t e : {c->ev_fork, c->ev_join, c->ev_side[0], c->ev_side[1], c->ev_main[0], c->ev_main[1]})
         if (e) (void)hipEventDestroy(e);
     if (c->side) (void)hipStreamDestroy(c->side);
     delete c;
@@ -1508,7 +1537,8 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
         for (int ed : {0, 1, 2})
             for (int sp : passes)
                 for (int gr : {0, 1})
-                    if (ed != 1 || ctx->g.n_fft <= 128) cand.push_back(fftdg_tuning{chunk, ed, sp, gr, 0, 0});
+                    for (int cs : {0, 1})
+                        if (ed != 1 || ctx->g.n_fft <= 128) cand.push_back(fftdg_tuning{chunk, ed, sp, gr, 0, cs});
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     HIPCHK(ctx, hipEventCreate(&e0));
