@@ -297,7 +297,10 @@ def batched_timing(reps: int = 3):
     del gl, ol
     b = fd.Batch(w.ligands)
     log(f"batched timing: {len(w.ligands)} ligands, {b.n_cfg} configurations x {S} snapshots")
-    tun, _ = ctx.autotune(b, w.T, max_cfgs=2048)
+    # 1024 sampled configurations x 10 snapshots per candidate schedule keep
+    # the tuner within a couple of minutes
+    tun, _ = ctx.autotune(b, w.T, max_cfgs=1024)
+    log(f"batched schedule {tun}")
     out = ctx.alloc_partials(b)
     ctx.scan(b, w.T, out)
     torch.cuda.synchronize()
@@ -360,8 +363,8 @@ def configs_needed(args):
     if csnaps == "half":
         csnaps = list(range(0, S, 2))
     ctx_c = prop.make_context(w, cdesc, snapshots=csnaps, clash_mode=args.is_coarse_clash)
-    ctx_f.autotune(b, T, max_cfgs=2048)
-    ctx_c.autotune(b, T, max_cfgs=2048)
+    log(f"fine schedule {ctx_f.autotune(b, T, max_cfgs=1024)[0]}")
+    log(f"coarse schedule {ctx_c.autotune(b, T, max_cfgs=2048)[0]}")
 
     def timed_scan(ctx, bb):
         out = ctx.scan(bb, T)
@@ -372,10 +375,11 @@ def configs_needed(args):
         return out, time.perf_counter() - t0
 
     part_f, t_f = timed_scan(ctx_f, b)
+    log(f"exhaustive fine scan {t_f:.2f}s")
     per_fine = t_f / b.n_cfg          # seconds per configuration of the fine scan
     if cascade:
         ctx_m = prop.make_context(w, cdesc, snapshots="mean", clash_mode=args.is_coarse_clash)
-        ctx_m.autotune(b, T, max_cfgs=2048)
+        log(f"mean-receptor schedule {ctx_m.autotune(b, T, max_cfgs=2048)[0]}")
         part_m, t_m = timed_scan(ctx_m, b)
         y_mean = prop.coarse_score(ctx_m, b, part_m)
         cand = np.zeros(b.n_cfg, np.uint8)
