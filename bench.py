@@ -352,9 +352,9 @@ def configs_needed(args):
     S = w.receptor.n_snap
     log(f"configs needed: {len(w.ligands)} ligands, {b.n_cfg} configurations x {S} snapshots")
     ctx_f = prop.make_context(w)
-    # coarse pre-scan at twice the spacing: against every snapshot (default),
-    # one receptor at the snapshots' mean coordinates, every other snapshot,
-    # the first snapshot, or a cascade (the mean receptor for every
+    # coarse pre-scan at twice the spacing: against every snapshot, one
+    # receptor at the snapshots' mean coordinates, every other snapshot, the
+    # first snapshot, or a cascade (default: the mean receptor for every
     # configuration, then every snapshot for each ligand's top fraction by
     # that score); repulsion capped (default) or overlaps excluded
     cascade = args.is_coarse == "cascade"
@@ -419,12 +419,15 @@ def configs_needed(args):
     else:
         t, wt = prop.targets(ctx_f, b, part_f)
     alpha = 0.1
-    val_score = prop.pool_fraction_scorer(w, b, P_f, val_l, alpha, (0.5, 1.0, 2.0), kT, reps=50)
+    # plan (mixture temperature, exact share of the budget) chosen on the
+    # validation ligands with the epochs
+    plans = [(tau, share) for share in args.is_exact_shares for tau in (0.5, 1.0, 2.0)]
+    val_score = prop.pool_fraction_scorer(w, b, P_f, val_l, alpha, plans, kT, reps=50)
     pred, tau_of, t_train, epochs_of, val_of = {}, {}, {}, {}, {}
     y_coarse = X[:, fd.N_FEATURES].cpu().numpy()
     val_of["coarse"], tau_of["coarse"] = val_score(y_coarse)
     pred["coarse"] = y_coarse
-    log(f"coarse: validation mean fraction {val_of['coarse']:.3f} at tau {tau_of['coarse']}")
+    log(f"coarse: validation mean fraction {val_of['coarse']:.3f} at plan {tau_of['coarse']}")
     # net_scan: residual form (coarse relative log weight through the skip;
     # at epoch 0 it is the coarse score); net_cfg: configuration descriptors
     # only.  The epoch count is chosen on the validation ligands.
@@ -439,7 +442,7 @@ def configs_needed(args):
         tau_of[name], epochs_of[name], val_of[name] = keep["tau"], keep["epoch"], keep["score"]
         log(f"{name}: {args.is_epochs} epochs on {rows.size} rows in {t_train[name]:.1f}s (with validation), "
             f"last batch loss {keep['loss']:.4f}; kept epoch {keep['epoch']}")
-    log(f"mixture temperatures (nats) chosen on validation ligands: {tau_of}")
+    log(f"plans (mixture temperature in nats, exact share) chosen on validation ligands: {tau_of}")
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([170807045, 21])))
     per = []
     for l in test_l:
@@ -448,8 +451,8 @@ def configs_needed(args):
         row = {"ligand": int(l), "n_cfg": int(Pl), "plain": prop.kstar_plain(Zs, kT, rng, reps=args.is_reps)}
         for name in pred:
             yl = pred[name][b.cfg_off[l]:b.cfg_off[l + 1]]
-            k, bf = prop.kstar_is(prop.sub_batch(w, l), Zs, yl, alpha, tau_of[name], kT, 2000 + int(l),
-                                  reps=args.is_reps)
+            k, bf = prop.kstar_is(prop.sub_batch(w, l), Zs, yl, alpha, tau_of[name][0], kT, 2000 + int(l),
+                                  reps=args.is_reps, exact_share=tau_of[name][1])
             extra = float(extra_cfg[b.cfg_off[l]:b.cfg_off[l + 1]].sum()) if name in ("net_scan", "coarse") else 0.0
             row[name] = min(float(Pl), k + extra)
             row[name + "_budget"] = bf
@@ -458,8 +461,9 @@ def configs_needed(args):
             f"coarse {row['coarse']:.0f}  net_cfg {row['net_cfg']:.0f}")
     med = lambda key: float(np.median([r["plain"] / r[key] for r in per]))
     # one real importance-sampled scan of the held-out ligands at 10 % of
-    # the configurations (5 % exact top + 5 % draws), against the exhaustive,
-    # with the network's proposal and with the coarse score's
+    # the configurations (exact top and draws split as the plan chosen on the
+    # validation ligands), against the exhaustive, with the network's
+    # proposal and with the coarse score's
     bt = fd.Batch([w.ligands[l] for l in test_l])
     u = synth.uniforms(31, bt.n_cfg)
     Bref = B_ex[test_l]
@@ -469,7 +473,8 @@ def configs_needed(args):
         yt = np.concatenate([pred[name][b.cfg_off[l]:b.cfg_off[l + 1]] for l in test_l])
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        est = prop.is_estimate(ctx_f, bt, yt, 0.05, 0.05, alpha, tau_of[name], u, T)
+        tau, share = tau_of[name]
+        est = prop.is_estimate(ctx_f, bt, yt, 0.1 * share, 0.1 * (1.0 - share), alpha, tau, u, T)
         torch.cuda.synchronize()
         t_is = time.perf_counter() - t0
         dB = est["B"] - Bref
@@ -504,7 +509,8 @@ def configs_needed(args):
         "target": args.is_target,
         "split": "101 training ligands = 81 fitted + 20 validation (temperature, epochs); 40 held out",
         "mixture_alpha": alpha,
-        "mixture_tau_nats": tau_of,
+        "mixture_tau_nats": {k: v[0] for k, v in tau_of.items()},
+        "exact_share": {k: v[1] for k, v in tau_of.items()},
         "epochs_kept": epochs_of,
         "validation_mean_fraction": val_of,
         "train_seconds": t_train,
@@ -557,15 +563,22 @@ def main():
                     help="training target: largest per-snapshot relative log weight, or the log of the "
                          "snapshot-weighted sum")
     ap.add_argument("--is-detail", default="", help="write per-ligand configurations-needed results here (JSON)")
-    ap.add_argument("--is-coarse", default="all", choices=["mean", "all", "half", "first", "cascade"],
+    ap.add_argument("--is-coarse", default="cascade", choices=["mean", "all", "half", "first", "cascade"],
                     help="coarse pre-scan receptors: one at the snapshots' mean coordinates, every snapshot, "
-                         "every other snapshot, the first snapshot, or a cascade (the mean receptor for every configuration, then every "
-                         "snapshot for each ligand's top --is-cascade-frac by that score)")
-    ap.add_argument("--is-cascade-frac", type=float, default=0.3)
+                         "every other snapshot, the first snapshot, or a cascade (default: the mean receptor for "
+                         "every configuration, then every snapshot for each ligand's top --is-cascade-frac by that "
+                         "score)")
+    ap.add_argument("--is-cascade-frac", type=float, default=0.4)
+    ap.add_argument("--is-exact-shares", default="0.5,0.75,0.9",
+                    help="candidate shares of the budget scanned exactly (the top of the proposal), chosen with the "
+                         "mixture temperature on the validation ligands")
     ap.add_argument("--is-coarse-clash", default="cap", choices=["occ", "cap"],
                     help="clash handling of the coarse pre-scan: capped repulsion (one inverse channel; default) "
                          "or occupancy exclusion (as the fine scan)")
     args = ap.parse_args()
+    args.is_exact_shares = [float(x) for x in args.is_exact_shares.split(",")]
+    if not args.is_exact_shares or any(not 0.0 <= x < 1.0 for x in args.is_exact_shares):
+        ap.error("--is-exact-shares: comma-separated fractions in [0, 1)")
     args.is_coarse_snapshots = {"mean": "mean", "all": None, "half": "half", "first": [0],
                                 "cascade": None}[args.is_coarse]
     if args.is_coarse_factor not in (2, 4):

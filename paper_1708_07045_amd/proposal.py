@@ -287,19 +287,21 @@ def kstar_plain(Zs, kT, rng, reps: int = 200, tol: float = 0.1):
     return float(P)
 
 
-def kstar_is(sub_batch, Zs, yhat, alpha, tau, kT, seed0, reps: int = 200, tol: float = 0.1):
-    """Same for the stratified plan (half the budget exact top, half draws)
-    over the budget fractions BUDGETS; returns (distinct configurations,
-    budget fraction) or (P, None)."""
+def kstar_is(sub_batch, Zs, yhat, alpha, tau, kT, seed0, reps: int = 200, tol: float = 0.1,
+             exact_share: float = 0.5):
+    """Same for the stratified plan (exact_share of the budget the exact top,
+    the rest draws) over the budget fractions BUDGETS; returns (distinct
+    configurations, budget fraction) or (P, None)."""
     P = Zs.shape[1]
     for bf in BUDGETS:
-        half = bf / 2.0
-        K = int(np.ceil(half * P))
+        top = bf * exact_share
+        draw = bf - top
+        K = int(np.ceil(draw * P))
         Wr = np.zeros((reps, P))
         ns = np.zeros(reps)
         for r in range(reps):
             u = np.random.Generator(np.random.PCG64(np.random.SeedSequence([170807045, seed0, r]))).random(K + 1)
-            sel, wt, n = fd.is_plan(sub_batch, yhat, half, half, alpha, tau / 5.0, u)
+            sel, wt, n = fd.is_plan(sub_batch, yhat, top, draw, alpha, tau / 5.0, u)
             Wr[r] = wt
             ns[r] = n
         Zw = Wr @ Zs.T
@@ -308,24 +310,27 @@ def kstar_is(sub_batch, Zs, yhat, alpha, tau, kT, seed0, reps: int = 200, tol: f
     return float(P), None
 
 
-def pool_fraction_scorer(w, batch, P_fine, ligs, alpha: float, taus, kT: float, reps: int = 50, seed0: int = 1000):
+def pool_fraction_scorer(w, batch, P_fine, ligs, alpha: float, plans, kT: float, reps: int = 50, seed0: int = 1000):
     """Function y -> (mean over `ligs` of the fraction of the pool the
-    stratified plan needs (kstar_is), best tau of `taus`) for predictions y
-    over all configurations of `batch`; used to choose the mixture
-    temperature and the training epochs on ligands not fitted."""
+    stratified plan needs (kstar_is), best plan of `plans`) for predictions y
+    over all configurations of `batch`; a plan is (mixture temperature tau,
+    exact share of the budget), a bare tau meaning (tau, 0.5).  Used to choose
+    the plan and the training epochs on ligands not fitted."""
     Z = {int(l): ligand_weights(P_fine, batch.cfg_off, l) for l in ligs}
+    plans = [tuple(p) if isinstance(p, (tuple, list)) else (float(p), 0.5) for p in plans]
 
     def score(y):
         best = None
-        for tau in taus:
+        for tau, share in plans:
             ks = []
             for l in ligs:
                 yl = y[batch.cfg_off[l]:batch.cfg_off[l + 1]]
-                k, _ = kstar_is(sub_batch(w, l), Z[int(l)], yl, alpha, tau, kT, seed0 + int(l), reps=reps)
+                k, _ = kstar_is(sub_batch(w, l), Z[int(l)], yl, alpha, tau, kT, seed0 + int(l), reps=reps,
+                                exact_share=share)
                 ks.append(k / Z[int(l)].shape[1])
             m = float(np.mean(ks))
             if best is None or m < best[0]:
-                best = (m, tau)
+                best = (m, (tau, share))
         return best
 
     return score
@@ -335,8 +340,8 @@ def fit_selected(net, X, t, wt, rows, score, epochs: int, check_at=(0, 2, 5, 10,
     """Train `net` on `rows` for `epochs` and keep the parameters of the
     checkpoint (epoch in check_at, or the last) that `score` rates best;
     epoch 0 is the starting network (for the residual form, the coarse
-    score itself).  Returns dict(score, tau, epoch, params, loss) and leaves
-    the kept parameters set."""
+    score itself).  Returns dict(score, tau (the plan score chose), epoch,
+    params, loss) and leaves the kept parameters set."""
     at = {e for e in check_at if e <= epochs} | {epochs}
     keep = {}
 
@@ -345,7 +350,7 @@ def fit_selected(net, X, t, wt, rows, score, epochs: int, check_at=(0, 2, 5, 10,
             return
         sc, tau = score(net.forward(X).cpu().numpy())
         if log:
-            log(f"{name} epoch {ep}: score {sc:.4f} at tau {tau}")
+            log(f"{name} epoch {ep}: score {sc:.4f} at plan {tau}")
         if "score" not in keep or sc < keep["score"]:
             keep.update(score=sc, tau=tau, epoch=ep, params=net.get_params())
 
