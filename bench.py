@@ -333,12 +333,13 @@ def batched_timing(reps: int = 3):
             "dG_mean_kcal_mol": float(np.mean(res["dG"]))}
 
 
-def configs_needed(args):
+def configs_needed(args, fine_tuning=None):
     """Configurations a BPMF estimate needs for +-0.1 kcal/mol in every
     snapshot, plain uniform sampling vs the learned proposal, on the batched
     141-ligand x 10-snapshot workload (seeded split: 101 training ligands,
     40 held out).  Costs are fine-scan equivalents; a coarse pre-scan counts
-    at its measured cost ratio."""
+    at its measured cost ratio.  fine_tuning: the fine scans' schedule
+    (else autotuned here)."""
     import numpy as np
     import torch
     import paper_1708_07045_amd as fd
@@ -363,7 +364,11 @@ def configs_needed(args):
     if csnaps == "half":
         csnaps = list(range(0, S, 2))
     ctx_c = prop.make_context(w, cdesc, snapshots=csnaps, clash_mode=args.is_coarse_clash)
-    log(f"fine schedule {ctx_f.autotune(b, T, max_cfgs=1024)[0]}")
+    if fine_tuning:  # the batched timing tuned this same workload already
+        ctx_f.set_tuning(**fine_tuning)
+        log(f"fine schedule {fine_tuning} (from the batched timing)")
+    else:
+        log(f"fine schedule {ctx_f.autotune(b, T, max_cfgs=1024)[0]}")
     log(f"coarse schedule {ctx_c.autotune(b, T, max_cfgs=2048)[0]}")
 
     def timed_scan(ctx, bb):
@@ -827,7 +832,7 @@ def main():
         rec["batched"] = batched_timing()
         torch.cuda.empty_cache()
     if args.workload == "c2" and not args.no_is:
-        cn = configs_needed(args)
+        cn = configs_needed(args, rec["batched"]["tuning"] if rec.get("batched") else None)
         rec["configs_needed"] = {k: v for k, v in cn.items() if k != "per_ligand"}
         rec["configs_needed_median_plain_over_learned"] = cn["median_plain_over"]["net_scan"]
         if args.is_detail:
