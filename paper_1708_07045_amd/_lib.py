@@ -60,7 +60,7 @@ EXPORTS = ["fftdg_version", "fftdg_status_string", "fftdg_create", "fftdg_destro
            "fftdg_set_stream", "fftdg_receptor_grids", "fftdg_set_receptors", "fftdg_scan",
            "fftdg_energy_grid", "fftdg_place", "fftdg_reduce", "fftdg_reduce_static", "fftdg_profile", "fftdg_profile_read",
            "fftdg_get_tuning", "fftdg_set_tuning", "fftdg_autotune", "fftdg_config_features",
-           "fftdg_mlp_create", "fftdg_mlp_destroy", "fftdg_mlp_last_error", "fftdg_mlp_num_params",
+           "fftdg_mlp_create", "fftdg_mlp_create_ex", "fftdg_mlp_destroy", "fftdg_mlp_last_error", "fftdg_mlp_num_params",
            "fftdg_mlp_set_params", "fftdg_mlp_get_params", "fftdg_mlp_set_skip", "fftdg_mlp_forward", "fftdg_mlp_grad",
            "fftdg_mlp_train_step", "fftdg_proposal_sample", "fftdg_scan_features", "fftdg_is_plan", "fftdg_sample_poses",
            "fftdg_grids_build", "fftdg_grid_energies", "fftdg_pair_energies"]
@@ -106,6 +106,7 @@ def load():
     L.fftdg_autotune.argtypes = [p, ctypes.POINTER(BatchC), d, i32, ctypes.POINTER(Tuning), p]
     L.fftdg_config_features.argtypes = [p, ctypes.POINTER(BatchC), p]
     L.fftdg_mlp_create.argtypes = [ctypes.POINTER(p), ctypes.c_int, p, i32, i32, i32]
+    L.fftdg_mlp_create_ex.argtypes = [ctypes.POINTER(p), ctypes.c_int, p, i32, i32, i32, i32]
     L.fftdg_mlp_destroy.argtypes = [p]
     L.fftdg_mlp_destroy.restype = None
     L.fftdg_mlp_last_error.argtypes = [p]
@@ -482,10 +483,11 @@ def is_plan(batch: Batch, yhat, top_frac: float, draw_frac: float, alpha: float,
 
 
 class Network:
-    """The proposal network of the library (fftdg_mlp)."""
+    """The proposal network of the library (fftdg_mlp); fp32: FP32 operands
+    and activations instead of BF16 (fftdg_mlp_create_ex)."""
 
     def __init__(self, n_in: int = N_FEATURES, width: int = 256, max_batch: int = 4096, device: int = 0,
-                 stream=None):
+                 stream=None, fp32: bool = False):
         import torch
         self.torch = torch
         self.L = load()
@@ -494,9 +496,10 @@ class Network:
         if stream is None:
             stream = torch.cuda.current_stream(self.device).cuda_stream
         h = ctypes.c_void_p()
-        rc = self.L.fftdg_mlp_create(ctypes.byref(h), device, ctypes.c_void_p(stream), n_in, width, max_batch)
+        rc = self.L.fftdg_mlp_create_ex(ctypes.byref(h), device, ctypes.c_void_p(stream), n_in, width, max_batch,
+                                        1 if fp32 else 0)
         if rc != OK:
-            raise FFTDGError(rc, "fftdg_mlp_create failed (" + self.L.fftdg_status_string(rc).decode() + ")")
+            raise FFTDGError(rc, "fftdg_mlp_create_ex failed (" + self.L.fftdg_status_string(rc).decode() + ")")
         self.h = h
         self.n_params = int(self.L.fftdg_mlp_num_params(h))
 

@@ -9,6 +9,11 @@
 //   B[k][j]: lane = j + 16*(k/4), element k%4      (column j, 4 consecutive k)
 //   D[i][j]: lane = j + 16*(i/4), element i%4
 // so with both operands stored K-contiguous a lane loads 8 contiguous bytes.
+// Every kernel is also instantiated with FP32 operands and activations
+// (element type E = float; GEMMs on v_mfma_f32_16x16x4_f32, A[i][k] at lane
+// i + 16 k and B[k][j] at lane j + 16 k of each 16 x 16 x 4 step, D as above):
+// the same network in FP32 throughout, for checking gradients against an
+// FP64 reference to FP32 rounding.
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdint.h>
@@ -35,20 +40,26 @@ __device__ __forceinline__ uint16_t f2bf(float f) {  // round to nearest even
     return (uint16_t)(u >> 16);
 }
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+// operand / activation element: BF16 bits (uint16_t) or FP32
+template <typename E> __device__ __forceinline__ E to_e(float f);
+template <> __device__ __forceinline__ uint16_t to_e<uint16_t>(float f) { return f2bf(f); }
+template <> __device__ __forceinline__ float to_e<float>(float f) { return f; }
+__device__ __forceinline__ float from_e(uint16_t h) { return bf2f(h); }
+__device__ __forceinline__ float from_e(float f) { return f; }
 __device__ __forceinline__ float silu(float z) { return z / (1.0f + expf(-z)); }
 __device__ __forceinline__ float dsilu(float z) {
     const float s = 1.0f / (1.0f + expf(-z));
     return s * (1.0f + z * (1.0f - s));
 }
 
-// C[M][N] = A[M][K] * B[N][K]^T, BF16 operands, FP32 accumulation.
+// C[M][N] = A[M][K] * B[N][K]^T, E operands, FP32 accumulation.
 // M, N multiples of 64; K multiple of 16; lda, ldb multiples of 4.
 // mode 0: C (+ bias[n] if bias) -> Cout (fp32, ldc)
-// mode 1: Z = C + bias[n] -> Cout; H = silu(Z) -> Hout (bf16, ldh)
-__global__ __launch_bounds__(256) void k_gemm(const uint16_t *__restrict__ A, int lda, const uint16_t *__restrict__ B,
-                                              int ldb, int K, const float *__restrict__ bias, int mode,
-                                              float *__restrict__ Cout, int ldc, uint16_t *__restrict__ Hout,
-                                              int ldh) {
+// mode 1: Z = C + bias[n] -> Cout; H = silu(Z) -> Hout (E, ldh)
+template <typename E>
+__global__ __launch_bounds__(256) void k_gemm(const E *__restrict__ A, int lda, const E *__restrict__ B, int ldb,
+                                              int K, const float *__restrict__ bias, int mode,
+                                              float *__restrict__ Cout, int ldc, E *__restrict__ Hout, int ldh) {
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int m0 = blockIdx.y * 64 + (wave >> 1) * 32, n0 = blockIdx.x * 64 + (wave & 1) * 32;
     const int r = lane & 15, kq = (lane >> 4) * 4;
@@ -58,17 +69,36 @@ __global__ __launch_bounds__(256) void k_gemm(const uint16_t *__restrict__ A, in
 #pragma unroll
         for (int b = 0; b < 2; ++b) acc[a][b] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int k = 0; k < K; k += 16) {
-        bf16x4 fa[2], fb[2];
+        if constexpr (sizeof(E) == 2) {
+            bf16x4 fa[2], fb[2];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
-            fa[t] = *reinterpret_cast<const bf16x4 *>(A + (size_t)(m0 + t * 16 + r) * lda + k + kq);
-            fb[t] = *reinterpret_cast<const bf16x4 *>(B + (size_t)(n0 + t * 16 + r) * ldb + k + kq);
+            for (int t = 0; t < 2; ++t) {
+                fa[t] = *reinterpret_cast<const bf16x4 *>(A + (size_t)(m0 + t * 16 + r) * lda + k + kq);
+                fb[t] = *reinterpret_cast<const bf16x4 *>(B + (size_t)(n0 + t * 16 + r) * ldb + k + kq);
+            }
+#pragma unroll
+            for (int a = 0; a < 2; ++a)
+#pragma unroll
+                for (int b = 0; b < 2; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa[a], fb[b], acc[a][b], 0, 0, 0);
+        } else {
+            // four 16 x 16 x 4 steps; lane (r, q = lane / 16) supplies k + 4 s + q
+            const int q = lane >> 4;
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                float fa[2], fb[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t) {
+                    fa[t] = A[(size_t)(m0 + t * 16 + r) * lda + k + 4 * s4 + q];
+                    fb[t] = B[(size_t)(n0 + t * 16 + r) * ldb + k + 4 * s4 + q];
+                }
+#pragma unroll
+                for (int a = 0; a < 2; ++a)
+#pragma unroll
+                    for (int b = 0; b < 2; ++b)
+                        acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(fa[a], fb[b], acc[a][b], 0, 0, 0);
+            }
         }
-#pragma unroll
-        for (int a = 0; a < 2; ++a)
-#pragma unroll
-            for (int b = 0; b < 2; ++b)
-                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(fa[a], fb[b], acc[a][b], 0, 0, 0);
     }
 #pragma unroll
     for (int a = 0; a < 2; ++a)
@@ -81,31 +111,33 @@ __global__ __launch_bounds__(256) void k_gemm(const uint16_t *__restrict__ A, in
                 float v = acc[a][b][e];
                 if (bias) v += bias[j];
                 Cout[(size_t)i * ldc + j] = v;
-                if (mode == 1) Hout[(size_t)i * ldh + j] = f2bf(silu(v));
+                if (mode == 1) Hout[(size_t)i * ldh + j] = to_e<E>(silu(v));
             }
 }
 
-// rows idx[b] of X [N][n_in] (fp32) -> A0 [Bp][KP] bf16, zero padded
+// rows idx[b] of X [N][n_in] (fp32) -> A0 [Bp][KP] (E), zero padded
+template <typename E>
 __global__ void k_gather(const float *__restrict__ X, int n_in, const int32_t *__restrict__ idx, int B, int Bp,
-                         uint16_t *__restrict__ A0) {
+                         E *__restrict__ A0) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= Bp * KP) return;
     const int b = e / KP, k = e - b * KP;
     float v = 0.f;
     if (b < B && k < n_in) v = X[(size_t)(idx ? idx[b] : b) * n_in + k];
-    A0[e] = f2bf(v);
+    A0[e] = to_e<E>(v);
 }
 
-// y[b] = H3[b] . W4 + b4 (FP32 accumulation of BF16 activations and
+// y[b] = H3[b] . W4 + b4 (FP32 accumulation of E activations and
 // weights), plus skip_scale times input column skip_col of the row (FP32)
 // when skip_col >= 0
-__global__ void k_out(const uint16_t *__restrict__ H3, int W, const uint16_t *__restrict__ W4, const float *b4,
+template <typename E>
+__global__ void k_out(const E *__restrict__ H3, int W, const E *__restrict__ W4, const float *b4,
                       int B, const float *__restrict__ X, int n_in, const int32_t *__restrict__ idx, int skip_col,
                       float skip_scale, float *__restrict__ y) {
     const int b = blockIdx.x * blockDim.x + threadIdx.x;
     if (b >= B) return;
     float s = 0.f;
-    for (int k = 0; k < W; ++k) s += bf2f(H3[(size_t)b * W + k]) * bf2f(W4[k]);
+    for (int k = 0; k < W; ++k) s += from_e(H3[(size_t)b * W + k]) * from_e(W4[k]);
     const float sk = skip_col >= 0 ? skip_scale * X[(size_t)(idx ? idx[b] : b) * n_in + skip_col] : 0.f;
     y[b] = s + b4[0] + sk;
 }
@@ -141,34 +173,36 @@ __global__ __launch_bounds__(256) void k_loss(const float *__restrict__ y, const
 }
 
 // output layer gradients: dW4[k] = sum_b dy_b H3[b][k], db4 = sum_b dy_b
-__global__ void k_out_grad(const float *__restrict__ dy, const uint16_t *__restrict__ H3, int W, int B,
+template <typename E>
+__global__ void k_out_grad(const float *__restrict__ dy, const E *__restrict__ H3, int W, int B,
                            float *__restrict__ gW4, float *__restrict__ gb4) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k > W) return;
     float s = 0.f;
     if (k < W)
-        for (int b = 0; b < B; ++b) s += dy[b] * bf2f(H3[(size_t)b * W + k]);
+        for (int b = 0; b < B; ++b) s += dy[b] * from_e(H3[(size_t)b * W + k]);
     else
         for (int b = 0; b < B; ++b) s += dy[b];
     if (k < W) gW4[k] = s; else gb4[0] = s;
 }
 
 // dZ[b][n] = dH[b][n] * silu'(Z[b][n]) with dH = dy_b W4[n] (from_out) or the
-// given fp32 dH; writes bf16 dZ [Bp][N] and its transpose [N][Bp] (rows
+// given fp32 dH; writes E dZ [Bp][N] and its transpose [N][Bp] (rows
 // b >= B are zero) and keeps fp32 dZ for the bias gradient.
-__global__ void k_dz(const float *__restrict__ dH, const float *__restrict__ dy, const uint16_t *__restrict__ W4,
-                     const float *__restrict__ Z, int N, int B, int Bp, float *__restrict__ dZf,
-                     uint16_t *__restrict__ dZ, uint16_t *__restrict__ dZt) {
+template <typename E>
+__global__ void k_dz(const float *__restrict__ dH, const float *__restrict__ dy, const E *__restrict__ W4,
+                     const float *__restrict__ Z, int N, int B, int Bp, float *__restrict__ dZf, E *__restrict__ dZ,
+                     E *__restrict__ dZt) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= Bp * N) return;
     const int b = e / N, n = e - b * N;
     float v = 0.f;
     if (b < B) {
-        const float g = dH ? dH[e] : dy[b] * bf2f(W4[n]);
+        const float g = dH ? dH[e] : dy[b] * from_e(W4[n]);
         v = g * dsilu(Z[e]);
     }
     dZf[e] = v;
-    const uint16_t h = f2bf(v);
+    const E h = to_e<E>(v);
     dZ[e] = h;
     dZt[(size_t)n * Bp + b] = h;
 }
@@ -182,8 +216,9 @@ __global__ void k_colsum(const float *__restrict__ M, int N, int B, float *__res
     out[n] = s;
 }
 
-// bf16 transpose: out[c][r] = in[r][c], in [R][C]
-__global__ void k_transpose(const uint16_t *__restrict__ in, int R, int C, uint16_t *__restrict__ out) {
+// transpose: out[c][r] = in[r][c], in [R][C]
+template <typename E>
+__global__ void k_transpose(const E *__restrict__ in, int R, int C, E *__restrict__ out) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= R * C) return;
     const int r = e / C, c = e - r * C;
@@ -211,12 +246,13 @@ __global__ void k_adam(float *__restrict__ p, const float *__restrict__ g, float
     p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
 }
 
-// BF16 working copies of a weight matrix [R][C] into [R][ldd] (zero padded)
-__global__ void k_w_bf16(const float *__restrict__ W, int R, int C, int ldd, uint16_t *__restrict__ out) {
+// E working copies of a weight matrix [R][C] into [R][ldd] (zero padded)
+template <typename E>
+__global__ void k_w_copy(const float *__restrict__ W, int R, int C, int ldd, E *__restrict__ out) {
     const int e = blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= R * ldd) return;
     const int r = e / ldd, c = e - r * ldd;
-    out[e] = c < C ? f2bf(W[(size_t)r * C + c]) : (uint16_t)0;
+    out[e] = to_e<E>(c < C ? W[(size_t)r * C + c] : 0.f);
 }
 
 // Defensive mixture proposal over P configurations and inverse-CDF draws:
@@ -290,8 +326,9 @@ struct fftdg_mlp {
     std::string err;
     int n_in = 0, width = 0, max_batch = 0, Bmax = 0;
     int64_t np = 0;
+    bool fp32 = false;             // operands and activations FP32 (else BF16)
     Buf P, G, Mm, Vv;              // fp32 master params, grads, Adam moments
-    Buf W1, W2, W3, W4, W2t, W3t;  // bf16 working copies
+    Buf W1, W2, W3, W4, W2t, W3t;  // working copies in the operand type
     Buf A0, A0t, H1, H2, H3, H1t, H2t, Z1, Z2, Z3, y, dy, dZf, dZ, dZt, dH, gtmp, loss, idx_tmp;
     Buf pcdf;
     int64_t step = 0;
@@ -343,100 +380,110 @@ struct Lay {
     }
 };
 
-int refresh_bf16(fftdg_mlp *m) {
+template <typename E>
+int refresh_t(fftdg_mlp *m) {
     const int F = m->n_in, H = m->width;
     const Lay L(F, H);
     const float *p = (const float *)m->P.p;
     hipStream_t st = m->stream;
-    hipLaunchKernelGGL(k_w_bf16, dim3(nb((size_t)H * KP)), dim3(256), 0, st, p + L.W1, H, F, KP, (uint16_t *)m->W1.p);
-    hipLaunchKernelGGL(k_w_bf16, dim3(nb((size_t)H * H)), dim3(256), 0, st, p + L.W2, H, H, H, (uint16_t *)m->W2.p);
-    hipLaunchKernelGGL(k_w_bf16, dim3(nb((size_t)H * H)), dim3(256), 0, st, p + L.W3, H, H, H, (uint16_t *)m->W3.p);
-    hipLaunchKernelGGL(k_w_bf16, dim3(nb((size_t)H)), dim3(256), 0, st, p + L.W4, 1, H, H, (uint16_t *)m->W4.p);
-    hipLaunchKernelGGL(k_transpose, dim3(nb((size_t)H * H)), dim3(256), 0, st, (const uint16_t *)m->W2.p, H, H,
-                       (uint16_t *)m->W2t.p);
-    hipLaunchKernelGGL(k_transpose, dim3(nb((size_t)H * H)), dim3(256), 0, st, (const uint16_t *)m->W3.p, H, H,
-                       (uint16_t *)m->W3t.p);
+    hipLaunchKernelGGL(k_w_copy<E>, dim3(nb((size_t)H * KP)), dim3(256), 0, st, p + L.W1, H, F, KP, (E *)m->W1.p);
+    hipLaunchKernelGGL(k_w_copy<E>, dim3(nb((size_t)H * H)), dim3(256), 0, st, p + L.W2, H, H, H, (E *)m->W2.p);
+    hipLaunchKernelGGL(k_w_copy<E>, dim3(nb((size_t)H * H)), dim3(256), 0, st, p + L.W3, H, H, H, (E *)m->W3.p);
+    hipLaunchKernelGGL(k_w_copy<E>, dim3(nb((size_t)H)), dim3(256), 0, st, p + L.W4, 1, H, H, (E *)m->W4.p);
+    hipLaunchKernelGGL(k_transpose<E>, dim3(nb((size_t)H * H)), dim3(256), 0, st, (const E *)m->W2.p, H, H,
+                       (E *)m->W2t.p);
+    hipLaunchKernelGGL(k_transpose<E>, dim3(nb((size_t)H * H)), dim3(256), 0, st, (const E *)m->W3.p, H, H,
+                       (E *)m->W3t.p);
     MCHK(m, hipGetLastError());
     return FFTDG_OK;
 }
 
-int gemm(fftdg_mlp *m, const uint16_t *A, int lda, const uint16_t *B, int ldb, int M, int N, int K,
-         const float *bias, int mode, float *C, int ldc, uint16_t *Hh, int ldh) {
-    hipLaunchKernelGGL(k_gemm, dim3(N / 64, M / 64), dim3(256), 0, m->stream, A, lda, B, ldb, K, bias, mode, C, ldc,
-                       Hh, ldh);
+// the working copies of the weights from the FP32 master parameters
+int refresh_w(fftdg_mlp *m) { return m->fp32 ? refresh_t<float>(m) : refresh_t<uint16_t>(m); }
+
+template <typename E>
+int gemm(fftdg_mlp *m, const E *A, int lda, const E *B, int ldb, int M, int N, int K, const float *bias, int mode,
+         float *C, int ldc, E *Hh, int ldh) {
+    hipLaunchKernelGGL(k_gemm<E>, dim3(N / 64, M / 64), dim3(256), 0, m->stream, A, lda, B, ldb, K, bias, mode, C,
+                       ldc, Hh, ldh);
     MCHK(m, hipGetLastError());
     return FFTDG_OK;
 }
 
 // forward pass over B rows (rows of X selected by idx, or the first B rows)
-int forward(fftdg_mlp *m, const float *X, const int32_t *idx, int B, int Bp) {
+template <typename E>
+int forward_t(fftdg_mlp *m, const float *X, const int32_t *idx, int B, int Bp) {
     const int H = m->width;
     const Lay L(m->n_in, H);
     const float *p = (const float *)m->P.p;
-    hipLaunchKernelGGL(k_gather, dim3(nb((size_t)Bp * KP)), dim3(256), 0, m->stream, X, m->n_in, idx, B, Bp,
-                       (uint16_t *)m->A0.p);
+    hipLaunchKernelGGL(k_gather<E>, dim3(nb((size_t)Bp * KP)), dim3(256), 0, m->stream, X, m->n_in, idx, B, Bp,
+                       (E *)m->A0.p);
     int rc;
-    if ((rc = gemm(m, (uint16_t *)m->A0.p, KP, (uint16_t *)m->W1.p, KP, Bp, H, KP, p + L.b1, 1, (float *)m->Z1.p, H,
-                   (uint16_t *)m->H1.p, H)))
+    if ((rc = gemm<E>(m, (E *)m->A0.p, KP, (E *)m->W1.p, KP, Bp, H, KP, p + L.b1, 1, (float *)m->Z1.p, H,
+                      (E *)m->H1.p, H)))
         return rc;
-    if ((rc = gemm(m, (uint16_t *)m->H1.p, H, (uint16_t *)m->W2.p, H, Bp, H, H, p + L.b2, 1, (float *)m->Z2.p, H,
-                   (uint16_t *)m->H2.p, H)))
+    if ((rc = gemm<E>(m, (E *)m->H1.p, H, (E *)m->W2.p, H, Bp, H, H, p + L.b2, 1, (float *)m->Z2.p, H, (E *)m->H2.p,
+                      H)))
         return rc;
-    if ((rc = gemm(m, (uint16_t *)m->H2.p, H, (uint16_t *)m->W3.p, H, Bp, H, H, p + L.b3, 1, (float *)m->Z3.p, H,
-                   (uint16_t *)m->H3.p, H)))
+    if ((rc = gemm<E>(m, (E *)m->H2.p, H, (E *)m->W3.p, H, Bp, H, H, p + L.b3, 1, (float *)m->Z3.p, H, (E *)m->H3.p,
+                      H)))
         return rc;
-    hipLaunchKernelGGL(k_out, dim3(nb((size_t)B)), dim3(256), 0, m->stream, (const uint16_t *)m->H3.p, H,
-                       (const uint16_t *)m->W4.p, p + L.b4, B, X, m->n_in, idx, m->skip_col, m->skip_scale,
+    hipLaunchKernelGGL(k_out<E>, dim3(nb((size_t)B)), dim3(256), 0, m->stream, (const E *)m->H3.p, H,
+                       (const E *)m->W4.p, p + L.b4, B, X, m->n_in, idx, m->skip_col, m->skip_scale,
                        (float *)m->y.p);
     MCHK(m, hipGetLastError());
     return FFTDG_OK;
 }
+int forward(fftdg_mlp *m, const float *X, const int32_t *idx, int B, int Bp) {
+    return m->fp32 ? forward_t<float>(m, X, idx, B, Bp) : forward_t<uint16_t>(m, X, idx, B, Bp);
+}
 
-int backward(fftdg_mlp *m, const float *X, const float *t, const float *w, const int32_t *idx, int B, float *g) {
+template <typename E>
+int backward_t(fftdg_mlp *m, const float *X, const float *t, const float *w, const int32_t *idx, int B, float *g) {
     const int H = m->width, F = m->n_in;
     const int Bp = (B + 63) / 64 * 64;
     const Lay L(F, H);
     hipStream_t st = m->stream;
     int rc;
-    if ((rc = forward(m, X, idx, B, Bp))) return rc;
+    if ((rc = forward_t<E>(m, X, idx, B, Bp))) return rc;
     hipLaunchKernelGGL(k_loss, dim3(1), dim3(256), 0, st, (const float *)m->y.p, t, w, idx, B, (float *)m->dy.p,
                        (float *)m->loss.p);
-    hipLaunchKernelGGL(k_out_grad, dim3(nb((size_t)H + 1)), dim3(256), 0, st, (const float *)m->dy.p,
-                       (const uint16_t *)m->H3.p, H, B, g + L.W4, g + L.b4);
+    hipLaunchKernelGGL(k_out_grad<E>, dim3(nb((size_t)H + 1)), dim3(256), 0, st, (const float *)m->dy.p,
+                       (const E *)m->H3.p, H, B, g + L.W4, g + L.b4);
     // layer 3
-    hipLaunchKernelGGL(k_dz, dim3(nb((size_t)Bp * H)), dim3(256), 0, st, (const float *)nullptr,
-                       (const float *)m->dy.p, (const uint16_t *)m->W4.p, (const float *)m->Z3.p, H, B, Bp,
-                       (float *)m->dZf.p, (uint16_t *)m->dZ.p, (uint16_t *)m->dZt.p);
+    hipLaunchKernelGGL(k_dz<E>, dim3(nb((size_t)Bp * H)), dim3(256), 0, st, (const float *)nullptr,
+                       (const float *)m->dy.p, (const E *)m->W4.p, (const float *)m->Z3.p, H, B, Bp,
+                       (float *)m->dZf.p, (E *)m->dZ.p, (E *)m->dZt.p);
     hipLaunchKernelGGL(k_colsum, dim3(nb((size_t)H)), dim3(256), 0, st, (const float *)m->dZf.p, H, B, g + L.b3);
-    hipLaunchKernelGGL(k_transpose, dim3(nb((size_t)Bp * H)), dim3(256), 0, st, (const uint16_t *)m->H2.p, Bp, H,
-                       (uint16_t *)m->H2t.p);
-    if ((rc = gemm(m, (uint16_t *)m->dZt.p, Bp, (uint16_t *)m->H2t.p, Bp, H, H, Bp, nullptr, 0, g + L.W3, H,
+    hipLaunchKernelGGL(k_transpose<E>, dim3(nb((size_t)Bp * H)), dim3(256), 0, st, (const E *)m->H2.p, Bp, H,
+                       (E *)m->H2t.p);
+    if ((rc = gemm<E>(m, (E *)m->dZt.p, Bp, (E *)m->H2t.p, Bp, H, H, Bp, nullptr, 0, g + L.W3, H,
                    nullptr, 0)))
         return rc;
-    if ((rc = gemm(m, (uint16_t *)m->dZ.p, H, (uint16_t *)m->W3t.p, H, Bp, H, H, nullptr, 0, (float *)m->dH.p, H,
+    if ((rc = gemm<E>(m, (E *)m->dZ.p, H, (E *)m->W3t.p, H, Bp, H, H, nullptr, 0, (float *)m->dH.p, H,
                    nullptr, 0)))
         return rc;
     // layer 2
-    hipLaunchKernelGGL(k_dz, dim3(nb((size_t)Bp * H)), dim3(256), 0, st, (const float *)m->dH.p,
-                       (const float *)nullptr, (const uint16_t *)nullptr, (const float *)m->Z2.p, H, B, Bp,
-                       (float *)m->dZf.p, (uint16_t *)m->dZ.p, (uint16_t *)m->dZt.p);
+    hipLaunchKernelGGL(k_dz<E>, dim3(nb((size_t)Bp * H)), dim3(256), 0, st, (const float *)m->dH.p,
+                       (const float *)nullptr, (const E *)nullptr, (const float *)m->Z2.p, H, B, Bp,
+                       (float *)m->dZf.p, (E *)m->dZ.p, (E *)m->dZt.p);
     hipLaunchKernelGGL(k_colsum, dim3(nb((size_t)H)), dim3(256), 0, st, (const float *)m->dZf.p, H, B, g + L.b2);
-    hipLaunchKernelGGL(k_transpose, dim3(nb((size_t)Bp * H)), dim3(256), 0, st, (const uint16_t *)m->H1.p, Bp, H,
-                       (uint16_t *)m->H1t.p);
-    if ((rc = gemm(m, (uint16_t *)m->dZt.p, Bp, (uint16_t *)m->H1t.p, Bp, H, H, Bp, nullptr, 0, g + L.W2, H,
+    hipLaunchKernelGGL(k_transpose<E>, dim3(nb((size_t)Bp * H)), dim3(256), 0, st, (const E *)m->H1.p, Bp, H,
+                       (E *)m->H1t.p);
+    if ((rc = gemm<E>(m, (E *)m->dZt.p, Bp, (E *)m->H1t.p, Bp, H, H, Bp, nullptr, 0, g + L.W2, H,
                    nullptr, 0)))
         return rc;
-    if ((rc = gemm(m, (uint16_t *)m->dZ.p, H, (uint16_t *)m->W2t.p, H, Bp, H, H, nullptr, 0, (float *)m->dH.p, H,
+    if ((rc = gemm<E>(m, (E *)m->dZ.p, H, (E *)m->W2t.p, H, Bp, H, H, nullptr, 0, (float *)m->dH.p, H,
                    nullptr, 0)))
         return rc;
     // layer 1 (no input gradient)
-    hipLaunchKernelGGL(k_dz, dim3(nb((size_t)Bp * H)), dim3(256), 0, st, (const float *)m->dH.p,
-                       (const float *)nullptr, (const uint16_t *)nullptr, (const float *)m->Z1.p, H, B, Bp,
-                       (float *)m->dZf.p, (uint16_t *)m->dZ.p, (uint16_t *)m->dZt.p);
+    hipLaunchKernelGGL(k_dz<E>, dim3(nb((size_t)Bp * H)), dim3(256), 0, st, (const float *)m->dH.p,
+                       (const float *)nullptr, (const E *)nullptr, (const float *)m->Z1.p, H, B, Bp,
+                       (float *)m->dZf.p, (E *)m->dZ.p, (E *)m->dZt.p);
     hipLaunchKernelGGL(k_colsum, dim3(nb((size_t)H)), dim3(256), 0, st, (const float *)m->dZf.p, H, B, g + L.b1);
-    hipLaunchKernelGGL(k_transpose, dim3(nb((size_t)Bp * KP)), dim3(256), 0, st, (const uint16_t *)m->A0.p, Bp, KP,
-                       (uint16_t *)m->A0t.p);
-    if ((rc = gemm(m, (uint16_t *)m->dZt.p, Bp, (uint16_t *)m->A0t.p, Bp, H, KP, Bp, nullptr, 0,
+    hipLaunchKernelGGL(k_transpose<E>, dim3(nb((size_t)Bp * KP)), dim3(256), 0, st, (const E *)m->A0.p, Bp, KP,
+                       (E *)m->A0t.p);
+    if ((rc = gemm<E>(m, (E *)m->dZt.p, Bp, (E *)m->A0t.p, Bp, H, KP, Bp, nullptr, 0,
                    (float *)m->gtmp.p, KP, nullptr, 0)))
         return rc;
     hipLaunchKernelGGL(k_copy_cols, dim3(nb((size_t)H * F)), dim3(256), 0, st, (const float *)m->gtmp.p, H, KP, F,
@@ -444,15 +491,24 @@ int backward(fftdg_mlp *m, const float *X, const float *t, const float *w, const
     MCHK(m, hipGetLastError());
     return FFTDG_OK;
 }
+int backward(fftdg_mlp *m, const float *X, const float *t, const float *w, const int32_t *idx, int B, float *g) {
+    return m->fp32 ? backward_t<float>(m, X, t, w, idx, B, g) : backward_t<uint16_t>(m, X, t, w, idx, B, g);
+}
 
 }  // namespace
 
 extern "C" {
 
 int fftdg_mlp_create(fftdg_mlp **out, int device, void *stream, int32_t n_in, int32_t width, int32_t max_batch) {
+    return fftdg_mlp_create_ex(out, device, stream, n_in, width, max_batch, 0);
+}
+
+int fftdg_mlp_create_ex(fftdg_mlp **out, int device, void *stream, int32_t n_in, int32_t width, int32_t max_batch,
+                        int32_t fp32_operands) {
     if (!out) return FFTDG_E_INVALID;
     *out = nullptr;
-    if (n_in < 1 || n_in > KP || width < 64 || width % 64 || width > 1024 || max_batch < 1 || max_batch > (1 << 22))
+    if (n_in < 1 || n_in > KP || width < 64 || width % 64 || width > 1024 || max_batch < 1 || max_batch > (1 << 22) ||
+        (fp32_operands != 0 && fp32_operands != 1))
         return FFTDG_E_INVALID;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0) {
@@ -471,6 +527,7 @@ int fftdg_mlp_create(fftdg_mlp **out, int device, void *stream, int32_t n_in, in
     m->n_in = n_in;
     m->width = width;
     m->max_batch = max_batch;
+    m->fp32 = fp32_operands != 0;
     m->Bmax = (max_batch + 63) / 64 * 64;
     const Lay L(n_in, width);
     m->np = L.n;
@@ -479,7 +536,7 @@ int fftdg_mlp_create(fftdg_mlp **out, int device, void *stream, int32_t n_in, in
     Buf *f32n[] = {&m->P, &m->G, &m->Mm, &m->Vv};
     for (Buf *b : f32n)
         if (!rc) rc = balloc(m, *b, sizeof(float) * L.n);
-    const size_t bf = sizeof(uint16_t);
+    const size_t bf = m->fp32 ? sizeof(float) : sizeof(uint16_t);  // operand element
     if (!rc) rc = balloc(m, m->W1, bf * H * KP);
     if (!rc) rc = balloc(m, m->W2, bf * H * H);
     if (!rc) rc = balloc(m, m->W3, bf * H * H);
@@ -510,7 +567,7 @@ int fftdg_mlp_create(fftdg_mlp **out, int device, void *stream, int32_t n_in, in
         fftdg_mlp_destroy(m);
         return FFTDG_E_DEVICE;
     }
-    if ((rc = refresh_bf16(m)) || hipStreamSynchronize(m->stream) != hipSuccess) {
+    if ((rc = refresh_w(m)) || hipStreamSynchronize(m->stream) != hipSuccess) {
         fftdg_mlp_destroy(m);
         return rc ? rc : FFTDG_E_DEVICE;
     }
@@ -543,7 +600,7 @@ int fftdg_mlp_set_params(fftdg_mlp *m, const float *p_host, int64_t n) {
     MCHK(m, hipMemcpyAsync(m->Mm.p, zero.data(), sizeof(float) * n, hipMemcpyHostToDevice, m->stream));
     MCHK(m, hipMemcpyAsync(m->Vv.p, zero.data(), sizeof(float) * n, hipMemcpyHostToDevice, m->stream));
     m->step = 0;
-    int rc = refresh_bf16(m);
+    int rc = refresh_w(m);
     if (rc) return rc;
     MCHK(m, hipStreamSynchronize(m->stream));
     return FFTDG_OK;
@@ -608,7 +665,7 @@ int fftdg_mlp_train_step(fftdg_mlp *m, const float *x_all, const float *t_all, c
                        (const float *)m->G.p, (float *)m->Mm.p, (float *)m->Vv.p, (int)m->np, lr, b1, b2, 1e-8f, c1,
                        c2);
     MCHK(m, hipGetLastError());
-    if ((rc = refresh_bf16(m))) return rc;
+    if ((rc = refresh_w(m))) return rc;
     if (loss_host) {
         MCHK(m, hipMemcpyAsync(loss_host, m->loss.p, sizeof(float), hipMemcpyDeviceToHost, m->stream));
         MCHK(m, hipStreamSynchronize(m->stream));

@@ -5,6 +5,8 @@ numpy computation.
 
 Tolerances: BF16 operands carry 8 significant bits, so forward outputs and
 gradients are compared normwise (relative <= 2e-2, cosine >= 0.999); the
+FP32 instantiation of the same kernels to FP32 rounding (relative <= 1e-5);
+the
 sampler's q is FP64 (relative 1e-12) and its indices are exact except where a
 uniform falls within 1e-12 of a CDF boundary."""
 import math
@@ -80,6 +82,36 @@ def test_gradient_matches_oracle(B):
         for blk in (W.ravel().astype(int), b.astype(int)):
             a, r = g[blk], gr[blk]
             assert np.linalg.norm(a - r) <= 3e-2 * np.linalg.norm(r) + 1e-7
+
+
+@pytest.mark.parametrize("B", [64, 333])
+def test_fp32_instantiation_matches_oracle_to_fp32_rounding(B):
+    """The same network with FP32 operands and activations
+    (fftdg_mlp_create_ex): forward, loss and gradients against the FP64
+    oracle on the same FP32-rounded inputs, normwise relative <= 1e-5 (FP32
+    rounding of 256-term products and B-row sums, ~1e-6), every block of the
+    layout within 1e-4 of its own norm."""
+    import paper_1708_07045_amd as fd
+    net = fd.Network(N_IN, WIDTH, 1024, fp32=True)
+    p = _params(5)
+    net.set_params(p)
+    X, t, w = _data(B, seed=B)
+    p64 = p.astype(np.float32).astype(np.float64)
+    X32 = X.astype(np.float32).astype(np.float64)
+    y = net.forward(X).cpu().numpy().astype(np.float64)
+    yr = omlp.forward(p64, X32, N_IN, WIDTH)
+    assert np.linalg.norm(y - yr) <= 1e-5 * np.linalg.norm(yr)
+    loss, g = net.grad(X, t, w)
+    g = g.cpu().numpy().astype(np.float64)
+    Lr, gr = omlp.grad(p64, X32, t.astype(np.float32), w.astype(np.float32), N_IN, WIDTH)
+    assert loss == pytest.approx(Lr, rel=1e-5)
+    rel = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    assert rel <= 1e-5, rel
+    lay = omlp.unpack(np.arange(p.size, dtype=np.float64), N_IN, WIDTH)
+    for W, b in lay:
+        for blk in (W.ravel().astype(int), b.astype(int)):
+            a, r = g[blk], gr[blk]
+            assert np.linalg.norm(a - r) <= 1e-4 * np.linalg.norm(r) + 1e-9 * np.linalg.norm(gr)
 
 
 def test_skip_connection_matches_oracle():
