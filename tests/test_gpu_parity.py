@@ -321,18 +321,22 @@ def test_scan_batched_uneven_ligands_three_snapshots_fused(fused, chunk):
     assert P.shape[0] == 3
 
 
-@pytest.mark.parametrize("fused", [1, 2])
-def test_clash_stream_matches_one_stream(fused):
-    """The clash test on the second stream (next item beside the current z
-    pass and inverse, double-buffered results, event-ordered) gives the same
-    partials bit for bit as one stream, eagerly and as a captured graph
-    replayed several times with eager work and synchronizations between
-    replays; ragged three-snapshot batch, chunks of 5 (many items)."""
+@pytest.mark.parametrize("fused,snap_pass", [(1, 1), (2, 1), (0, 1), (0, 3)])
+def test_clash_stream_matches_one_stream(fused, snap_pass):
+    """The second stream (fused path: the clash test of the next item beside
+    the current z pass and inverse; plane path: the inverse of one z pass
+    beside the next; double-buffered, event-ordered) gives the same partials
+    bit for bit as one stream, eagerly and as a captured graph replayed
+    several times with eager work and synchronizations between replays;
+    ragged three-snapshot batch, chunks of 5 (many items)."""
     import torch
     w = synth.config3(n_ligands=5, n_snap=3, cfg_scale=0.02)
-    ctx, grids, occ = _gpu_setup(w, fused=fused, configs_per_chunk=5, clash_stream=0, use_graph=0)
+    tun = dict(fused=fused, configs_per_chunk=5, clash_stream=0, use_graph=0)
+    if fused == 0:
+        tun.update(snapshots_per_pass=snap_pass, energy_xy_direct=0)
+    ctx, grids, occ = _gpu_setup(w, **tun)
     b = _batch(w)
-    _announce(f"clash stream vs one stream: fused={fused} n_cfg={b.n_cfg} n_snap=3")
+    _announce(f"second stream vs one stream: fused={fused} snapshots per pass {snap_pass} n_cfg={b.n_cfg} n_snap=3")
     ref = ctx.scan(b, w.T).cpu().numpy()
     ctx.set_tuning(clash_stream=1)
     np.testing.assert_array_equal(ctx.scan(b, w.T).cpu().numpy(), ref)
