@@ -333,6 +333,48 @@ def batched_timing(reps: int = 3):
             "dG_mean_kcal_mol": float(np.mean(res["dG"]))}
 
 
+def mlp_rates(X, t, wt, rows, train_batch: int = 512, reps: int = 5):
+    """Proposal-network throughput in samples per second on a throwaway
+    network of the proposal's shape (residual form, width 256): forward
+    over every row of X in blocks of 512 (the batch the proposal predicts
+    with) and of 4096, and Adam training steps of train_batch rows.  HIP
+    events on the network's stream (torch's current stream); median of
+    reps after one untimed pass."""
+    import numpy as np
+    import torch
+    from paper_1708_07045_amd import proposal as prop
+
+    def timed(fn):
+        fn()
+        ms = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms))
+
+    n = int(X.shape[0])
+    out = {"rows": n, "n_in": int(X.shape[1]), "width": 256}
+    for mb in (512, 4096):
+        net = prop.make_network(int(X.shape[1]), 256, residual=True, max_batch=mb)
+        out[f"forward_samples_per_s_block{mb}"] = n / (timed(lambda: net.forward(X)) * 1e-3)
+        if mb == train_batch:
+            steps = max(1, min(rows.size // train_batch, 64))
+            idx = torch.as_tensor(np.asarray(rows[:steps * train_batch], np.int32), device=X.device)
+
+            def train():
+                for k in range(steps):
+                    net.train_step(X, t, wt, idx[k * train_batch:(k + 1) * train_batch], 1e-3)
+
+            out["train_samples_per_s"] = steps * train_batch / (timed(train) * 1e-3)
+            out["train_batch"] = train_batch
+        net.close()
+    return out
+
+
 def configs_needed(args, fine_tuning=None):
     """Configurations a BPMF estimate needs for +-0.1 kcal/mol in every
     snapshot, plain uniform sampling vs the learned proposal, on the batched
@@ -448,6 +490,9 @@ def configs_needed(args, fine_tuning=None):
         log(f"{name}: {args.is_epochs} epochs on {rows.size} rows in {t_train[name]:.1f}s (with validation), "
             f"last batch loss {keep['loss']:.4f}; kept epoch {keep['epoch']}")
     log(f"plans (mixture temperature in nats, exact share) chosen on validation ligands: {tau_of}")
+    mlp = mlp_rates(X, t, wt, rows)
+    log(f"proposal network: forward {mlp['forward_samples_per_s_block512']:.3g} samples/s (blocks of 512), "
+        f"{mlp['forward_samples_per_s_block4096']:.3g} (4096); training {mlp['train_samples_per_s']:.3g} samples/s")
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([170807045, 21])))
     per = []
     for l in test_l:
@@ -461,9 +506,14 @@ def configs_needed(args, fine_tuning=None):
             extra = float(extra_cfg[b.cfg_off[l]:b.cfg_off[l + 1]].sum()) if name in ("net_scan", "coarse") else 0.0
             row[name] = min(float(Pl), k + extra)
             row[name + "_budget"] = bf
+        # gain test: the network's plan with its proposal replaced by a
+        # uniform one (no pre-scan, so no extra cost)
+        k, bf = prop.kstar_is(prop.sub_batch(w, l), Zs, np.zeros(Pl, np.float32), alpha, tau_of["net_scan"][0],
+                              kT, 2000 + int(l), reps=args.is_reps, exact_share=tau_of["net_scan"][1])
+        row["uniform"], row["uniform_budget"] = min(float(Pl), k), bf
         per.append(row)
         log(f"ligand {l}: P={Pl} plain {row['plain']:.0f}  net_scan {row['net_scan']:.0f}  "
-            f"coarse {row['coarse']:.0f}  net_cfg {row['net_cfg']:.0f}")
+            f"coarse {row['coarse']:.0f}  net_cfg {row['net_cfg']:.0f}  uniform {row['uniform']:.0f}")
     med = lambda key: float(np.median([r["plain"] / r[key] for r in per]))
     # one real importance-sampled scan of the held-out ligands at 10 % of
     # the configurations (exact top and draws split as the plan chosen on the
@@ -519,9 +569,13 @@ def configs_needed(args, fine_tuning=None):
         "epochs_kept": epochs_of,
         "validation_mean_fraction": val_of,
         "train_seconds": t_train,
-        "median_plain_over": {"net_scan": med("net_scan"), "net_cfg": med("net_cfg"), "coarse": med("coarse")},
+        "network_throughput": mlp,
+        "median_plain_over": {"net_scan": med("net_scan"), "net_cfg": med("net_cfg"), "coarse": med("coarse"),
+                              "uniform": med("uniform")},
         "median_fraction_of_pool": {k: float(np.median([r[k] / r["n_cfg"] for r in per]))
-                                    for k in ("plain", "net_scan", "net_cfg", "coarse")},
+                                    for k in ("plain", "net_scan", "net_cfg", "coarse", "uniform")},
+        "gain_test": "uniform: the net_scan plan (temperature, exact share) with a uniform proposal in place "
+                     "of the network",
         "is_run_10pct": is_runs["net_scan"],
         "is_run_10pct_coarse": is_runs["coarse"],
         "per_ligand": per,
