@@ -635,7 +635,10 @@ def main():
                     help="clash handling of the coarse pre-scan: capped repulsion (one inverse channel; default) "
                          "or occupancy exclusion (as the fine scan)")
     args = ap.parse_args()
-    args.is_exact_shares = [float(x) for x in args.is_exact_shares.split(",")]
+    try:
+        args.is_exact_shares = [float(x) for x in args.is_exact_shares.split(",")]
+    except ValueError:
+        args.is_exact_shares = []
     if not args.is_exact_shares or any(not 0.0 <= x < 1.0 for x in args.is_exact_shares):
         ap.error("--is-exact-shares: comma-separated fractions in [0, 1)")
     args.is_coarse_snapshots = {"mean": "mean", "all": None, "half": "half", "first": [0],

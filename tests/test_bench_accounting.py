@@ -81,3 +81,22 @@ def test_committed_traffic_profile_is_parsable(bench):
             rec[k.strip()] = v.strip().strip("`")
     assert float(rec["hbm_bytes_per_cfg"]) > 1e6
     assert len(rec["kernel_source_sha256"]) == 64
+
+
+def test_more_than_one_gpu_is_refused_before_any_work():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=60)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and not r.stdout
+
+
+@pytest.mark.parametrize("shares", ["1.0", "0.5,-0.1", ""])
+def test_exact_shares_outside_unit_interval_are_rejected(shares):
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--is-exact-shares", shares],
+                       capture_output=True, text=True, timeout=60)
+    assert r.returncode == 2
+    assert "--is-exact-shares" in r.stderr and not r.stdout
