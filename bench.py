@@ -46,10 +46,10 @@ def zpass_flops(n_fft: int, n_in: int, n_out: int, occ_product: bool, n_cfg: int
     return float(n_cfg) * pencils * (n_in * t * passes + n_snap * (n_out * t + N * (24 + (6 if occ_product else 0))))
 
 
-def s8d_bytes_per_cfg(P, n_fft: int, occ: bool, B_rc: int) -> float:
-    """Algorithmic bytes per configuration of the scan as the survey's
-    measurement section defines them (what the method must move when a 3D FFT
-    does not fit one CU's LDS): 16 N (N/2 + 1) (n_in L_z + n_out V_z) + 8 S_h
+def pruned_bytes_per_cfg(P, n_fft: int, occ: bool, B_rc: int) -> float:
+    """Algorithmic bytes per configuration of the scan in the pruned-transform
+    traffic model (what the method must move when a 3D FFT does not fit one
+    CU's LDS): 16 N (N/2 + 1) (n_in L_z + n_out V_z) + 8 S_h
     n_rc / B_rc, with n_in = n_rc = 4, n_out = 2 in occupancy mode (3, 1 in
     cap mode), L_z = B_z + 1 and V_z from this workload's placements, S_h =
     N^2 (N/2 + 1) and B_rc configurations per receptor read.  Evaluated over
@@ -280,7 +280,7 @@ def batched_timing(reps: int = 3):
     exhaustively under the autotuned schedule: the median of `reps` scans
     timed with HIP events on the library's stream (receptor spectra built
     beforehand), the per-kernel table of one more, profiled, scan, and the
-    survey's per-configuration bytes at that rate."""
+    pruned-transform model's bytes per configuration at that rate."""
     import numpy as np
     import torch
     import paper_1708_07045_amd as fd
@@ -320,8 +320,8 @@ def batched_timing(reps: int = 3):
     med = float(np.median(ms))
     scans = b.n_cfg * S
     boxes = ctx.boxes(b)
-    s8d = s8d_bytes_per_cfg({"box_z": boxes[:, 2], "V_z": np.maximum(w.n_rec - boxes[:, 2], 0)}, w.n_fft,
-                            w.clash_mode == "occ", tun["configs_per_chunk"])
+    pb = pruned_bytes_per_cfg({"box_z": boxes[:, 2], "V_z": np.maximum(w.n_rec - boxes[:, 2], 0)}, w.n_fft,
+                              w.clash_mode == "occ", tun["configs_per_chunk"])
     rate = scans / (med / 1e3)
     B, res = ctx.reduce(b, out, w.T)
     return {"workload": f"batched: {len(w.ligands)} ligands of 8-40 atoms, {b.n_cfg} configurations, {S} jittered "
@@ -329,7 +329,7 @@ def batched_timing(reps: int = 3):
             "tuning": tun, "scan_ms": ms, "scan_ms_median": med, "scans_per_s": rate,
             "configs_per_s": b.n_cfg / (med / 1e3),
             "kernels_ms": {k: v[0] for k, v in prof.items() if v[1] > 0},
-            "s8d_bytes_per_scan": s8d, "s8d_GBps": s8d * rate / 1e9, "s8d_frac_of_peak": s8d * rate / 1e9 / HBM_PEAK_GBS,
+            "pruned_bytes_per_scan": pb, "pruned_GBps": pb * rate / 1e9, "pruned_frac_of_peak": pb * rate / 1e9 / HBM_PEAK_GBS,
             "dG_mean_kcal_mol": float(np.mean(res["dG"]))}
 
 
@@ -771,17 +771,17 @@ def main():
                          "avg_launch_us": 1e3 * ms / n, "alg_GBps": (b / 1e9) / (ms / 1e3) if ms > 0 else None,
                          "alg_bytes_per_launch": b / n}
     boxes = ctx.boxes(batch)
-    s8d = s8d_bytes_per_cfg({"box_z": boxes[:, 2], "V_z": np.maximum(w.n_rec - boxes[:, 2], 0)}, w.n_fft,
-                            w.clash_mode == "occ", tun["configs_per_chunk"])
+    pb = pruned_bytes_per_cfg({"box_z": boxes[:, 2], "V_z": np.maximum(w.n_rec - boxes[:, 2], 0)}, w.n_fft,
+                              w.clash_mode == "occ", tun["configs_per_chunk"])
     # Roofline.  The unit is one scan (every configuration of the batch
     # against every snapshot): on the fused path no single kernel moves the
     # method's data and the clash test runs on a second stream beside the z
-    # pass, so the survey's algorithmic bytes per configuration-snapshot scan
-    # (s8d) are rated against the scan's GPU time, HIP events on the
+    # pass, so the pruned-transform model's algorithmic bytes per
+    # configuration-snapshot scan are rated against the scan's GPU time, HIP events on the
     # library's stream around each timed scan (median).
     scan_med = float(np.median(scan_ms))
     scans = n_cfg * n_snap
-    achieved = s8d * scans / (scan_med * 1e-3) / 1e9
+    achieved = pb * scans / (scan_med * 1e-3) / 1e9
     traffic = None
     if args.workload == "c2":
         per_cfg = recorded_traffic(tun)
@@ -812,8 +812,8 @@ def main():
                 " (clash test on a second stream)" if tun.get("clash_stream") and fused else ""),
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": traffic,
-            "per_unit": "survey algorithmic bytes per configuration-snapshot scan (s8d_bytes_per_cfg) x scans",
-            "alg_bytes_per_launch": s8d * scans, "avg_launch_us": 1e3 * scan_med,
+            "per_unit": "pruned-transform algorithmic bytes per configuration-snapshot scan (pruned_bytes_per_cfg) x scans",
+            "alg_bytes_per_launch": pb * scans, "avg_launch_us": 1e3 * scan_med,
             "scan_ms": scan_ms, "copy_GBps": copy_gbps, "frac_of_copy": achieved / copy_gbps,
             "profiled_kernels_sum_ms": seq_ms,
             "note": "one launch = one scan; its kernels' profiled times (one stream, no overlap) sum to "
@@ -856,9 +856,9 @@ def main():
         "path_alg_GBps": path_bytes / (ms_step / 1e3) / 1e9,
         "path_frac_of_peak": path_bytes / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
         "path_frac_of_copy": path_bytes / (ms_step / 1e3) / 1e9 / copy_gbps,
-        "s8d_bytes_per_cfg": s8d,
-        "s8d_GBps": s8d * cfg_s * n_snap / 1e9,
-        "s8d_frac_of_peak": s8d * cfg_s * n_snap / 1e9 / HBM_PEAK_GBS,
+        "pruned_bytes_per_cfg": pb,
+        "pruned_GBps": pb * cfg_s * n_snap / 1e9,
+        "pruned_frac_of_peak": pb * cfg_s * n_snap / 1e9 / HBM_PEAK_GBS,
         "roofline": roof,
         "kernels": kernels,
         "precision": precision_vs_oracle(args, result),

@@ -464,8 +464,8 @@ int fftdg_mlp_create(fftdg_mlp **out, int device, void *hip_stream, int32_t n_in
 /* The same network with a choice of operand type: fp32_operands = 0 is
  * fftdg_mlp_create (BF16 operands and activations); 1 keeps operands and
  * activations in FP32 (GEMMs on FP32 MFMA, FP32 accumulation throughout),
- * for checking gradients against an FP64 reference to FP32 rounding (the
- * survey's FP32-instantiated gradient pin); twice the activation memory.
+ * for checking gradients against an FP64 reference to FP32 rounding;
+ * twice the activation memory.
  * E_INVALID for any other value, as for fftdg_mlp_create's arguments. */
 int fftdg_mlp_create_ex(fftdg_mlp **out, int device, void *hip_stream, int32_t n_in, int32_t width,
                         int32_t max_batch, int32_t fp32_operands);

@@ -41,17 +41,17 @@ def test_zpass_flops_count(bench):
     assert one_pass == pytest.approx(per_snap - 3 * pencils * 4 * t)
 
 
-def test_s8d_bytes_per_configuration(bench):
+def test_pruned_bytes_per_configuration(bench):
     """16 N (N/2+1) (n_in L_z + n_out V_z) + 8 S_h n_rc / B_rc, worked by hand
     for one configuration: N = 128, box_z = 37 (L_z = 38), V_z = 59,
     occupancy mode (n_in = n_rc = 4, n_out = 2), B_rc = 16."""
     nh = 128 * 65
     want = 16 * nh * (4 * 38 + 2 * 59) + 8 * 128 * nh * 4 / 16
     assert want == pytest.approx(35_942_400.0 + 2_129_920.0)
-    got = bench.s8d_bytes_per_cfg({"box_z": [37], "V_z": [59]}, 128, True, 16)
+    got = bench.pruned_bytes_per_cfg({"box_z": [37], "V_z": [59]}, 128, True, 16)
     assert got == pytest.approx(want)
     # cap mode: 3 input channels, 1 output; the mean over configurations
-    two = bench.s8d_bytes_per_cfg({"box_z": [37, 41], "V_z": [59, 55]}, 128, False, 16)
+    two = bench.pruned_bytes_per_cfg({"box_z": [37, 41], "V_z": [59, 55]}, 128, False, 16)
     a = 16 * nh * (3 * 38 + 59) + 8 * 128 * nh * 3 / 16
     b = 16 * nh * (3 * 42 + 55) + 8 * 128 * nh * 3 / 16
     assert two == pytest.approx((a + b) / 2)
