@@ -773,10 +773,14 @@ int run_plan(fftdg_ctx *ctx, const fftdg_batch *b, const Plan &P, double T_K, ff
         if ((rc = reserve(ctx, ctx->scnt, sizeof(int32_t) * e_cfgs * nsets))) return rc;
     }
     if (overlap && !ctx->side) {
-        HIPCHK(ctx, hipStreamCreateWithFlags(&ctx->side, hipStreamNonBlocking));
+        // the events first: the stream is set only once all of them exist,
+        // so a failed attempt leaves nothing half made for the next call
         for (hipEvent_t *e : {&ctx->ev_fork, &ctx->ev_join, &ctx->ev_side[0], &ctx->ev_side[1], &ctx->ev_main[0],
                               &ctx->ev_main[1]})
-            HIPCHK(ctx, hipEventCreateWithFlags(e, hipEventDisableTiming));
+            if (!*e) HIPCHK(ctx, hipEventCreateWithFlags(e, hipEventDisableTiming));
+        hipStream_t side = nullptr;
+        HIPCHK(ctx, hipStreamCreateWithFlags(&side, hipStreamNonBlocking));
+        ctx->side = side;
     }
     // snapshots whose inverse planes share the workspace: the z kernel keeps
     // a configuration's forward spectra in registers across the group
@@ -1522,6 +1526,11 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
         ctx->fused = t.fused;
         ctx->clash_stream = t.clash_stream != 0;
     };
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+        if (e0) (void)hipEventDestroy(e0);
+        return set_err(ctx, FFTDG_E_DEVICE, "autotune: hipEventCreate failed");
+    }
     const bool prof = ctx->prof;
     ctx->prof = false;
     std::vector<fftdg_tuning> cand;
@@ -1540,9 +1549,6 @@ int fftdg_autotune(fftdg_ctx *ctx, const fftdg_batch *b, double T_K, int32_t max
                     for (int cs : {0, 1})
                         if (ed != 1 || ctx->g.n_fft <= 128) cand.push_back(fftdg_tuning{chunk, ed, sp, gr, 0, cs});
     }
-    hipEvent_t e0 = nullptr, e1 = nullptr;
-    HIPCHK(ctx, hipEventCreate(&e0));
-    HIPCHK(ctx, hipEventCreate(&e1));
     double best = INFINITY;
     fftdg_tuning bt = keep;
     int err = FFTDG_OK;
