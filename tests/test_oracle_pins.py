@@ -96,6 +96,27 @@ def test_placement_matches_quaternion_sandwich():
         assert list(box) == bb or np.max(np.abs(u - np.array(ub))) > 0
 
 
+def test_rotation_convention_closed_forms():
+    """Active rotation by the unit quaternion (cos t/2, sin t/2 n): a quarter
+    turn about z takes x to y and y to -x; q and -q, and any positive
+    multiple of q, rotate alike; a half turn about x negates y and z."""
+    s = math.sqrt(0.5)
+    qz = [s, 0.0, 0.0, s]
+    np.testing.assert_allclose(brute.quat_rotate(qz, [1.0, 0.0, 0.0]), [0.0, 1.0, 0.0], atol=1e-15)
+    np.testing.assert_allclose(brute.quat_rotate(qz, [0.0, 1.0, 0.0]), [-1.0, 0.0, 0.0], atol=1e-15)
+    np.testing.assert_allclose(brute.quat_rotate([-3 * s, 0.0, 0.0, -3 * s], [0.3, -2.0, 1.5]),
+                               brute.quat_rotate(qz, [0.3, -2.0, 1.5]), atol=1e-14)
+    np.testing.assert_allclose(brute.quat_rotate([0.0, 1.0, 0.0, 0.0], [0.5, 2.0, -1.0]), [0.5, -2.0, 1.0],
+                               atol=1e-15)
+    # the C oracle places by the same convention: a two-atom rod along x,
+    # turned a quarter about z, lies along y (3 A = 12 spacings at 0.25 A)
+    rod = np.array([[0.0, 0.0, 0.0], [3.0, 0.0, 0.0]])
+    u, box = oracle.place(rod, np.array(qz), 0.25)
+    np.testing.assert_allclose(np.sort(u[:, 1]), [2.0, 14.0], atol=2.0 ** -16)
+    np.testing.assert_allclose(u[:, [0, 2]], 2.0, atol=2.0 ** -16)
+    assert list(box) == [4, 16, 4]
+
+
 def test_placement_invariants():
     c = json.load(open(GOLD))
     margin = c["placement_margin_spacings"]["value"]
