@@ -25,8 +25,8 @@ METRIC = "ligand configs/sec (FFT scan) + configs needed for BPMF ±0.1 kcal/mol
 HBM_PEAK_GBS = 8000.0
 # FP32 vector peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2 flops (FMA) x
 # 2 (packed FP32, two FMAs per lane per cycle) x 2.4 GHz = 157.3 TFLOP/s.
-# This build keeps packed-FP32 instructions out of its kernels, so half of
-# it, 78.6 TFLOP/s, is the rate its instructions can issue at.
+# The library is compiled without packed-FP32 instructions, so half of it,
+# 78.6 TFLOP/s, is the rate its kernels' instructions can issue at.
 VALU_FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2 * 2 * 2.4e9 / 1e12
 VALU_FP32_NONPACKED_TFLOPS = VALU_FP32_PEAK_TFLOPS / 2
 
