@@ -369,7 +369,7 @@ def mlp_rates(X, t, wt, rows, train_batch: int = 512, reps: int = 5):
                 for k in range(steps):
                     net.train_step(X, t, wt, idx[k * train_batch:(k + 1) * train_batch], 1e-3)
 
-            out["train_samples_per_s"] = steps * train_batch / (timed(train) * 1e-3)
+            out["train_samples_per_s"] = int(idx.shape[0]) / (timed(train) * 1e-3)
             out["train_batch"] = train_batch
         net.close()
     return out
