@@ -162,16 +162,26 @@ class Batch:
         self.conf_xyz = cat([L.conformers.reshape(-1, 3) for L in ligands], np.float64)
         self.cfg_conf = cat([L.cfg_conf for L in ligands], np.int32)
         self.cfg_quat = cat([L.cfg_quat for L in ligands], np.float64)
-        self.select = None if select is None else np.ascontiguousarray(select, np.uint8)
         self.n_cfg = int(self.cfg_off[-1])
+        self.select = self._select_array(select)
         self.c = BatchC(n_lig, _ptr(self.atom_off), _ptr(self.conf_off), _ptr(self.cfg_off), _ptr(self.q),
                         _ptr(self.sigma), _ptr(self.eps), _ptr(self.conf_xyz), _ptr(self.cfg_conf),
                         _ptr(self.cfg_quat), _ptr(self.select))
 
+    def _select_array(self, select):
+        """cfg_select: one byte per configuration of the batch (the library
+        reads n_cfg of them), or None."""
+        if select is None:
+            return None
+        a = np.ascontiguousarray(select, np.uint8).reshape(-1)
+        if a.size != self.n_cfg:
+            raise ValueError(f"select has {a.size} entries, the batch {self.n_cfg} configurations")
+        return a
+
     def with_select(self, select: Optional[np.ndarray]) -> "Batch":
         b = object.__new__(Batch)
         b.__dict__.update(self.__dict__)
-        b.select = None if select is None else np.ascontiguousarray(select, np.uint8)
+        b.select = self._select_array(select)
         b.c = BatchC(*[getattr(self.c, f) for f, _ in BatchC._fields_])
         b.c.cfg_select = _ptr(b.select)
         return b

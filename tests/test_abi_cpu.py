@@ -103,3 +103,25 @@ def test_calls_with_null_context():
     assert L.fftdg_set_receptors(None, 1, None, None, None) == fd._lib.E_INVALID
     assert L.fftdg_last_error(None) == b"context is NULL"
     L.fftdg_destroy(None)
+
+
+def test_batch_offsets_and_select_length():
+    """The binding lays a batch out as CSR offsets over ligands and takes a
+    selection only with one byte per configuration (the library reads that
+    many)."""
+    import numpy as np
+    import paper_1708_07045_amd as fd
+    from workload import synth
+    rng = np.random.default_rng(3)
+    ligs = [synth.make_ligand(rng, rng, na, nc, nr) for na, nc, nr in ((3, 2, 4), (5, 1, 0), (2, 3, 1))]
+    b = fd.Batch(ligs)
+    np.testing.assert_array_equal(b.atom_off, [0, 3, 8, 10])
+    np.testing.assert_array_equal(b.conf_off, [0, 2, 3, 6])
+    np.testing.assert_array_equal(b.cfg_off, [0, 8, 8, 11])
+    assert b.n_cfg == 11 and b.conf_xyz.shape == (3 * 2 + 5 + 2 * 3, 3)
+    assert b.with_select(np.ones(11, np.uint8)).select.size == 11
+    for bad in (np.ones(10, np.uint8), np.ones(12, np.uint8)):
+        with pytest.raises(ValueError):
+            fd.Batch(ligs, bad)
+        with pytest.raises(ValueError):
+            b.with_select(bad)
