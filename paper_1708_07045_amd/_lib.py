@@ -314,10 +314,22 @@ class FFTDG:
         return self.torch.empty(self.n_snap * batch.n_cfg * PARTIAL_DTYPE.itemsize, dtype=self.torch.uint8,
                                 device=self.device)
 
+    def _partials_ok(self, buf, batch: Batch):
+        """The library reads or writes n_snap * n_cfg fftdg_partial records
+        through this pointer: a contiguous tensor on this context's device
+        holding at least that many bytes."""
+        t = self.torch
+        need = self.n_snap * batch.n_cfg * PARTIAL_DTYPE.itemsize
+        if (not t.is_tensor(buf) or buf.device != self.device or not buf.is_contiguous()
+                or buf.numel() * buf.element_size() < need):
+            raise ValueError(f"partials: need a contiguous tensor on {self.device} of at least {need} bytes")
+        return buf
+
     def scan(self, batch: Batch, T: float, out=None):
         """Partials [n_snap * n_cfg] (device bytes of fftdg_partial)."""
         if out is None:
             out = self.alloc_partials(batch)
+        self._partials_ok(out, batch)
         self._check(self.L.fftdg_scan(self.h_ctx, ctypes.byref(batch.c), float(T), _ptr(out)))
         return out
 
@@ -368,6 +380,7 @@ class FFTDG:
         t = self.torch
         assert feat.dtype == t.float32 and feat.dim() == 2 and feat.is_contiguous()
         assert feat.shape[0] == batch.n_cfg
+        self._partials_ok(partials, batch)
         self._check(self.L.fftdg_scan_features(self.h_ctx, ctypes.byref(batch.c), _ptr(partials), _ptr(feat),
                                                int(feat.shape[1]), int(col0)))
         return feat
@@ -385,6 +398,7 @@ class FFTDG:
         cfg = np.zeros(K, np.int32)
         t = np.zeros((K, 3), np.int32)
         psi = np.zeros(K, np.float64)
+        self._partials_ok(partials, batch)
         self._check(self.L.fftdg_sample_poses(self.h_ctx, ctypes.byref(batch.c), _ptr(partials), int(lig), int(snap),
                                               float(T), K, _ptr(u), _ptr(cfg), _ptr(t), _ptr(psi)))
         return cfg, t, psi
@@ -399,6 +413,7 @@ class FFTDG:
         return self._reduce(self.L.fftdg_reduce_static, batch, partials, T, cfg_weight)
 
     def _reduce(self, fn, batch, partials, T, cfg_weight):
+        self._partials_ok(partials, batch)
         B = np.zeros((batch.n_lig, self.n_snap), np.float64)
         res = np.zeros(batch.n_lig, RESULT_DTYPE)
         w = cfg_weight
@@ -408,7 +423,10 @@ class FFTDG:
                         or cfg_weight.numel() != batch.n_cfg):
                     raise ValueError("cfg_weight: need a contiguous float64 device tensor of n_cfg entries")
             else:
-                w = self.torch.as_tensor(np.ascontiguousarray(cfg_weight, np.float64), device=self.device)
+                w = np.ascontiguousarray(cfg_weight, np.float64).reshape(-1)
+                if w.size != batch.n_cfg:
+                    raise ValueError(f"cfg_weight: {w.size} entries for {batch.n_cfg} configurations")
+                w = self.torch.as_tensor(w, device=self.device)
         self._check(fn(self.h_ctx, ctypes.byref(batch.c), _ptr(partials), _ptr(w), float(T), _ptr(B), _ptr(res)))
         return B, res
 

@@ -125,3 +125,25 @@ def test_batch_offsets_and_select_length():
             fd.Batch(ligs, bad)
         with pytest.raises(ValueError):
             b.with_select(bad)
+
+
+def test_partials_buffer_check():
+    """Calls that hand partials to the library first check that the buffer
+    is a contiguous tensor on the context's device holding n_snap * n_cfg
+    records (checked here with a stand-in context on the CPU device)."""
+    import types
+    import numpy as np
+    import torch
+    import paper_1708_07045_amd as fd
+    from workload import synth
+    rng = np.random.default_rng(4)
+    b = fd.Batch([synth.make_ligand(rng, rng, 3, 2, 5)])             # 10 configurations
+    ctx = types.SimpleNamespace(torch=torch, n_snap=3, device=torch.device("cpu"))
+    need = 3 * 10 * fd.PARTIAL_DTYPE.itemsize
+    ok = torch.empty(need, dtype=torch.uint8)
+    assert fd.FFTDG._partials_ok(ctx, ok, b) is ok
+    assert fd.FFTDG._partials_ok(ctx, torch.empty(need // 8, dtype=torch.float64), b) is not None
+    for bad in (torch.empty(need - 1, dtype=torch.uint8), np.zeros(need, np.uint8),
+                torch.empty(2 * need, dtype=torch.uint8)[::2]):
+        with pytest.raises(ValueError):
+            fd.FFTDG._partials_ok(ctx, bad, b)
