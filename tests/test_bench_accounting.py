@@ -100,3 +100,12 @@ def test_exact_shares_outside_unit_interval_are_rejected(shares):
                        capture_output=True, text=True, timeout=60)
     assert r.returncode == 2
     assert "--is-exact-shares" in r.stderr and not r.stdout
+
+
+def test_traffic_digest_covers_every_scan_kernel_source(bench):
+    """The recorded HBM traffic is trusted only while the scan kernels'
+    sources are unchanged, so the digest must cover every HIP source and
+    header of the library except the network's."""
+    csrc = os.path.join(ROOT, "paper_1708_07045_amd", "csrc")
+    kernel_files = {f for f in os.listdir(csrc) if f.endswith((".hip", ".hpp"))} - {"mlp.hip"}
+    assert kernel_files == set(bench.KERNEL_SOURCES)
